@@ -1,0 +1,102 @@
+"""Handley's population DAG, computed plainly (test infrastructure only).
+
+Handley represents the population as a DAG in which structurally identical
+subtrees are stored once (related-work section of the paper).  Here two nodes
+are identical when their opcode, payload and (already canonical) children are
+equal; the payload is the axis for a variable and the FP32 bit pattern for a
+constant, and is empty for every function node.  Identifiers are handed out
+in first-occurrence order of a postfix walk over the trees in population
+order, so every child has a smaller id than its parents.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Arities by opcode, in Table 1 order (kept here independently of any other module).
+_ARITY = [0, 0, 2, 2, 2, 2, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 1, 1, 1, 3, 2, 1, 3, 1, 1, 1, 2, 3]
+
+
+def tree_stack_depth(ops) -> int:
+    """Largest number of values on the stack in a left-to-right postfix walk."""
+    d = best = 0
+    for op in ops:
+        d += 1 - _ARITY[op]
+        best = max(best, d)
+    return best
+
+
+def build_dag(tokens, offsets):
+    """Canonicalise a population.
+
+    Returns a dict with
+      node_op, node_var (uint8), node_value (float32), children (int32 [U][3], -1 = none),
+      roots (int32 [R]), multiplicity (int32 [U], tokens mapped to each node),
+      indegree (int32 [U], DAG edges (parent, slot) into each node),
+      and the counts tree_nodes, tree_internal, dag_nodes, dag_internal,
+      shared_internal, max_stack, max_height.
+    """
+    ops = tokens["op"].astype(np.int64)
+    var = tokens["var"].astype(np.int64)
+    bits = tokens["value"].view(np.uint32).astype(np.int64)
+    table = {}
+    node_key = []
+    mult = []
+    roots = []
+    heights = []
+    max_stack = 0
+    for r in range(len(offsets) - 1):
+        stack = []
+        hstack = []
+        ops_r = []
+        for t in range(int(offsets[r]), int(offsets[r + 1])):
+            op = int(ops[t])
+            ops_r.append(op)
+            a = _ARITY[op]
+            if a:
+                kids = tuple(stack[len(stack) - a:])
+                del stack[len(stack) - a:]
+                h = 1 + max(hstack[len(hstack) - a:])
+                del hstack[len(hstack) - a:]
+                key = (op, 0, kids)
+            else:
+                payload = int(var[t]) if op == 0 else int(bits[t])
+                key = (op, payload, ())
+                h = 0
+            nid = table.get(key)
+            if nid is None:
+                nid = len(node_key)
+                table[key] = nid
+                node_key.append(key)
+                mult.append(0)
+            mult[nid] += 1
+            stack.append(nid)
+            hstack.append(h)
+        if len(stack) != 1:
+            raise ValueError(f"tree {r} is not a single postfix tree")
+        roots.append(stack[0])
+        heights.append(hstack[0])
+        max_stack = max(max_stack, tree_stack_depth(ops_r))
+    U = len(node_key)
+    node_op = np.zeros(U, np.uint8)
+    node_var = np.zeros(U, np.uint8)
+    node_value = np.zeros(U, np.float32)
+    children = np.full((U, 3), -1, np.int32)
+    indeg = np.zeros(U, np.int32)
+    for i, (op, payload, kids) in enumerate(node_key):
+        node_op[i] = op
+        if op == 0:
+            node_var[i] = payload
+        elif op == 1:
+            node_value[i] = np.array([payload], np.uint32).view(np.float32)[0]
+        for j, k in enumerate(kids):
+            children[i, j] = k
+            indeg[k] += 1
+    mult = np.array(mult, np.int32)
+    internal = np.array([_ARITY[k[0]] > 0 for k in node_key], bool)
+    tree_internal = int(sum(1 for o in ops if _ARITY[o] > 0))
+    return dict(node_op=node_op, node_var=node_var, node_value=node_value, children=children,
+                roots=np.array(roots, np.int32), multiplicity=mult, indegree=indeg,
+                tree_nodes=int(len(ops)), tree_internal=tree_internal, dag_nodes=U,
+                dag_internal=int(internal.sum()),
+                shared_internal=int((internal & (mult >= 2)).sum()),
+                max_stack=int(max_stack), max_height=int(max(heights) if heights else 0))

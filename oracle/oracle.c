@@ -1,0 +1,512 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for whole-population GP fitness evaluation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; it shares no code, header or table with the HIP library.
+ *
+ * What it computes (TensorGP, Sec. 3.1 "Genotype to Phenotype", Sec. 3.2
+ * "Primitive Set" with Table 1, Sec. 4.1 for the RMSE objective):
+ *   - every tree of the population is evaluated over every fitness case of an
+ *     N-dimensional coordinate grid whose variables span [-1, 1] (Sec. 3.1);
+ *   - each operator is applied with the protection rules of Table 1;
+ *     trigonometric arguments are first multiplied by pi (Sec. 3.2);
+ *   - the per-individual error against a target tensor is the root mean
+ *     squared error (Sec. 4.1, Table 2) or the mean squared error.
+ *
+ * It walks each tree recursively, one fitness case at a time, in double
+ * precision (mode O64).  For the parity contract it can also evaluate three
+ * FP32-shaped variants of the same walk (each operator result computed in
+ * FP64 from the operands and then rounded to FP32 (O32r), or rounded and then
+ * pushed one FP32 ulp up (O32u) or down (O32d) whenever the rounding was
+ * inexact) and record, at every operator with a discontinuity, which side of
+ * it each variant took.  A case is "stable" when all four variants agree on
+ * every such side, the O64 result is finite, and each FP32 variant is finite
+ * and within 1e-6 * max(|O64|, 1) of it.
+ *
+ * Readings of points the paper leaves open (each one a deliberate choice):
+ *   sin/cos are sin(pi x) and cos(pi x) (Table 1 prints them swapped);
+ *   div(x, 0) = +0 for either sign of zero; log(x<0) = -1, log(0) = -inf;
+ *   pow(0, 0) = 0, otherwise C99 pow; sqrt has arity 1 and sqrt(x<0) = 0;
+ *   min/max are IEEE minNum/maxNum (a NaN operand yields the other one);
+ *   sign(NaN) = 0; clip(x, y, z) = max(min(x, z), y);
+ *   mod is floored (result takes the divisor's sign), mod(x, 0) = 0;
+ *   frac(x) = x - floor(x); if(x, y, z) = x != 0 ? y : z (NaN counts true);
+ *   tan(x) = sin(pi x) / cos(pi x) with IEEE division;
+ *   len(x, y) = the exact sqrt(x^2 + y^2) (hypot);
+ *   coordinate k along an axis of n points is the FP32 rounding of
+ *   lo + (hi - lo) * k / (n - 1) computed in FP64 (lo when n == 1),
+ *   axes row-major with the last axis fastest; axis 0 is x, 1 is y, 2 is z.
+ * Any non-finite squared error makes an individual's fitness +inf.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    uint8_t op, var;
+    uint16_t pad;
+    float value;
+} orc_token;
+
+/* Opcodes in the order of the paper's Table 1 (terminals first). */
+enum {
+    OV_VAR, OV_CONST,
+    OV_ADD, OV_SUB, OV_MULT, OV_DIV,
+    OV_SIN, OV_COS, OV_TAN,
+    OV_EXP, OV_LOG, OV_POW,
+    OV_MIN, OV_MAX, OV_MDIST, OV_NEG,
+    OV_SQRT, OV_SIGN, OV_ABS, OV_CLIP,
+    OV_MOD, OV_FRAC, OV_IF,
+    OV_STEP, OV_SSTEP, OV_SSTEPP, OV_LEN, OV_LERP,
+    OV_COUNT
+};
+
+static const int orc_arity[OV_COUNT] = {
+    0, 0,
+    2, 2, 2, 2,
+    1, 1, 1,
+    1, 1, 2,
+    2, 2, 2, 1,
+    1, 1, 1, 3,
+    2, 1, 3,
+    1, 1, 1, 2, 3,
+};
+
+#define ORC_MAX_DIM 3
+
+typedef struct {
+    uint8_t op, var;
+    float value;
+    int32_t kid[3];
+} onode;
+
+typedef struct {
+    onode *n;
+    int32_t count; /* root is n[count-1] */
+} otree;
+
+/* ---------------------------------------------------------------- parsing */
+
+/* Returns 0 on success, -1 on a malformed tree (bad opcode, var, arity). */
+static int build_tree(const orc_token *t, int64_t len, int ndim, otree *out)
+{
+    out->n = NULL;
+    out->count = 0;
+    if (len <= 0)
+        return -1;
+    onode *n = (onode *)malloc(sizeof(onode) * (size_t)len);
+    int32_t *stk = (int32_t *)malloc(sizeof(int32_t) * (size_t)len);
+    if (!n || !stk) {
+        free(n);
+        free(stk);
+        return -1;
+    }
+    int64_t sp = 0;
+    for (int64_t i = 0; i < len; i++) {
+        int op = t[i].op;
+        if (op >= OV_COUNT)
+            goto bad;
+        if (op == OV_VAR && t[i].var >= ndim)
+            goto bad;
+        int a = orc_arity[op];
+        if (sp < a)
+            goto bad;
+        n[i].op = (uint8_t)op;
+        n[i].var = t[i].var;
+        n[i].value = t[i].value;
+        n[i].kid[0] = n[i].kid[1] = n[i].kid[2] = -1;
+        for (int j = a - 1; j >= 0; j--)
+            n[i].kid[j] = stk[--sp];
+        stk[sp++] = (int32_t)i;
+    }
+    if (sp != 1)
+        goto bad;
+    free(stk);
+    out->n = n;
+    out->count = (int32_t)len;
+    return 0;
+bad:
+    free(n);
+    free(stk);
+    return -1;
+}
+
+/* ------------------------------------------------------ operator semantics */
+
+/* sin(pi x) and cos(pi x) without rounding pi: x is reduced exactly to
+ * t = x - n/2 with |t| <= 1/4 and n = rint(2x), then the quadrant n mod 4
+ * picks +-sin(pi t) or +-cos(pi t).  Exact at every multiple of 1/2. */
+static void sincospi64(double x, double *s, double *c)
+{
+    if (!isfinite(x)) {
+        *s = *c = NAN;
+        return;
+    }
+    if (fabs(x) >= 9007199254740992.0) { /* 2^53: every double is an even integer */
+        *s = 0.0;
+        *c = 1.0;
+        return;
+    }
+    double n = rint(2.0 * x);
+    double t = x - 0.5 * n; /* exact */
+    double st = sin(M_PI * t), ct = cos(M_PI * t);
+    long q = (long)fmod(n, 4.0);
+    if (q < 0)
+        q += 4;
+    switch (q) {
+    case 0: *s = st;  *c = ct;  break;
+    case 1: *s = ct;  *c = -st; break;
+    case 2: *s = -st; *c = -ct; break;
+    default: *s = -ct; *c = st; break;
+    }
+    /* zeros of sin(pi x) and cos(pi x) are returned as +0 */
+    if (*s == 0.0) *s = 0.0;
+    if (*c == 0.0) *c = 0.0;
+}
+
+static double floor_mod(double x, double y)
+{
+    if (y == 0.0)
+        return 0.0;
+    double r = fmod(x, y);
+    if (r != 0.0 && ((r < 0.0) != (y < 0.0)))
+        r += y;
+    return r;
+}
+
+static int is_integral(double v)
+{
+    return isfinite(v) && floor(v) == v;
+}
+
+/* Applies operator op to a, b, c (unused operands ignored) in FP64.
+ * *br receives the side of the operator's discontinuity the operands fall on
+ * (0 for operators without one); NaN-free integers or floors, compared by
+ * value across evaluation variants. */
+static double apply(int op, double a, double b, double c, double *br)
+{
+    double s, co;
+    *br = 0.0;
+    switch (op) {
+    case OV_ADD: return a + b;
+    case OV_SUB: return a - b;
+    case OV_MULT: return a * b;
+    case OV_DIV:
+        *br = (b == 0.0);
+        return b == 0.0 ? 0.0 : a / b;
+    case OV_SIN: sincospi64(a, &s, &co); return s;
+    case OV_COS: sincospi64(a, &s, &co); return co;
+    case OV_TAN:
+        *br = isfinite(a) ? floor(a + 0.5) : -1.0;
+        sincospi64(a, &s, &co);
+        return s / co;
+    case OV_EXP: return exp(a);
+    case OV_LOG:
+        *br = isnan(a) ? 3 : (a < 0.0 ? 0 : (a == 0.0 ? 1 : 2));
+        return a < 0.0 ? -1.0 : log(a);
+    case OV_POW:
+        if (isnan(a) || isnan(b)) *br = 5;
+        else if (a == 0.0 && b == 0.0) *br = 0;
+        else if (a == 0.0) *br = 1;
+        else if (a < 0.0) *br = is_integral(b) ? 2 : 3;
+        else *br = 4;
+        return (a == 0.0 && b == 0.0) ? 0.0 : pow(a, b);
+    case OV_MIN: return fmin(a, b);
+    case OV_MAX: return fmax(a, b);
+    case OV_MDIST: return (a + b) / 2.0;
+    case OV_NEG: return -a;
+    case OV_SQRT:
+        *br = (a < 0.0);
+        return a < 0.0 ? 0.0 : sqrt(a);
+    case OV_SIGN:
+        *br = isnan(a) ? 3 : (a < 0.0 ? 0 : (a == 0.0 ? 1 : 2));
+        return (double)((a > 0.0) - (a < 0.0));
+    case OV_ABS: return fabs(a);
+    case OV_CLIP: return fmax(fmin(a, c), b);
+    case OV_MOD:
+        if (b == 0.0 || isnan(a) || isnan(b)) *br = -1.0;
+        else *br = floor(a / b);
+        return floor_mod(a, b);
+    case OV_FRAC:
+        *br = isfinite(a) ? floor(a) : -1.0;
+        return a - floor(a);
+    case OV_IF:
+        *br = (a != 0.0);
+        return a != 0.0 ? b : c;
+    case OV_STEP:
+        *br = (a < 0.0);
+        return a < 0.0 ? -1.0 : 1.0;
+    case OV_SSTEP: return a * a * (3.0 - 2.0 * a);
+    case OV_SSTEPP: return a * a * a * (a * (6.0 * a - 15.0) + 10.0);
+    case OV_LEN: return hypot(a, b);
+    case OV_LERP:
+        *br = isfinite(c) ? floor(c) : -1.0;
+        return a + (b - a) * (c - floor(c));
+    }
+    return NAN;
+}
+
+/* ------------------------------------------------------------ the domain */
+
+typedef struct {
+    int ndim;
+    int64_t shape[ORC_MAX_DIM];
+    int64_t stride[ORC_MAX_DIM];
+    float *coord[ORC_MAX_DIM];
+} odomain;
+
+static int make_domain(int ndim, const int64_t *shape, const double *lo, const double *hi, odomain *d)
+{
+    memset(d, 0, sizeof(*d));
+    if (ndim < 1 || ndim > ORC_MAX_DIM)
+        return -1;
+    d->ndim = ndim;
+    int64_t st = 1;
+    for (int k = ndim - 1; k >= 0; k--) {
+        if (shape[k] < 1)
+            return -1;
+        d->shape[k] = shape[k];
+        d->stride[k] = st;
+        st *= shape[k];
+    }
+    for (int k = 0; k < ndim; k++) {
+        d->coord[k] = (float *)malloc(sizeof(float) * (size_t)shape[k]);
+        for (int64_t i = 0; i < shape[k]; i++) {
+            double v = shape[k] == 1 ? lo[k] : lo[k] + (hi[k] - lo[k]) * (double)i / (double)(shape[k] - 1);
+            d->coord[k][i] = (float)v;
+        }
+    }
+    return 0;
+}
+
+static void free_domain(odomain *d)
+{
+    for (int k = 0; k < ORC_MAX_DIM; k++)
+        free(d->coord[k]);
+}
+
+static void case_coords(const odomain *d, int64_t c, double *xyz)
+{
+    for (int k = 0; k < d->ndim; k++) {
+        int64_t i = (c / d->stride[k]) % d->shape[k];
+        xyz[k] = (double)d->coord[k][i];
+    }
+}
+
+/* ------------------------------------------------------- the tree walkers */
+
+static double ev64(const onode *n, int32_t i, const double *xyz)
+{
+    const onode *p = &n[i];
+    if (p->op == OV_VAR)
+        return xyz[p->var];
+    if (p->op == OV_CONST)
+        return (double)p->value;
+    double a = 0.0, b = 0.0, c = 0.0, br;
+    int ar = orc_arity[p->op];
+    a = ev64(n, p->kid[0], xyz);
+    if (ar > 1)
+        b = ev64(n, p->kid[1], xyz);
+    if (ar > 2)
+        c = ev64(n, p->kid[2], xyz);
+    return apply(p->op, a, b, c, &br);
+}
+
+/* Four variants at once: v[0] = O64, v[1] = O32r, v[2] = O32u, v[3] = O32d. */
+static void round_variant(double r, double *out3)
+{
+    float f = (float)r;
+    out3[0] = (double)f;
+    if (isnan(r) || (double)f == r || isinf(f)) {
+        out3[1] = out3[2] = (double)f;
+        return;
+    }
+    out3[1] = (double)nextafterf(f, INFINITY);
+    out3[2] = (double)nextafterf(f, -INFINITY);
+}
+
+static int same_branch(double a, double b)
+{
+    return a == b || (isnan(a) && isnan(b));
+}
+
+static void ev4(const onode *n, int32_t i, const double *xyz, double *v, int *trace_ok)
+{
+    const onode *p = &n[i];
+    if (p->op == OV_VAR) {
+        v[0] = v[1] = v[2] = v[3] = xyz[p->var];
+        return;
+    }
+    if (p->op == OV_CONST) {
+        v[0] = v[1] = v[2] = v[3] = (double)p->value;
+        return;
+    }
+    double k[3][4] = {{0}};
+    int ar = orc_arity[p->op];
+    for (int j = 0; j < ar; j++)
+        ev4(n, p->kid[j], xyz, k[j], trace_ok);
+    double br0, brm, r;
+    v[0] = apply(p->op, k[0][0], k[1][0], k[2][0], &br0);
+    for (int m = 1; m < 4; m++) {
+        double rr[3];
+        r = apply(p->op, k[0][m], k[1][m], k[2][m], &brm);
+        if (!same_branch(br0, brm))
+            *trace_ok = 0;
+        round_variant(r, rr);
+        v[m] = rr[m - 1];
+    }
+}
+
+static int nonfinite_class(double v)
+{
+    if (isnan(v)) return 1;
+    if (isinf(v)) return v > 0 ? 2 : 3;
+    return 0;
+}
+
+/*
+ * Evaluate trees over fitness cases.
+ *   tokens/offsets: n_roots postfix trees (tree r = tokens[offsets[r]..offsets[r+1]) ).
+ *   ndim/shape/lo/hi: the coordinate grid.
+ *   cases: n_cases case indices (row-major, last axis fastest), or NULL for
+ *          all cases in order (then n_cases must equal the grid size).
+ *   v64:   out [n_roots][n_cases] O64 values (required).
+ *   v32r:  out [n_roots][n_cases] O32r values, or NULL.
+ *   stab:  out [n_roots][n_cases] flags, or NULL: bit0 = stable finite case,
+ *          bit1 = every FP32 variant non-finite of one class with agreeing
+ *          branch sides (that class is then the required one).
+ *   When v32r or stab is given, the four-variant walk runs; otherwise only O64.
+ * Returns 0, or -(1 + r) when tree r is malformed, or -1000000000 on bad args.
+ */
+int orc_eval(const orc_token *tokens, const int64_t *offsets, int64_t n_roots,
+             int ndim, const int64_t *shape, const double *lo, const double *hi,
+             const int64_t *cases, int64_t n_cases,
+             double *v64, double *v32r, uint8_t *stab, int nthreads)
+{
+    odomain d;
+    if (make_domain(ndim, shape, lo, hi, &d) != 0)
+        return -1000000000;
+    int64_t total = 1;
+    for (int k = 0; k < ndim; k++)
+        total *= shape[k];
+    if (!cases && n_cases != total) {
+        free_domain(&d);
+        return -1000000000;
+    }
+    otree *trees = (otree *)calloc((size_t)(n_roots > 0 ? n_roots : 1), sizeof(otree));
+    int rc = 0;
+    for (int64_t r = 0; r < n_roots; r++) {
+        if (build_tree(tokens + offsets[r], offsets[r + 1] - offsets[r], ndim, &trees[r]) != 0) {
+            rc = (int)(-(1 + r));
+            break;
+        }
+    }
+    if (rc == 0) {
+        int four = (v32r != NULL) || (stab != NULL);
+        int64_t work = n_roots * n_cases;
+#ifdef _OPENMP
+        if (nthreads > 0)
+            omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+        for (int64_t w = 0; w < work; w += 256) {
+            int64_t end = w + 256 < work ? w + 256 : work;
+            for (int64_t q = w; q < end; q++) {
+                int64_t r = q / n_cases, ci = q % n_cases;
+                int64_t c = cases ? cases[ci] : ci;
+                double xyz[ORC_MAX_DIM] = {0, 0, 0};
+                case_coords(&d, c, xyz);
+                const otree *t = &trees[r];
+                if (!four) {
+                    v64[q] = ev64(t->n, t->count - 1, xyz);
+                    continue;
+                }
+                double v[4];
+                int ok = 1;
+                ev4(t->n, t->count - 1, xyz, v, &ok);
+                v64[q] = v[0];
+                if (v32r)
+                    v32r[q] = v[1];
+                if (stab) {
+                    uint8_t f = 0;
+                    int fin = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]);
+                    if (ok && fin) {
+                        double sc = fabs(v[0]) > 1.0 ? fabs(v[0]) : 1.0;
+                        int close = 1;
+                        for (int m = 1; m < 4; m++)
+                            if (fabs(v[m] - v[0]) > 1e-6 * sc)
+                                close = 0;
+                        if (close)
+                            f |= 1;
+                    }
+                    int cl = nonfinite_class(v[1]);
+                    if (ok && cl && nonfinite_class(v[2]) == cl && nonfinite_class(v[3]) == cl)
+                        f |= 2;
+                    stab[q] = f;
+                }
+            }
+        }
+    }
+    (void)nthreads;
+    for (int64_t r = 0; r < n_roots; r++)
+        free(trees[r].n);
+    free(trees);
+    free_domain(&d);
+    return rc;
+}
+
+/* Coordinate table of one axis, for tests of the grid convention. */
+int orc_coords(int64_t n, double lo, double hi, float *out)
+{
+    if (n < 1)
+        return -1;
+    for (int64_t i = 0; i < n; i++)
+        out[i] = (float)(n == 1 ? lo : lo + (hi - lo) * (double)i / (double)(n - 1));
+    return 0;
+}
+
+/*
+ * Fitness per individual from per-case values (Sec. 4.1: RMSE against the
+ * target).  values: [n_ind * n_ch][n_cases] FP64, tree-major (individual i,
+ * channel ch is row i * n_ch + ch).  target: [n_ch][n_cases] FP32.
+ * Sums (v - t)^2 in FP64 in index order over channels then cases; loss 0
+ * gives sqrt(sum / N), loss 1 gives sum / N, with N = n_ch * n_cases.
+ * Any non-finite term makes the fitness +inf.
+ */
+int orc_fitness(const double *values, const float *target, int64_t n_ind, int n_ch,
+                int64_t n_cases, int loss, double *out)
+{
+    if (n_ch < 1 || n_cases < 1 || (loss != 0 && loss != 1))
+        return -1;
+    double N = (double)n_ch * (double)n_cases;
+    for (int64_t i = 0; i < n_ind; i++) {
+        double s = 0.0;
+        int bad = 0;
+        for (int ch = 0; ch < n_ch; ch++) {
+            const double *v = values + (i * n_ch + ch) * n_cases;
+            const float *t = target + (int64_t)ch * n_cases;
+            for (int64_t c = 0; c < n_cases; c++) {
+                double e = v[c] - (double)t[c];
+                double q = e * e;
+                if (!isfinite(q))
+                    bad = 1;
+                s += q;
+            }
+        }
+        out[i] = bad ? INFINITY : (loss == 0 ? sqrt(s / N) : s / N);
+    }
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
