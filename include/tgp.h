@@ -1,0 +1,231 @@
+/*
+ * tgp.h -- C ABI of libtgp: whole-population genetic-programming fitness
+ * evaluation on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (TensorGP, Baeta et al.): every individual is an expression tree
+ * over the primitive set of Table 1; the tree is evaluated over a fixed domain
+ * of fitness cases held as an N-dimensional coordinate grid (Sec. 3.1), all
+ * cases at once ("vectorisation", Sec. 1 and Sec. 2), with results of
+ * intermediate subtrees cached so that code shared between individuals is not
+ * executed again (Sec. 1, Sec. 3.1; the population DAG of Handley described
+ * in Sec. 2), and each individual's error against a target tensor is reduced
+ * to its root mean squared error (Sec. 4.1, Table 2).
+ *
+ * Conventions for every call:
+ *   - every function returns tgp_status (TGP_OK = 0 on success) except the
+ *     destroy functions and tgp_last_error; no C++ exception crosses the ABI;
+ *   - arguments are validated on the host before any kernel is launched; the
+ *     message of the last failure on a context is tgp_last_error(ctx);
+ *   - "device pointer" means memory on the context's GPU (for instance a torch
+ *     tensor's data_ptr()); it belongs to the caller and must be large enough;
+ *   - host buffers passed in are only read during the call; handles belong to
+ *     the library and are released by the matching *_destroy;
+ *   - device work is ordered on the context's HIP stream and is asynchronous
+ *     unless a function says it blocks;
+ *   - a context is used by one host thread at a time.
+ */
+#ifndef TGP_H
+#define TGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TGP_OK = 0,
+    TGP_EINVAL = -1,  /* bad argument (null pointer, bad size, bad loss, ...) */
+    TGP_EPARSE = -2,  /* a token range is not exactly one postfix tree */
+    TGP_EDEPTH = -3,  /* a program cannot be fitted into the evaluator's stack */
+    TGP_EOP = -4,     /* unknown opcode */
+    TGP_ENOMEM = -5,  /* device or host allocation failed, or over budget */
+    TGP_EHIP = -6,    /* a HIP runtime call failed (text in tgp_last_error) */
+    TGP_ESHAPE = -7,  /* domain / channel / variable-axis mismatch */
+    TGP_EBUSY = -8    /* timed out, or the request cannot be admitted yet */
+} tgp_status;
+
+/*
+ * Opcodes: the pointwise operators of Table 1 in the paper's order, after the
+ * two terminal kinds.  Arity in brackets.  Trigonometric arguments are in
+ * half-turns (multiplied by pi, Sec. 3.2).  Protected forms follow Table 1;
+ * where the table is silent the library uses the reading given here.
+ */
+enum tgp_opcode {
+    TGP_VAR = 0,    /* [0] coordinate along axis `var` (0 = x, 1 = y, 2 = z) */
+    TGP_CONST = 1,  /* [0] the FP32 constant `value` */
+    TGP_ADD = 2,    /* [2] x + y */
+    TGP_SUB = 3,    /* [2] x - y */
+    TGP_MULT = 4,   /* [2] x * y */
+    TGP_DIV = 5,    /* [2] x / y, 0 when y == 0 (either sign) */
+    TGP_SIN = 6,    /* [1] sin(pi x) (Table 1 prints sin and cos swapped) */
+    TGP_COS = 7,    /* [1] cos(pi x) */
+    TGP_TAN = 8,    /* [1] sin(pi x) / cos(pi x), IEEE division at the poles */
+    TGP_EXP = 9,    /* [1] e^x */
+    TGP_LOG = 10,   /* [1] ln x, -1 when x < 0 (ln 0 = -inf) */
+    TGP_POW = 11,   /* [2] x^y, 0 when x == y == 0, otherwise C99 pow */
+    TGP_MIN = 12,   /* [2] IEEE minNum */
+    TGP_MAX = 13,   /* [2] IEEE maxNum */
+    TGP_MDIST = 14, /* [2] (x + y) / 2 */
+    TGP_NEG = 15,   /* [1] -x */
+    TGP_SQRT = 16,  /* [1] sqrt(x), 0 when x < 0 (arity 1; the table prints 2) */
+    TGP_SIGN = 17,  /* [1] -1 / 0 / 1; NaN gives 0 */
+    TGP_ABS = 18,   /* [1] |x| */
+    TGP_CLIP = 19,  /* [3] max(min(x, z), y) */
+    TGP_MOD = 20,   /* [2] floored remainder (sign of y), 0 when y == 0 */
+    TGP_FRAC = 21,  /* [1] x - floor(x) */
+    TGP_IF = 22,    /* [3] x != 0 ? y : z (NaN counts as true) */
+    TGP_STEP = 23,  /* [1] -1 when x < 0, else 1 */
+    TGP_SSTEP = 24, /* [1] x^2 (3 - 2x) */
+    TGP_SSTEPP = 25,/* [1] x^3 (x (6x - 15) + 10) */
+    TGP_LEN = 26,   /* [2] sqrt(x^2 + y^2) without intermediate overflow */
+    TGP_LERP = 27,  /* [3] x + (y - x) frac(z) */
+    TGP_NUM_OPS = 28
+};
+
+/* One tree node.  Trees are postfix (children before parent, left to right).
+ * `var` is read only for TGP_VAR and `value` only for TGP_CONST; the other
+ * fields of a node are ignored.  Two constants are the same node exactly when
+ * their FP32 bit patterns are equal. */
+typedef struct {
+    uint8_t op;
+    uint8_t var;
+    uint16_t pad;
+    float value;
+} tgp_token;
+
+enum { TGP_MEM_HOST = 0, TGP_MEM_DEVICE = 1 };
+
+/* A population of n_individuals, each made of n_channels trees (one tree per
+ * output channel, e.g. R, G, B of an image, Sec. 3.1).  Tree r = i * n_channels
+ * + ch is tokens[offsets[r] .. offsets[r + 1]).  offsets has n_individuals *
+ * n_channels + 1 entries, starts at 0 and never decreases.  `memory` says
+ * whether offsets and tokens are host (TGP_MEM_HOST) or device pointers. */
+typedef struct {
+    int32_t n_individuals;
+    int32_t n_channels;
+    const int64_t *offsets;
+    const tgp_token *tokens;
+    int32_t memory;
+} tgp_population;
+
+typedef enum { TGP_RMSE = 0, TGP_MSE = 1 } tgp_loss;
+
+/* Counts that describe a population DAG.  "internal" = function nodes. */
+typedef struct {
+    int64_t tree_nodes;      /* tokens in the population */
+    int64_t tree_internal;   /* function tokens */
+    int64_t dag_nodes;       /* distinct subtrees (nodes of the DAG) */
+    int64_t dag_internal;    /* distinct function subtrees */
+    int64_t shared_internal; /* distinct function subtrees occurring >= 2 times */
+    int64_t max_stack;       /* deepest left-to-right postfix stack of any tree */
+    int64_t max_height;      /* tallest tree (a lone terminal has height 0) */
+    int64_t n_roots;         /* n_individuals * n_channels */
+    int64_t max_var;         /* largest axis index used, -1 when none */
+} tgp_dag_stats;
+
+typedef struct tgp_ctx_s *tgp_ctx;
+typedef struct tgp_domain_s *tgp_domain;
+typedef struct tgp_dag_s *tgp_dag;
+
+/* ------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` that orders its work on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  The device
+ * must be a gfx950 GPU; the call fails with TGP_EHIP otherwise. */
+tgp_status tgp_ctx_create(int device, void *hip_stream, tgp_ctx *out);
+void tgp_ctx_destroy(tgp_ctx ctx);
+/* Switch the stream later work is ordered on. */
+tgp_status tgp_ctx_set_stream(tgp_ctx ctx, void *hip_stream);
+/* Message of the last failed call on ctx ("" when none); valid until the
+ * next call on ctx.  Accepts NULL (returns the last context-less failure). */
+const char *tgp_last_error(tgp_ctx ctx);
+/* Largest number of bytes the subtree-result cache of one evaluation may
+ * occupy (default: 1/4 of the device memory).  Cached subtrees that would
+ * exceed it are recomputed instead, except those needed to bound the
+ * evaluator's stack, whose excess makes the evaluation fail with TGP_ENOMEM. */
+tgp_status tgp_ctx_set_cache_budget(tgp_ctx ctx, size_t bytes);
+
+/* Tuning of the evaluator (the autotuner sets these): cases_per_lane is K,
+ * the number of fitness cases each lane of a wave owns per tile (2 or 4; 0 =
+ * chosen from the domain size); tiles_per_item is how many consecutive tiles
+ * of 64*K cases one wave evaluates for one program (0 = chosen so that a
+ * launch has about 65536 work items).  Per-case values do not depend on
+ * either; a fitness changes only through the order of its compensated sums. */
+tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles_per_item);
+
+/* Test hook: keep only the low `bits` bits of the DAG builder's 64-bit key
+ * hash (0 = all bits), forcing collisions so that the full-key comparison is
+ * exercised.  Process-wide; the DAG produced must not change. */
+tgp_status tgp_debug_set_hash_bits(int32_t bits);
+
+/* ------------------------------------------------------------- domain */
+
+/* The grid of fitness cases (Sec. 3.1, Sec. 4.1): ndim in 1..3 axes of
+ * shape[k] >= 1 points; point i of axis k has coordinate
+ * fl32(lo[k] + (hi[k] - lo[k]) * i / (shape[k] - 1)) computed in FP64 (lo[k]
+ * when shape[k] == 1).  lo/hi NULL mean -1 and 1 for every axis (the paper's
+ * standard range).  Cases are numbered row-major, last axis fastest; at most
+ * 2^31 - 1 cases.  The coordinate tables are copied to the device. */
+tgp_status tgp_domain_create(tgp_ctx ctx, int32_t ndim, const int64_t *shape, const double *lo,
+                             const double *hi, tgp_domain *out);
+void tgp_domain_destroy(tgp_domain dom);
+int64_t tgp_domain_cases(tgp_domain dom);
+
+/* ---------------------------------------------------------------- DAG */
+
+/* Hash-cons a population into one DAG (Handley's population DAG, Sec. 2):
+ * structurally identical subtrees (same opcode, same payload, identical
+ * children) become one node.  Runs on the GPU (structure scan, level-by-level
+ * hash-consing with a device hash table, compaction) and blocks until the DAG
+ * is built.  Node ids follow the first occurrence of each subtree in a
+ * postfix walk of the trees in population order, so children precede parents.
+ * Errors: TGP_EPARSE (tree r malformed, r in the message), TGP_EOP,
+ * TGP_EINVAL (bad offsets or sizes). */
+tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out);
+tgp_status tgp_dag_stats_get(tgp_dag dag, tgp_dag_stats *out);
+/* Copy the DAG to host arrays of dag_nodes (nodes, multiplicity, indegree),
+ * dag_nodes * 3 (children, -1 where a child slot is unused) and n_roots
+ * (roots) entries.  multiplicity = number of tokens of the population that
+ * map to the node; indegree = number of (parent, child slot) edges into it.
+ * Any output pointer may be NULL.  Blocks. */
+tgp_status tgp_dag_export(tgp_dag dag, tgp_token *nodes, int32_t *children, int32_t *roots,
+                          int32_t *multiplicity, int32_t *indegree);
+void tgp_dag_destroy(tgp_dag dag);
+
+/* --------------------------------------------------------- evaluation */
+
+/* Phenotypes (Sec. 3.1): the value of every tree at every case, FP32, written
+ * to out_dev[r][case] with r = individual * n_channels + channel (device
+ * pointer, n_roots * cases floats).  TGP_ESHAPE when a tree uses an axis the
+ * domain does not have. */
+tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, float *out_dev);
+
+/* Fitness (Sec. 4.1): per individual, the RMSE (TGP_RMSE) or MSE (TGP_MSE)
+ * over all channels and cases against target_dev[channel][case] (device,
+ * n_channels * cases floats), written as FP64 to out_dev[individual]
+ * (device pointer).  Squares are accumulated with compensated FP32 sums and
+ * combined in FP64; any non-finite term makes the fitness +inf. */
+tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, const float *target_dev,
+                       int32_t loss, double *out_dev);
+
+/* Work counts of the last tgp_evaluate / tgp_fitness on ctx (for reports):
+ * credited = dag_nodes x cases x ... as defined in the fields. */
+typedef struct {
+    int64_t credited_node_evals; /* DAG nodes reachable from the roots x cases */
+    int64_t executed_node_evals; /* interpreter instructions run x cases */
+    int64_t cached_nodes;        /* subtrees materialised in the cache */
+    int64_t cache_levels;        /* dependent cache-fill launches */
+    int64_t programs;            /* root programs (distinct (root, channel) pairs) */
+    int64_t instructions;        /* total program length */
+    double algorithmic_valu;     /* VALU lane-slots by the op cost model x cases */
+    int64_t cache_bytes_read;    /* HBM bytes of cache loads (algorithmic) */
+    int64_t cache_bytes_written; /* HBM bytes of cache stores (algorithmic) */
+} tgp_work_stats;
+tgp_status tgp_last_work(tgp_ctx ctx, tgp_work_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGP_H */

@@ -1,0 +1,145 @@
+#!/usr/bin/env python3
+"""Writes interp_gen.inc: the stack-depth-specialised postfix interpreter.
+
+The interpreter keeps the operand stack of a postfix program in registers.
+One wave runs one program and each lane owns K fitness cases, so the stack
+depth S before every instruction is the same for all lanes and is known when
+the instruction is dispatched.  The generated code has one dispatch block per
+depth S = 0..D.  In block S the stack slots are plain named values s0..s{D-1}
+(each a vector of K lanes' cases), an operator of arity a reads
+s{S-a}..s{S-1} and writes s{S-a}, and then jumps straight to the dispatch
+block of depth S-a+1.  No register is ever indexed at run time, and because
+the depth only rises by pushes of one value the control flow stays reducible:
+the block of depth S dominates every block of greater depth.
+
+Operators with long bodies (transcendentals, floored modulo, the FP64 image
+operators) are compiled once as out-of-line functions that take and return
+the K-vectors by value in registers; the cheap operators are written into
+every block.
+
+Run:  python gen_interp.py          writes interp_gen.inc beside this file
+      python gen_interp.py --check  exits 1 when interp_gen.inc is stale
+"""
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# (name, public opcode, arity) of the function operators, in Table 1 order.
+FUNCS = [
+    ("add", 2, 2), ("sub", 3, 2), ("mult", 4, 2), ("div", 5, 2),
+    ("sin", 6, 1), ("cos", 7, 1), ("tan", 8, 1),
+    ("exp", 9, 1), ("log", 10, 1), ("pow", 11, 2),
+    ("min", 12, 2), ("max", 13, 2), ("mdist", 14, 2), ("neg", 15, 1),
+    ("sqrt", 16, 1), ("sign", 17, 1), ("abs", 18, 1), ("clip", 19, 3),
+    ("mod", 20, 2), ("frac", 21, 1), ("if", 22, 3),
+    ("step", 23, 1), ("sstep", 24, 1), ("sstepp", 25, 1), ("len", 26, 2), ("lerp", 27, 3),
+]
+FN_BASE = 8
+# Operators compiled once, out of line.
+CALLED = {"sin", "cos", "tan", "exp", "log", "pow", "mod", "sstep", "sstepp", "len", "lerp"}
+DEPTHS = [8]
+ARGS = "abc"
+
+
+def called_functions():
+    L = []
+    e = L.append
+    e("// Out-of-line operators on K-vectors (arguments and results in registers).")
+    for name, _, ar in FUNCS:
+        if name not in CALLED:
+            continue
+        params = ", ".join(f"FV<K> {ARGS[i]}" for i in range(ar))
+        call = ", ".join(f"{ARGS[i]}.v[k]" for i in range(ar))
+        e("template <int K>")
+        e(f"__device__ __attribute__((noinline)) FV<K> vcall_{name}({params}) {{")
+        e("    FV<K> r;")
+        e("#pragma unroll")
+        e(f"    for (int k = 0; k < K; ++k) r.v[k] = f_{name}({call});")
+        e("    return r;")
+        e("}")
+    e("")
+    return "\n".join(L)
+
+
+def body_for_depth(D):
+    L = []
+    e = L.append
+    e(f"// Stack of {D} register slots.  Returns when the program's I_END is reached")
+    e(f"// at depth 1 (res = the program's value); a malformed program gives NaN.")
+    e("template <int K>")
+    e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
+    e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int32_t n_cases,")
+    e("        const int32_t (&cidx)[K], FV<K> &res)")
+    e("{")
+    e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
+    e("    uint2 ins;")
+    for S in range(D + 1):
+        e(f"L{S}:")
+        e("    ins = *ip;")
+        e("    ++ip;")
+        e("    switch (ins.x & 0xffu) {")
+        if S < D:
+            for name, reg in (("I_X", "xv"), ("I_Y", "yv"), ("I_Z", "zv")):
+                e(f"    case {name}: s{S} = {reg}; goto L{S + 1};")
+            e("    case I_CONST: {")
+            e("        const float c = __uint_as_float(ins.y);")
+            e("#pragma unroll")
+            e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = c;")
+            e(f"        goto L{S + 1};")
+            e("    }")
+            e("    case I_CACHE: {")
+            e("        const float *row = cache + (size_t)(ins.x >> 8) * (size_t)n_cases;")
+            e("#pragma unroll")
+            e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];")
+            e(f"        goto L{S + 1};")
+            e("    }")
+        if S == 1:
+            e("    case I_END: res = s0; return;")
+        for name, op, ar in FUNCS:
+            if S < ar:
+                continue
+            c = FN_BASE + op
+            src = [f"s{S - ar + i}" for i in range(ar)]
+            dst = S - ar
+            if name in CALLED:
+                e(f"    case {c}: s{dst} = vcall_{name}<K>({', '.join(src)}); goto L{dst + 1};")
+            else:
+                e(f"    case {c}:")
+                e("#pragma unroll")
+                args = ", ".join(f"{x}.v[k]" for x in src)
+                e(f"        for (int k = 0; k < K; ++k) s{dst}.v[k] = f_{name}({args});")
+                e(f"        goto L{dst + 1};")
+        e("    default: goto BAD;")
+        e("    }")
+    e("BAD:")
+    e("#pragma unroll")
+    e("    for (int k = 0; k < K; ++k) res.v[k] = __builtin_nanf(\"\");")
+    e("}")
+    e("")
+    return "\n".join(L)
+
+
+def generate():
+    out = ["// interp_gen.inc -- GENERATED by gen_interp.py; do not edit.",
+           "// Stack-depth-specialised postfix interpreters, one per stack size.",
+           f"// Stack sizes: {', '.join(map(str, DEPTHS))}.",
+           "",
+           called_functions()]
+    for D in DEPTHS:
+        out.append(body_for_depth(D))
+    return "\n".join(out) + "\n"
+
+
+def main():
+    path = os.path.join(HERE, "interp_gen.inc")
+    text = generate()
+    if len(sys.argv) > 1 and sys.argv[1] == "--check":
+        cur = open(path).read() if os.path.exists(path) else ""
+        sys.exit(0 if cur == text else 1)
+    with open(path, "w") as f:
+        f.write(text)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,458 @@
+// k_dag.hip -- building Handley's population DAG on the GPU.
+//
+// The paper caches the results of structurally identical subtrees so that
+// code shared between individuals is not executed again (Sec. 1, Sec. 3.1),
+// generalising the trees to a DAG as in Handley's work (Sec. 2).  The DAG is
+// built here by hash-consing, in three steps:
+//   1. structure: one thread per tree scans its postfix tokens with a stack,
+//      validates arities and opcodes, and records each token's children and
+//      height (a terminal has height 0);
+//   2. hash-consing, level by level in increasing height: a token's key is
+//      (opcode, payload, canonical ids of its children), whose children all
+//      lie on lower, already finished levels.  Keys go into an open-addressing
+//      table (linear probing, capacity >= 2 x tokens); equal keys are
+//      detected by comparing the full key, never the hash alone, and the
+//      representative of a key is its smallest token index (atomicMin), so
+//      the result does not depend on thread timing;
+//   3. compaction: representatives are numbered by an exclusive scan in token
+//      order, which is the order of first occurrence in a postfix walk of the
+//      trees in population order, so children get smaller ids than parents.
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+#include <stdio.h>
+#include <vector>
+
+#include "tgp_internal.h"
+
+namespace tgp {
+
+__constant__ int8_t c_arity[TGP_NUM_OPS] = {
+    0, 0, 2, 2, 2, 2, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 1, 1, 1, 3, 2, 1, 3, 1, 1, 1, 2, 3};
+
+struct BuildStatus {
+    unsigned long long first_error;  // (tree << 4) | code, min over trees; ~0 = none
+    int32_t max_height;
+    int32_t max_var;
+    int32_t max_stack;
+    int32_t n_internal;
+};
+
+enum { ERR_NONE = 0, ERR_OP = 1, ERR_PARSE = 2, ERR_RANGE = 3 };
+
+__device__ __forceinline__ void report(BuildStatus *st, int64_t r, int code) {
+    atomicMin(&st->first_error, ((unsigned long long)r << 4) | (unsigned long long)code);
+}
+
+// 1. Structure scan, one thread per tree.  stk is T ints of scratch; tree r
+// uses stk[off[r] .. off[r+1]) as its stack.
+__global__ void k_structure(const uint2 *tok, const int64_t *off, int64_t R, int64_t T, int32_t *kid,
+                            int32_t *height, int32_t *stk, int32_t *root_tok, BuildStatus *st) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t o0 = off[r], o1 = off[r + 1];
+    if (o0 < 0 || o1 > T || o1 < o0) {
+        report(st, r, ERR_RANGE);
+        return;
+    }
+    if (o1 == o0) {
+        report(st, r, ERR_PARSE);
+        return;
+    }
+    int64_t sp = 0;
+    int32_t maxsp = 0, internal = 0, maxvar = -1;
+    for (int64_t t = o0; t < o1; ++t) {
+        const uint2 w = tok[t];
+        const uint32_t op = w.x & 0xffu;
+        if (op >= TGP_NUM_OPS) {
+            report(st, r, ERR_OP);
+            return;
+        }
+        const int a = c_arity[op];
+        if (sp < a) {
+            report(st, r, ERR_PARSE);
+            return;
+        }
+        int32_t h = 0;
+        int32_t k3[3] = {-1, -1, -1};
+        for (int j = a - 1; j >= 0; --j) {
+            const int32_t c = stk[o0 + (--sp)];
+            k3[j] = c;
+            const int32_t hc = height[c] + 1;
+            h = hc > h ? hc : h;
+        }
+        kid[3 * t + 0] = k3[0];
+        kid[3 * t + 1] = k3[1];
+        kid[3 * t + 2] = k3[2];
+        height[t] = h;
+        stk[o0 + sp] = (int32_t)t;
+        ++sp;
+        if (sp > maxsp) maxsp = (int32_t)sp;
+        if (a > 0) ++internal;
+        if (op == TGP_VAR) {
+            const int32_t v = (int32_t)((w.x >> 8) & 0xffu);
+            maxvar = v > maxvar ? v : maxvar;
+        }
+    }
+    if (sp != 1) {
+        report(st, r, ERR_PARSE);
+        return;
+    }
+    root_tok[r] = (int32_t)(o1 - 1);
+    atomicMax(&st->max_height, height[o1 - 1]);
+    atomicMax(&st->max_stack, maxsp);
+    atomicMax(&st->max_var, maxvar);
+    atomicAdd(&st->n_internal, internal);
+}
+
+__global__ void k_level_hist(const int32_t *height, int64_t T, int32_t *cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) atomicAdd(&cnt[height[t]], 1);
+}
+
+__global__ void k_level_scatter(const int32_t *height, int64_t T, int32_t *cursor, int32_t *list) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) {
+        const int32_t pos = atomicAdd(&cursor[height[t]], 1);
+        list[pos] = (int32_t)t;
+    }
+}
+
+// Key of token t: k0 = opcode | axis << 8 (the axis only for a variable);
+// k1 = constant bits or first child's canonical id; k2, k3 = further
+// children; unused fields are all-ones.
+struct Key {
+    uint32_t k0, k1, k2, k3;
+};
+
+__device__ __forceinline__ Key key_of(int32_t t, const uint2 *tok, const int32_t *kid,
+                                      const int32_t *canon) {
+    const uint2 w = tok[t];
+    const uint32_t op = w.x & 0xffu;
+    Key k{op, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+    if (op == TGP_VAR) {
+        k.k0 = op | (w.x & 0xff00u);
+    } else if (op == TGP_CONST) {
+        k.k1 = w.y;
+    } else {
+        const int a = c_arity[op];
+        k.k1 = (uint32_t)canon[kid[3 * t + 0]];
+        if (a > 1) k.k2 = (uint32_t)canon[kid[3 * t + 1]];
+        if (a > 2) k.k3 = (uint32_t)canon[kid[3 * t + 2]];
+    }
+    return k;
+}
+
+__device__ __forceinline__ bool key_eq(const Key &a, const Key &b) {
+    return a.k0 == b.k0 && a.k1 == b.k1 && a.k2 == b.k2 && a.k3 == b.k3;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t key_hash(const Key &k, uint32_t hash_mask_bits) {
+    uint64_t h = mix64(((uint64_t)k.k0 << 32) | k.k1);
+    h = mix64(h ^ (((uint64_t)k.k2 << 32) | k.k3));
+    if (hash_mask_bits) h &= ((1ull << hash_mask_bits) - 1);  // collision stress (tests)
+    return h;
+}
+
+// 2a. Insert the tokens of one level; the slot of a key ends up holding the
+// smallest token index with that key.
+__global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
+                              const int32_t *canon, int32_t *table, uint64_t mask,
+                              uint32_t hash_bits) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t t = list[i];
+    const Key k = key_of(t, tok, kid, canon);
+    uint64_t s = key_hash(k, hash_bits) & mask;
+    for (;;) {
+        int32_t e = table[s];
+        if (e < 0) {
+            e = atomicCAS(&table[s], -1, t);
+            if (e < 0) return;  // claimed an empty slot
+        }
+        if (key_eq(key_of(e, tok, kid, canon), k)) {
+            atomicMin(&table[s], t);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// 2b. Every token of the level looks its key up again and takes the
+// representative.
+__global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
+                               int32_t *canon, const int32_t *table, uint64_t mask,
+                               uint32_t hash_bits) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t t = list[i];
+    const Key k = key_of(t, tok, kid, canon);
+    uint64_t s = key_hash(k, hash_bits) & mask;
+    for (;;) {
+        const int32_t e = table[s];
+        if (e < 0) {  // cannot happen: t itself was inserted before the first empty slot
+            canon[t] = t;
+            return;
+        }
+        if (key_eq(key_of(e, tok, kid, canon), k)) {
+            canon[t] = e;
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+__global__ void k_flags(const int32_t *canon, int64_t T, int32_t *flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) flag[t] = canon[t] == (int32_t)t ? 1 : 0;
+}
+
+// Exclusive scan, 1024 elements per block (256 threads x 4).
+__global__ __launch_bounds__(256) void k_scan_block(const int32_t *in, int32_t *out, int64_t n,
+                                                    int32_t *block_sums) {
+    __shared__ int32_t sh[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * 1024 + tid * 4;
+    int32_t v[4];
+    int32_t sum = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = base + j < n ? in[base + j] : 0;
+        sum += v[j];
+    }
+    sh[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int32_t x = tid >= o ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += x;
+        __syncthreads();
+    }
+    int32_t run = sh[tid] - sum;  // exclusive prefix of this thread
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (tid == 255 && block_sums) block_sums[blockIdx.x] = sh[255];
+}
+
+__global__ void k_scan_add(int32_t *out, int64_t n, const int32_t *block_off) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += block_off[i / 1024];
+}
+
+static hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 1023) / 1024;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(256), 0, s, in, out, n, (int32_t *)nullptr);
+        return hipGetLastError();
+    }
+    int32_t *sums = nullptr, *offs = nullptr;
+    hipError_t e = hipMallocAsync((void **)&sums, nb * sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    e = hipMallocAsync((void **)&offs, nb * sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(256), 0, s, in, out, n, sums);
+    e = exclusive_scan(sums, offs, nb, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, s, out, n, offs);
+        e = hipGetLastError();
+    }
+    hipFreeAsync(sums, s);
+    hipFreeAsync(offs, s);
+    return e;
+}
+
+// 3a. Node fields of every representative.
+__global__ void k_emit_nodes(const uint2 *tok, const int32_t *canon, const int32_t *pos,
+                             const int32_t *height, int64_t T, int32_t *node_op, float *node_value,
+                             int32_t *node_height) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T || canon[t] != (int32_t)t) return;
+    const int32_t id = pos[t];
+    const uint2 w = tok[t];
+    const uint32_t op = w.x & 0xffu;
+    node_op[id] = (int32_t)(op == TGP_VAR ? (op | (w.x & 0xff00u)) : op);
+    node_value[id] = op == TGP_CONST ? __uint_as_float(w.y) : 0.0f;
+    node_height[id] = height[t];
+}
+
+// 3b. Children ids, in-degrees and multiplicities.
+__global__ void k_emit_edges(const int32_t *canon, const int32_t *pos, const int32_t *kid, int64_t T,
+                             int32_t *node_kid, int32_t *indeg, int32_t *mult) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int32_t c = canon[t];
+    const int32_t id = pos[c];
+    atomicAdd(&mult[id], 1);
+    if (c != (int32_t)t) return;
+    for (int j = 0; j < 3; ++j) {
+        const int32_t k = kid[3 * t + j];
+        const int32_t kid_id = k < 0 ? -1 : pos[canon[k]];
+        node_kid[3 * id + j] = kid_id;
+        if (kid_id >= 0) atomicAdd(&indeg[kid_id], 1);
+    }
+}
+
+__global__ void k_emit_roots(const int32_t *root_tok, const int32_t *canon, const int32_t *pos,
+                             int64_t R, int32_t *roots) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) roots[r] = pos[canon[root_tok[r]]];
+}
+
+static inline dim3 grid_for(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+void dag_device_free(DagDevice *d) {
+    hipFree(d->node_op);
+    hipFree(d->node_value);
+    hipFree(d->node_kid);
+    hipFree(d->node_height);
+    hipFree(d->roots);
+    hipFree(d->mult);
+    hipFree(d->indeg);
+    *d = DagDevice{};
+}
+
+#define DCHK(x)                                                                  \
+    do {                                                                         \
+        hipError_t _e = (x);                                                     \
+        if (_e != hipSuccess) {                                                  \
+            snprintf(err, errlen, "%s: %s", #x, hipGetErrorString(_e));          \
+            res.status = TGP_EHIP;                                               \
+            goto done;                                                           \
+        }                                                                        \
+    } while (0)
+
+uint32_t g_debug_hash_bits = 0;  // set by tests to force hash collisions
+
+DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
+                                int64_t T, DagDevice *dev, hipStream_t s, char *err,
+                                size_t errlen) {
+    DagBuildResult res{};
+    res.status = TGP_OK;
+    res.bad_tree = -1;
+    res.T = T;
+    const uint2 *tok = reinterpret_cast<const uint2 *>(tok_dev);
+    int32_t *kid = nullptr, *height = nullptr, *stk = nullptr, *root_tok = nullptr;
+    int32_t *canon = nullptr, *table = nullptr, *cnt = nullptr, *list = nullptr, *flag = nullptr,
+            *pos = nullptr;
+    BuildStatus *st = nullptr;
+    BuildStatus hs{};
+    std::vector<int32_t> hcnt;
+    uint64_t cap = 1024;
+    int64_t U = 0;
+    *dev = DagDevice{};
+    dev->T = T;
+    dev->R = R;
+    while (cap < (uint64_t)(2 * T)) cap <<= 1;
+
+    DCHK(hipMalloc((void **)&kid, sizeof(int32_t) * 3 * T));
+    DCHK(hipMalloc((void **)&height, sizeof(int32_t) * T));
+    DCHK(hipMalloc((void **)&stk, sizeof(int32_t) * T));
+    DCHK(hipMalloc((void **)&root_tok, sizeof(int32_t) * R));
+    DCHK(hipMalloc((void **)&st, sizeof(BuildStatus)));
+    hs.first_error = ~0ull;
+    hs.max_height = 0;
+    hs.max_var = -1;
+    hs.max_stack = 0;
+    hs.n_internal = 0;
+    DCHK(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_structure, grid_for(R, 64), dim3(64), 0, s, tok, off_dev, R, T, kid,
+                       height, stk, root_tok, st);
+    DCHK(hipGetLastError());
+    DCHK(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    DCHK(hipStreamSynchronize(s));
+    if (hs.first_error != ~0ull) {
+        const int code = (int)(hs.first_error & 15ull);
+        res.bad_tree = (int64_t)(hs.first_error >> 4);
+        res.status = code == ERR_OP ? TGP_EOP : (code == ERR_PARSE ? TGP_EPARSE : TGP_EINVAL);
+        snprintf(err, errlen, "tree %lld: %s", (long long)res.bad_tree,
+                 code == ERR_OP ? "unknown opcode"
+                                : (code == ERR_PARSE ? "token range is not exactly one postfix tree"
+                                                     : "offsets out of range or decreasing"));
+        goto done;
+    }
+    res.max_height = hs.max_height;
+    res.max_stack = hs.max_stack;
+    res.max_var = hs.max_var;
+    res.tree_internal = hs.n_internal;
+    {
+        const int64_t H = hs.max_height + 1;
+        DCHK(hipMalloc((void **)&cnt, sizeof(int32_t) * H));
+        DCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * H, s));
+        hipLaunchKernelGGL(k_level_hist, grid_for(T), dim3(256), 0, s, height, T, cnt);
+        DCHK(hipGetLastError());
+        hcnt.resize(H);
+        DCHK(hipMemcpyAsync(hcnt.data(), cnt, sizeof(int32_t) * H, hipMemcpyDeviceToHost, s));
+        DCHK(hipStreamSynchronize(s));
+        std::vector<int32_t> start(H + 1, 0);
+        for (int64_t h = 0; h < H; ++h) start[h + 1] = start[h] + hcnt[h];
+        DCHK(hipMemcpyAsync(cnt, start.data(), sizeof(int32_t) * H, hipMemcpyHostToDevice, s));
+        DCHK(hipMalloc((void **)&list, sizeof(int32_t) * T));
+        hipLaunchKernelGGL(k_level_scatter, grid_for(T), dim3(256), 0, s, height, T, cnt, list);
+        DCHK(hipGetLastError());
+        DCHK(hipMalloc((void **)&canon, sizeof(int32_t) * T));
+        DCHK(hipMalloc((void **)&table, sizeof(int32_t) * cap));
+        DCHK(hipMemsetAsync(table, 0xff, sizeof(int32_t) * cap, s));
+        for (int64_t h = 0; h < H; ++h) {
+            const int32_t n = hcnt[h];
+            if (!n) continue;
+            const int32_t *lst = list + start[h];
+            hipLaunchKernelGGL(k_hash_insert, grid_for(n), dim3(256), 0, s, lst, n, tok, kid, canon,
+                               table, (uint64_t)(cap - 1), g_debug_hash_bits);
+            hipLaunchKernelGGL(k_hash_resolve, grid_for(n), dim3(256), 0, s, lst, n, tok, kid,
+                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits);
+        }
+        DCHK(hipGetLastError());
+        DCHK(hipMalloc((void **)&flag, sizeof(int32_t) * T));
+        DCHK(hipMalloc((void **)&pos, sizeof(int32_t) * T));
+        hipLaunchKernelGGL(k_flags, grid_for(T), dim3(256), 0, s, canon, T, flag);
+        DCHK(exclusive_scan(flag, pos, T, s));
+        int32_t last[2] = {0, 0};
+        DCHK(hipMemcpyAsync(&last[0], pos + T - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DCHK(hipMemcpyAsync(&last[1], flag + T - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DCHK(hipStreamSynchronize(s));
+        U = (int64_t)last[0] + last[1];
+        res.U = U;
+        dev->U = U;
+        DCHK(hipMalloc((void **)&dev->node_op, sizeof(int32_t) * U));
+        DCHK(hipMalloc((void **)&dev->node_value, sizeof(float) * U));
+        DCHK(hipMalloc((void **)&dev->node_kid, sizeof(int32_t) * 3 * U));
+        DCHK(hipMalloc((void **)&dev->node_height, sizeof(int32_t) * U));
+        DCHK(hipMalloc((void **)&dev->roots, sizeof(int32_t) * R));
+        DCHK(hipMalloc((void **)&dev->mult, sizeof(int32_t) * U));
+        DCHK(hipMalloc((void **)&dev->indeg, sizeof(int32_t) * U));
+        DCHK(hipMemsetAsync(dev->mult, 0, sizeof(int32_t) * U, s));
+        DCHK(hipMemsetAsync(dev->indeg, 0, sizeof(int32_t) * U, s));
+        hipLaunchKernelGGL(k_emit_nodes, grid_for(T), dim3(256), 0, s, tok, canon, pos, height, T,
+                           dev->node_op, dev->node_value, dev->node_height);
+        hipLaunchKernelGGL(k_emit_edges, grid_for(T), dim3(256), 0, s, canon, pos, kid, T,
+                           dev->node_kid, dev->indeg, dev->mult);
+        hipLaunchKernelGGL(k_emit_roots, grid_for(R), dim3(256), 0, s, root_tok, canon, pos, R,
+                           dev->roots);
+        DCHK(hipGetLastError());
+        DCHK(hipStreamSynchronize(s));
+    }
+done:
+    hipFree(kid);
+    hipFree(height);
+    hipFree(stk);
+    hipFree(root_tok);
+    hipFree(st);
+    hipFree(cnt);
+    hipFree(list);
+    hipFree(canon);
+    hipFree(table);
+    hipFree(flag);
+    hipFree(pos);
+    if (res.status != TGP_OK) dag_device_free(dev);
+    return res;
+}
+
+}  // namespace tgp

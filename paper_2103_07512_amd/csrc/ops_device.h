@@ -1,0 +1,70 @@
+// ops_device.h -- FP32 device implementations of the primitive set (Table 1).
+//
+// Every operator maps FP32 operands to one FP32 result.  Protected forms
+// follow Table 1 of the paper; the readings where the table is silent are
+// the ones documented in include/tgp.h.  The same functions serve the fused
+// interpreter, the cache fill and the evaluate path, and the library is
+// compiled with -ffp-contract=off, so a subtree gives bit-identical values
+// whichever path computes it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tgp {
+
+__device__ __forceinline__ float f_add(float a, float b) { return a + b; }
+__device__ __forceinline__ float f_sub(float a, float b) { return a - b; }
+__device__ __forceinline__ float f_mult(float a, float b) { return a * b; }
+// Correctly rounded IEEE division; 0 for a zero denominator of either sign.
+__device__ __forceinline__ float f_div(float a, float b) { return b == 0.0f ? 0.0f : a / b; }
+// sin(pi x) / cos(pi x) by the device library's sinpi/cospi (exact at every
+// multiple of 1/2); adding +0 turns a -0 result into +0.
+__device__ __forceinline__ float f_sin(float a) { return sinpif(a) + 0.0f; }
+__device__ __forceinline__ float f_cos(float a) { return cospif(a) + 0.0f; }
+__device__ __forceinline__ float f_tan(float a) { return (sinpif(a) + 0.0f) / (cospif(a) + 0.0f); }
+__device__ __forceinline__ float f_exp(float a) { return expf(a); }
+__device__ __forceinline__ float f_log(float a) { return a < 0.0f ? -1.0f : logf(a); }
+__device__ __forceinline__ float f_pow(float a, float b) {
+    return (a == 0.0f && b == 0.0f) ? 0.0f : powf(a, b);
+}
+__device__ __forceinline__ float f_min(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float f_max(float a, float b) { return fmaxf(a, b); }
+// Halving each operand first is exact in the normal range and cannot overflow.
+__device__ __forceinline__ float f_mdist(float a, float b) { return a * 0.5f + b * 0.5f; }
+__device__ __forceinline__ float f_neg(float a) { return -a; }
+__device__ __forceinline__ float f_sqrt(float a) { return a < 0.0f ? 0.0f : sqrtf(a); }
+__device__ __forceinline__ float f_sign(float a) {
+    return a > 0.0f ? 1.0f : (a < 0.0f ? -1.0f : 0.0f);
+}
+__device__ __forceinline__ float f_abs(float a) { return fabsf(a); }
+__device__ __forceinline__ float f_clip(float a, float b, float c) { return fmaxf(fminf(a, c), b); }
+// Floored remainder: the exact truncated remainder, moved into the divisor's
+// sign when the two signs differ.
+__device__ __forceinline__ float f_mod(float a, float b) {
+    if (b == 0.0f) return 0.0f;
+    float r = fmodf(a, b);
+    if (r != 0.0f && ((r < 0.0f) != (b < 0.0f))) r += b;
+    return r;
+}
+__device__ __forceinline__ float f_frac(float a) { return a - floorf(a); }
+__device__ __forceinline__ float f_if(float a, float b, float c) { return a != 0.0f ? b : c; }
+__device__ __forceinline__ float f_step(float a) { return a < 0.0f ? -1.0f : 1.0f; }
+// The polynomial image operators are formed in FP64 and rounded once.
+__device__ __forceinline__ float f_sstep(float a) {
+    double x = a;
+    return (float)(x * x * (3.0 - 2.0 * x));
+}
+__device__ __forceinline__ float f_sstepp(float a) {
+    double x = a;
+    return (float)(x * x * x * (x * (6.0 * x - 15.0) + 10.0));
+}
+__device__ __forceinline__ float f_len(float a, float b) {
+    double x = a, y = b;
+    return (float)sqrt(x * x + y * y);
+}
+__device__ __forceinline__ float f_lerp(float a, float b, float c) {
+    double x = a, y = b, z = c;
+    return (float)(x + (y - x) * (z - floor(z)));
+}
+
+}  // namespace tgp

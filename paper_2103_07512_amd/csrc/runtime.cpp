@@ -1,0 +1,836 @@
+// runtime.cpp -- host side of libtgp: contexts, domains, the population DAG,
+// the cache planner, the program emitter and the C ABI of include/tgp.h.
+//
+// Evaluation of a DAG over a domain (TensorGP Sec. 3.1, with the subtree
+// caching of Sec. 1 / Sec. 2) is planned on the host:
+//   * every distinct (root, channel) pair becomes one interpreter program;
+//   * a shared subtree is materialised once in an HBM cache row when
+//     re-computing it at each use costs more VALU work than writing the row
+//     once and reading it at each use (HBM traffic priced in VALU slots);
+//   * subtrees whose evaluation would need more stack slots than the
+//     interpreter keeps in registers are materialised as well, so every
+//     program fits the register stack;
+//   * cached subtrees are filled level by level (a row's program may read
+//     rows of lower levels), then the root programs run fused with the error
+//     reduction (fitness) or with a store of their values (evaluate).
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "tgp_internal.h"
+
+namespace tgp {
+extern uint32_t g_debug_hash_bits;
+}
+
+using namespace tgp;
+
+// ------------------------------------------------------------------ objects
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct tgp_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t cache_budget = 0;
+    std::string err;
+    tgp_work_stats work{};
+    int force_K = 0;  // 0 = automatic
+    int force_tiles = 0;
+    DevBuf partial, cache;
+};
+
+struct tgp_domain_s {
+    tgp_ctx ctx = nullptr;
+    int32_t ndim = 0;
+    int64_t shape[3] = {1, 1, 1};
+    int64_t stride[3] = {1, 1, 1};
+    int64_t cases = 0;
+    float *coord[3] = {nullptr, nullptr, nullptr};
+};
+
+// A compiled evaluation plan of one DAG for one case count.
+struct Plan {
+    int64_t cases = -1;
+    int32_t n_slots = 0;
+    std::vector<int32_t> level_first;   // fill programs of level l: [level_first[l], level_first[l+1])
+    int32_t n_fill = 0;
+    int32_t n_reduce = 0;               // programs for (root, channel)
+    int32_t n_store = 0;                // programs for distinct roots
+    std::vector<int32_t> store_rows;    // for each root r: the store program's dest row, or -1
+    std::vector<int32_t> dup_src;       // for each root r: row r copies row dup_src[r] (-1: none)
+    uint2 *code_dev = nullptr;
+    ProgDesc *fill_dev = nullptr, *reduce_dev = nullptr, *store_dev = nullptr;
+    int32_t *ind_rows_dev = nullptr;
+    int64_t instructions = 0;
+    double exec_per_case = 0;           // instructions run per case, fitness form
+    double valu_dag_per_case = 0;       // cost-model slots of each DAG node once
+    int64_t cache_reads_per_case = 0;   // I_CACHE instructions executed, fitness form
+    void release() {
+        hipFree(code_dev);
+        hipFree(fill_dev);
+        hipFree(reduce_dev);
+        hipFree(store_dev);
+        hipFree(ind_rows_dev);
+        code_dev = nullptr;
+        fill_dev = reduce_dev = store_dev = nullptr;
+        ind_rows_dev = nullptr;
+        cases = -1;
+    }
+};
+
+struct tgp_dag_s {
+    tgp_ctx ctx = nullptr;
+    int32_t n_ind = 0, n_ch = 0;
+    tgp_dag_stats stats{};
+    DagDevice dev;
+    // host copies
+    std::vector<int32_t> op;   // op | var << 8
+    std::vector<float> value;
+    std::vector<int32_t> kid;  // [U][3]
+    std::vector<int32_t> roots, mult, indeg, height;
+    Plan plan;
+};
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    g_err = buf;
+    return st;
+}
+
+#define HCHK(ctx, x)                                                                           \
+    do {                                                                                       \
+        hipError_t _e = (x);                                                                   \
+        if (_e != hipSuccess)                                                                  \
+            return fail(ctx, TGP_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
+    } while (0)
+
+static hipError_t ensure(DevBuf &b, size_t bytes) {
+    if (b.cap >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e == hipSuccess) b.cap = want;
+    return e;
+}
+
+// --------------------------------------------------------------- cost model
+// VALU issue slots per case of each operator in the fused interpreter on
+// gfx950 (counted from the compiled instruction sequences; terminals cost
+// the register move that places them on the stack).
+static const double kOpCost[TGP_NUM_OPS] = {
+    1,  1,           // var const
+    1,  1,  1, 11,   // add sub mult div
+    21, 21, 46,      // sin cos tan
+    13, 15, 60,      // exp log pow
+    3,  3,  3,  1,   // min max mdist neg
+    11, 4,  1,  6,   // sqrt sign abs clip
+    40, 2,  3,       // mod frac if
+    2,  9,  12, 16, 14  // step sstep sstepp len lerp
+};
+// Writing a cache row once and reading it back, in VALU-slot equivalents per
+// case: 4 bytes of HBM traffic at 8 TB/s against 256 CUs x 64 lanes x 2.4 GHz
+// of VALU issue is about 20 slots per access.
+static const double kCacheAccessCost = 20.0;
+
+// --------------------------------------------------------------- contexts
+extern "C" {
+
+tgp_status tgp_ctx_create(int device, void *hip_stream, tgp_ctx *out) {
+    if (!out) return fail(nullptr, TGP_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0)
+        return fail(nullptr, TGP_EHIP, "no HIP device: %s", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, TGP_EINVAL, "device %d out of range", device);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, TGP_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess)
+        return fail(nullptr, TGP_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, TGP_EHIP, "device %d is %s, libtgp is built for gfx950", device,
+                    prop.gcnArchName);
+    tgp_ctx c = new tgp_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->cache_budget = prop.totalGlobalMem / 4;
+    *out = c;
+    return TGP_OK;
+}
+
+void tgp_ctx_destroy(tgp_ctx ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->partial.p);
+    hipFree(ctx->cache.p);
+    delete ctx;
+}
+
+tgp_status tgp_ctx_set_stream(tgp_ctx ctx, void *hip_stream) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    ctx->stream = (hipStream_t)hip_stream;
+    return TGP_OK;
+}
+
+const char *tgp_last_error(tgp_ctx ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+tgp_status tgp_ctx_set_cache_budget(tgp_ctx ctx, size_t bytes) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    ctx->cache_budget = bytes;
+    return TGP_OK;
+}
+
+// Tuning knobs (used by the autotuner and tests): cases per lane (2 or 4, 0 =
+// automatic) and tiles per work item (0 = automatic).
+tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles_per_item) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    if (cases_per_lane != 0 && !interp_variant_exists(cases_per_lane, 8))
+        return fail(ctx, TGP_EINVAL, "no interpreter with %d cases per lane", cases_per_lane);
+    if (tiles_per_item < 0) return fail(ctx, TGP_EINVAL, "tiles_per_item < 0");
+    ctx->force_K = cases_per_lane;
+    ctx->force_tiles = tiles_per_item;
+    return TGP_OK;
+}
+
+tgp_status tgp_debug_set_hash_bits(int32_t bits) {
+    if (bits < 0 || bits > 32) return fail(nullptr, TGP_EINVAL, "bits must be 0..32");
+    g_debug_hash_bits = (uint32_t)bits;
+    return TGP_OK;
+}
+
+// ---------------------------------------------------------------- domains
+tgp_status tgp_domain_create(tgp_ctx ctx, int32_t ndim, const int64_t *shape, const double *lo,
+                             const double *hi, tgp_domain *out) {
+    if (!ctx || !out || !shape) return fail(ctx, TGP_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (ndim < 1 || ndim > 3) return fail(ctx, TGP_ESHAPE, "ndim must be 1..3, got %d", ndim);
+    int64_t cases = 1;
+    for (int k = 0; k < ndim; ++k) {
+        if (shape[k] < 1) return fail(ctx, TGP_ESHAPE, "shape[%d] = %lld < 1", k, (long long)shape[k]);
+        cases *= shape[k];
+        if (cases > 0x7fffffffLL) return fail(ctx, TGP_ESHAPE, "more than 2^31-1 cases");
+    }
+    HCHK(ctx, hipSetDevice(ctx->device));
+    tgp_domain d = new tgp_domain_s();
+    d->ctx = ctx;
+    d->ndim = ndim;
+    d->cases = cases;
+    int64_t st = 1;
+    for (int k = ndim - 1; k >= 0; --k) {
+        d->shape[k] = shape[k];
+        d->stride[k] = st;
+        st *= shape[k];
+    }
+    for (int k = 0; k < ndim; ++k) {
+        const double l = lo ? lo[k] : -1.0, h = hi ? hi[k] : 1.0;
+        std::vector<float> tab(shape[k]);
+        for (int64_t i = 0; i < shape[k]; ++i) {
+            const double v = shape[k] == 1 ? l : l + (h - l) * (double)i / (double)(shape[k] - 1);
+            tab[i] = (float)v;
+        }
+        hipError_t e = hipMalloc((void **)&d->coord[k], sizeof(float) * shape[k]);
+        if (e == hipSuccess)
+            e = hipMemcpy(d->coord[k], tab.data(), sizeof(float) * shape[k], hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            tgp_domain_destroy(d);
+            return fail(ctx, TGP_EHIP, "coordinate table: %s", hipGetErrorString(e));
+        }
+    }
+    *out = d;
+    return TGP_OK;
+}
+
+void tgp_domain_destroy(tgp_domain d) {
+    if (!d) return;
+    for (int k = 0; k < 3; ++k) hipFree(d->coord[k]);
+    delete d;
+}
+
+int64_t tgp_domain_cases(tgp_domain d) { return d ? d->cases : -1; }
+
+// -------------------------------------------------------------------- DAG
+tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
+    if (!ctx || !pop || !out) return fail(ctx, TGP_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (pop->n_individuals < 0 || pop->n_channels < 1)
+        return fail(ctx, TGP_EINVAL, "n_individuals < 0 or n_channels < 1");
+    if (pop->memory != TGP_MEM_HOST && pop->memory != TGP_MEM_DEVICE)
+        return fail(ctx, TGP_EINVAL, "memory must be TGP_MEM_HOST or TGP_MEM_DEVICE");
+    const int64_t R = (int64_t)pop->n_individuals * pop->n_channels;
+    if (R > 0 && (!pop->offsets || !pop->tokens)) return fail(ctx, TGP_EINVAL, "NULL offsets/tokens");
+    HCHK(ctx, hipSetDevice(ctx->device));
+    int64_t T = 0;
+    const int64_t *off_dev = nullptr;
+    const tgp_token *tok_dev = nullptr;
+    int64_t *off_own = nullptr;
+    tgp_token *tok_own = nullptr;
+    if (R > 0) {
+        if (pop->memory == TGP_MEM_HOST) {
+            if (pop->offsets[0] != 0) return fail(ctx, TGP_EINVAL, "offsets[0] must be 0");
+            for (int64_t r = 0; r < R; ++r)
+                if (pop->offsets[r + 1] < pop->offsets[r])
+                    return fail(ctx, TGP_EINVAL, "offsets decrease at tree %lld", (long long)r);
+            T = pop->offsets[R];
+            if (T > 0x7fffffffLL) return fail(ctx, TGP_EINVAL, "more than 2^31-1 tokens");
+            HCHK(ctx, hipMalloc((void **)&off_own, sizeof(int64_t) * (R + 1)));
+            HCHK(ctx, hipMalloc((void **)&tok_own, sizeof(tgp_token) * std::max<int64_t>(T, 1)));
+            HCHK(ctx, hipMemcpyAsync(off_own, pop->offsets, sizeof(int64_t) * (R + 1),
+                                     hipMemcpyHostToDevice, ctx->stream));
+            if (T)
+                HCHK(ctx, hipMemcpyAsync(tok_own, pop->tokens, sizeof(tgp_token) * T,
+                                         hipMemcpyHostToDevice, ctx->stream));
+            off_dev = off_own;
+            tok_dev = tok_own;
+        } else {
+            int64_t ends[2];
+            HCHK(ctx, hipMemcpyAsync(&ends[0], pop->offsets, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                     ctx->stream));
+            HCHK(ctx, hipMemcpyAsync(&ends[1], pop->offsets + R, sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, ctx->stream));
+            HCHK(ctx, hipStreamSynchronize(ctx->stream));
+            if (ends[0] != 0) return fail(ctx, TGP_EINVAL, "offsets[0] must be 0");
+            T = ends[1];
+            if (T < 0 || T > 0x7fffffffLL) return fail(ctx, TGP_EINVAL, "bad token count");
+            off_dev = pop->offsets;
+            tok_dev = pop->tokens;
+        }
+    }
+    tgp_dag d = new tgp_dag_s();
+    d->ctx = ctx;
+    d->n_ind = pop->n_individuals;
+    d->n_ch = pop->n_channels;
+    d->stats.n_roots = R;
+    d->stats.max_var = -1;
+    if (R > 0) {
+        char msg[256] = "";
+        DagBuildResult br = build_dag_device(tok_dev, off_dev, R, T, &d->dev, ctx->stream, msg, sizeof msg);
+        hipFree(off_own);
+        hipFree(tok_own);
+        if (br.status != TGP_OK) {
+            delete d;
+            return fail(ctx, (tgp_status)br.status, "build_dag: %s", msg);
+        }
+        const int64_t U = br.U;
+        d->op.resize(U);
+        d->value.resize(U);
+        d->kid.resize(3 * U);
+        d->height.resize(U);
+        d->roots.resize(R);
+        d->mult.resize(U);
+        d->indeg.resize(U);
+        hipError_t e = hipSuccess;
+        auto cp = [&](void *dst, const void *src, size_t n) {
+            if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, ctx->stream);
+        };
+        cp(d->op.data(), d->dev.node_op, sizeof(int32_t) * U);
+        cp(d->value.data(), d->dev.node_value, sizeof(float) * U);
+        cp(d->kid.data(), d->dev.node_kid, sizeof(int32_t) * 3 * U);
+        cp(d->height.data(), d->dev.node_height, sizeof(int32_t) * U);
+        cp(d->roots.data(), d->dev.roots, sizeof(int32_t) * R);
+        cp(d->mult.data(), d->dev.mult, sizeof(int32_t) * U);
+        cp(d->indeg.data(), d->dev.indeg, sizeof(int32_t) * U);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            tgp_dag_destroy(d);
+            return fail(ctx, TGP_EHIP, "DAG readback: %s", hipGetErrorString(e));
+        }
+        d->stats.tree_nodes = T;
+        d->stats.tree_internal = br.tree_internal;
+        d->stats.dag_nodes = U;
+        int64_t di = 0, sh = 0;
+        for (int64_t i = 0; i < U; ++i) {
+            const int op = d->op[i] & 0xff;
+            if (kArity[op] > 0) {
+                ++di;
+                if (d->mult[i] >= 2) ++sh;
+            }
+        }
+        d->stats.dag_internal = di;
+        d->stats.shared_internal = sh;
+        d->stats.max_stack = br.max_stack;
+        d->stats.max_height = br.max_height;
+        d->stats.max_var = br.max_var;
+    }
+    *out = d;
+    return TGP_OK;
+}
+
+tgp_status tgp_dag_stats_get(tgp_dag dag, tgp_dag_stats *out) {
+    if (!dag || !out) return fail(nullptr, TGP_EINVAL, "NULL argument");
+    *out = dag->stats;
+    return TGP_OK;
+}
+
+tgp_status tgp_dag_export(tgp_dag dag, tgp_token *nodes, int32_t *children, int32_t *roots,
+                          int32_t *multiplicity, int32_t *indegree) {
+    if (!dag) return fail(nullptr, TGP_EINVAL, "dag is NULL");
+    const int64_t U = dag->stats.dag_nodes;
+    if (nodes)
+        for (int64_t i = 0; i < U; ++i) {
+            nodes[i].op = (uint8_t)(dag->op[i] & 0xff);
+            nodes[i].var = (uint8_t)((dag->op[i] >> 8) & 0xff);
+            nodes[i].pad = 0;
+            nodes[i].value = dag->value[i];
+        }
+    if (children && U) memcpy(children, dag->kid.data(), sizeof(int32_t) * 3 * U);
+    if (roots && dag->stats.n_roots) memcpy(roots, dag->roots.data(), sizeof(int32_t) * dag->stats.n_roots);
+    if (multiplicity && U) memcpy(multiplicity, dag->mult.data(), sizeof(int32_t) * U);
+    if (indegree && U) memcpy(indegree, dag->indeg.data(), sizeof(int32_t) * U);
+    return TGP_OK;
+}
+
+void tgp_dag_destroy(tgp_dag dag) {
+    if (!dag) return;
+    if (dag->ctx) hipSetDevice(dag->ctx->device);
+    dag->plan.release();
+    dag_device_free(&dag->dev);
+    delete dag;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ planner
+namespace {
+
+struct Planner {
+    const tgp_dag_s &d;
+    int D;
+    size_t budget_slots;
+    std::vector<uint8_t> cached;
+    std::vector<int32_t> slot, level;
+    std::vector<double> cost;
+
+    Planner(const tgp_dag_s &dag, int stack, size_t slots) : d(dag), D(stack), budget_slots(slots) {}
+
+    int op(int64_t n) const { return d.op[n] & 0xff; }
+    int arity(int64_t n) const { return kArity[op(n)]; }
+
+    // Decide the cached nodes; returns TGP_OK or an error.
+    tgp_status decide(const std::vector<int32_t> &rootrefs, std::string &why) {
+        const int64_t U = (int64_t)d.op.size();
+        cached.assign(U, 0);
+        cost.assign(U, 0.0);
+        for (int64_t n = 0; n < U; ++n) {
+            double c = kOpCost[op(n)];
+            for (int j = 0; j < arity(n); ++j) c += cost[d.kid[3 * n + j]];
+            cost[n] = c;
+        }
+        // Top-down: how often each node would be evaluated, and whether
+        // caching it pays for its HBM traffic.
+        std::vector<double> uses(U, 0.0);
+        for (int64_t n = 0; n < U; ++n) uses[n] = rootrefs[n];
+        size_t used = 0;
+        for (int64_t n = U - 1; n >= 0; --n) {
+            if (arity(n) > 0 && uses[n] >= 2 && used < budget_slots) {
+                const double save = cost[n] * (uses[n] - 1);
+                const double pay = kCacheAccessCost * (uses[n] + 1);
+                if (save > pay) {
+                    cached[n] = 1;
+                    ++used;
+                }
+            }
+            const double contrib = cached[n] ? 1.0 : uses[n];
+            if (contrib > 0)
+                for (int j = 0; j < arity(n); ++j) uses[d.kid[3 * n + j]] += contrib;
+        }
+        // Bottom-up: bound the register stack of every program.
+        std::vector<int32_t> need(U, 1);
+        auto ref_need = [&](int32_t c) { return cached[c] ? 1 : need[c]; };
+        for (int64_t n = 0; n < U; ++n) {
+            const int a = arity(n);
+            if (a == 0) {
+                need[n] = 1;
+                continue;
+            }
+            for (;;) {
+                int worst = 0, wj = -1;
+                for (int j = 0; j < a; ++j) {
+                    const int v = j + ref_need(d.kid[3 * n + j]);
+                    if (v > worst) {
+                        worst = v;
+                        wj = j;
+                    }
+                }
+                if (worst <= D) {
+                    need[n] = worst;
+                    break;
+                }
+                const int32_t c = d.kid[3 * n + wj];
+                cached[c] = 1;  // spill this child's subtree to a cache row
+                ++used;
+            }
+        }
+        if (used > budget_slots) {
+            why = "the subtree cache needed to bound the evaluator stack exceeds the cache budget";
+            return TGP_ENOMEM;
+        }
+        // Levels and slots.
+        std::vector<int32_t> dep(U, 0);
+        level.assign(U, -1);
+        slot.assign(U, -1);
+        int32_t ns = 0;
+        for (int64_t n = 0; n < U; ++n) {
+            int32_t dp = 0;
+            for (int j = 0; j < arity(n); ++j) {
+                const int32_t c = d.kid[3 * n + j];
+                dp = std::max(dp, cached[c] ? level[c] + 1 : dep[c]);
+            }
+            dep[n] = dp;
+            if (cached[n]) {
+                level[n] = dp;
+                slot[n] = ns++;
+            }
+        }
+        return TGP_OK;
+    }
+
+    // Postfix program of node n (n itself is expanded even when cached).
+    void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads) const {
+        std::vector<std::pair<int32_t, int32_t>> st;  // (node, next child)
+        st.push_back({root, 0});
+        while (!st.empty()) {
+            auto &top = st.back();
+            const int32_t n = top.first;
+            const bool leafish = arity(n) == 0 || (n != root && cached[n]);
+            if (!leafish && top.second < arity(n)) {
+                const int32_t c = d.kid[3 * n + top.second];
+                ++top.second;
+                st.push_back({c, 0});
+                continue;
+            }
+            uint2 ins{0, 0};
+            if (n != root && cached[n]) {
+                ins.x = I_CACHE | ((uint32_t)slot[n] << 8);
+                ++cache_reads;
+            } else {
+                const int o = op(n);
+                if (o == TGP_VAR) {
+                    const int v = (d.op[n] >> 8) & 0xff;
+                    ins.x = v == 0 ? I_X : (v == 1 ? I_Y : I_Z);
+                } else if (o == TGP_CONST) {
+                    ins.x = I_CONST;
+                    memcpy(&ins.y, &d.value[n], 4);
+                } else {
+                    ins.x = kFnBase + o;
+                }
+            }
+            code.push_back(ins);
+            st.pop_back();
+        }
+        code.push_back(uint2{I_END, 0});
+    }
+};
+
+}  // namespace
+
+static tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
+    Plan &P = d->plan;
+    if (P.cases == cases) return TGP_OK;
+    P.release();
+    const int64_t U = d->stats.dag_nodes, R = d->stats.n_roots;
+    const int n_ch = d->n_ch;
+    // distinct programs
+    std::vector<int32_t> rootrefs(U, 0);
+    std::unordered_map<int64_t, int32_t> reduce_of;  // (root id, ch) -> program
+    std::vector<std::pair<int32_t, int32_t>> reduce_list;
+    std::vector<int32_t> ind_rows(R);
+    std::vector<int32_t> store_of(U, -1);
+    std::vector<int32_t> store_list;  // root node ids
+    P.store_rows.assign(R, -1);
+    P.dup_src.assign(R, -1);
+    for (int64_t r = 0; r < R; ++r) {
+        const int32_t n = d->roots[r];
+        const int ch = (int)(r % n_ch);
+        const int64_t key = (int64_t)n * n_ch + ch;
+        auto it = reduce_of.find(key);
+        if (it == reduce_of.end()) {
+            it = reduce_of.emplace(key, (int32_t)reduce_list.size()).first;
+            reduce_list.push_back({n, ch});
+            rootrefs[n] += 1;
+        }
+        ind_rows[r] = it->second;
+        if (store_of[n] < 0) {
+            store_of[n] = (int32_t)r;
+            store_list.push_back(n);
+            P.store_rows[r] = (int32_t)r;
+        } else {
+            P.dup_src[r] = store_of[n];
+        }
+    }
+    const int D = interp_max_stack();
+    size_t budget_slots = (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
+    Planner pl(*d, D, budget_slots);
+    std::string why;
+    tgp_status st = pl.decide(rootrefs, why);
+    if (st != TGP_OK) return fail(ctx, st, "%s", why.c_str());
+
+    // Emit code: fill programs by level, then one program per distinct root.
+    std::vector<uint2> code;
+    std::vector<ProgDesc> fill, reduce, store;
+    int32_t max_level = -1;
+    std::vector<int32_t> cached_nodes;
+    for (int64_t n = 0; n < U; ++n)
+        if (pl.cached[n]) {
+            cached_nodes.push_back((int32_t)n);
+            max_level = std::max(max_level, pl.level[n]);
+        }
+    P.level_first.assign(max_level + 2, 0);
+    std::vector<std::vector<ProgDesc>> by_level(max_level + 1);
+    int64_t cache_reads_fill = 0;
+    for (int32_t n : cached_nodes) {
+        ProgDesc pd{};
+        pd.code_off = (uint32_t)code.size();
+        pl.emit(n, code, cache_reads_fill);
+        pd.len = (uint32_t)(code.size() - pd.code_off);
+        pd.dest = pl.slot[n];
+        pd.chan = 0;
+        by_level[pl.level[n]].push_back(pd);
+    }
+    auto longest_first = [](std::vector<ProgDesc> &v) {
+        std::stable_sort(v.begin(), v.end(), [](const ProgDesc &a, const ProgDesc &b) { return a.len > b.len; });
+    };
+    for (int l = 0; l <= max_level; ++l) {
+        longest_first(by_level[l]);
+        P.level_first[l] = (int32_t)fill.size();
+        fill.insert(fill.end(), by_level[l].begin(), by_level[l].end());
+    }
+    P.level_first[max_level + 1] = (int32_t)fill.size();
+    std::vector<uint32_t> root_code(U, 0), root_len(U, 0);
+    int64_t cache_reads_roots = 0;
+    double exec_roots = 0;
+    std::vector<int64_t> reads_of(U, 0);
+    for (int32_t n : store_list) {
+        root_code[n] = (uint32_t)code.size();
+        int64_t cr = 0;
+        pl.emit(n, code, cr);
+        reads_of[n] = cr;
+        root_len[n] = (uint32_t)(code.size() - root_code[n]);
+    }
+    for (size_t p = 0; p < reduce_list.size(); ++p) {
+        const int32_t n = reduce_list[p].first;
+        ProgDesc pd{root_code[n], root_len[n], (int32_t)p, reduce_list[p].second};
+        reduce.push_back(pd);
+        exec_roots += root_len[n] - 1;
+        cache_reads_roots += reads_of[n];
+    }
+    for (int32_t n : store_list) {
+        ProgDesc pd{root_code[n], root_len[n], store_of[n], 0};
+        store.push_back(pd);
+    }
+    // reduce programs keep dest = their row; order them longest first
+    longest_first(reduce);
+    longest_first(store);
+    code.push_back(uint2{I_END, 0});  // padding
+
+    double exec_fill = 0;
+    for (auto &pd : fill) exec_fill += pd.len - 1;
+    double valu = 0;
+    for (int64_t n = 0; n < U; ++n) valu += kOpCost[d->op[n] & 0xff];
+    P.exec_per_case = exec_fill + exec_roots;
+    P.valu_dag_per_case = valu;
+    P.cache_reads_per_case = cache_reads_fill + cache_reads_roots;
+    P.instructions = (int64_t)code.size();
+    P.n_slots = (int32_t)cached_nodes.size();
+    P.n_fill = (int32_t)fill.size();
+    P.n_reduce = (int32_t)reduce.size();
+    P.n_store = (int32_t)store.size();
+
+    auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+        return e;
+    };
+    hipError_t e = up((void **)&P.code_dev, code.data(), sizeof(uint2) * code.size());
+    if (e == hipSuccess) e = up((void **)&P.fill_dev, fill.data(), sizeof(ProgDesc) * fill.size());
+    if (e == hipSuccess) e = up((void **)&P.reduce_dev, reduce.data(), sizeof(ProgDesc) * reduce.size());
+    if (e == hipSuccess) e = up((void **)&P.store_dev, store.data(), sizeof(ProgDesc) * store.size());
+    if (e == hipSuccess) e = up((void **)&P.ind_rows_dev, ind_rows.data(), sizeof(int32_t) * ind_rows.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // host vectors die here
+    if (e != hipSuccess) {
+        P.release();
+        return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
+    }
+    P.cases = cases;
+    return TGP_OK;
+}
+
+// Work split: each work item is one program over tiles_per_stripe tiles of
+// 64*K cases; aim for enough items to fill 256 CUs several times over.
+static void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
+                         int32_t *tiles_per) {
+    const int64_t tile = 64 * (int64_t)K;
+    const int64_t n_tiles = (cases + tile - 1) / tile;
+    int64_t tps;
+    if (ctx->force_tiles > 0) {
+        tps = ctx->force_tiles;
+    } else {
+        const int64_t target_items = 65536;
+        int64_t want_stripes = (target_items + n_progs - 1) / std::max<int64_t>(n_progs, 1);
+        want_stripes = std::max<int64_t>(1, std::min(want_stripes, n_tiles));
+        tps = (n_tiles + want_stripes - 1) / want_stripes;
+    }
+    tps = std::max<int64_t>(1, std::min(tps, n_tiles));
+    *tiles_per = (int32_t)tps;
+    *stripes = (int32_t)((n_tiles + tps - 1) / tps);
+}
+
+static int choose_K(tgp_ctx ctx, int64_t cases) {
+    if (ctx->force_K) return ctx->force_K;
+    return cases >= 64 * 4 * 4 ? 4 : 2;
+}
+
+static void fill_args(InterpArgs &a, tgp_domain dom, const Plan &P, const float *cache) {
+    memset(&a, 0, sizeof a);
+    a.code = P.code_dev;
+    a.n_cases = (int32_t)dom->cases;
+    a.ndim = dom->ndim;
+    for (int k = 0; k < 3; ++k) {
+        a.shape[k] = (int32_t)dom->shape[k];
+        a.stride[k] = (int32_t)dom->stride[k];
+        a.coord[k] = dom->coord[k] ? dom->coord[k] : dom->coord[0];
+    }
+    a.cache = cache;
+}
+
+static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float **cache_out) {
+    const Plan &P = d->plan;
+    *cache_out = nullptr;
+    if (P.n_slots == 0) return TGP_OK;
+    const size_t bytes = sizeof(float) * (size_t)P.n_slots * (size_t)dom->cases;
+    HCHK(ctx, ensure(ctx->cache, bytes));
+    float *cache = (float *)ctx->cache.p;
+    *cache_out = cache;
+    for (size_t l = 0; l + 1 < P.level_first.size(); ++l) {
+        const int32_t b = P.level_first[l], e = P.level_first[l + 1];
+        if (e == b) continue;
+        InterpArgs a;
+        fill_args(a, dom, P, cache);
+        a.progs = P.fill_dev + b;
+        a.n_progs = e - b;
+        choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
+        a.out = cache;
+        HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
+    }
+    return TGP_OK;
+}
+
+static tgp_status check_eval_args(tgp_ctx ctx, tgp_dag d, tgp_domain dom) {
+    if (!ctx || !d || !dom) return fail(ctx, TGP_EINVAL, "NULL argument");
+    if (d->ctx != ctx || dom->ctx != ctx) return fail(ctx, TGP_EINVAL, "handles of another context");
+    if (d->stats.max_var >= dom->ndim)
+        return fail(ctx, TGP_ESHAPE, "a tree uses axis %lld but the domain has %d axes",
+                    (long long)d->stats.max_var, dom->ndim);
+    return TGP_OK;
+}
+
+static void record_work(tgp_ctx ctx, tgp_dag d, tgp_domain dom, bool fitness) {
+    const Plan &P = d->plan;
+    tgp_work_stats &w = ctx->work;
+    const double cases = (double)dom->cases;
+    w.credited_node_evals = d->stats.dag_nodes * dom->cases;
+    w.executed_node_evals = (int64_t)(P.exec_per_case * cases);
+    w.cached_nodes = P.n_slots;
+    w.cache_levels = (int64_t)P.level_first.size() - 1;
+    w.programs = fitness ? P.n_reduce : P.n_store;
+    w.instructions = P.instructions;
+    w.algorithmic_valu = P.valu_dag_per_case * cases;
+    w.cache_bytes_written = (int64_t)P.n_slots * dom->cases * 4;
+    w.cache_bytes_read = P.cache_reads_per_case * dom->cases * 4;
+}
+
+extern "C" {
+
+tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *target_dev, int32_t loss,
+                       double *out_dev) {
+    tgp_status st = check_eval_args(ctx, d, dom);
+    if (st != TGP_OK) return st;
+    if (loss != TGP_RMSE && loss != TGP_MSE) return fail(ctx, TGP_EINVAL, "loss must be TGP_RMSE or TGP_MSE");
+    if (d->n_ind == 0) return TGP_OK;
+    if (!target_dev || !out_dev) return fail(ctx, TGP_EINVAL, "NULL target or output");
+    HCHK(ctx, hipSetDevice(ctx->device));
+    st = build_plan(ctx, d, dom->cases);
+    if (st != TGP_OK) return st;
+    const Plan &P = d->plan;
+    const int K = choose_K(ctx, dom->cases);
+    float *cache = nullptr;
+    st = run_fill(ctx, d, dom, K, &cache);
+    if (st != TGP_OK) return st;
+    InterpArgs a;
+    fill_args(a, dom, P, cache);
+    a.progs = P.reduce_dev;
+    a.n_progs = P.n_reduce;
+    choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
+    a.target = target_dev;
+    HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.n_stripes));
+    a.partial = (float2 *)ctx->partial.p;
+    HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream));
+    HCHK(ctx, launch_finalize(a.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.n_stripes,
+                              (double)d->n_ch * (double)dom->cases, loss, out_dev, ctx->stream));
+    record_work(ctx, d, dom, true);
+    return TGP_OK;
+}
+
+tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) {
+    tgp_status st = check_eval_args(ctx, d, dom);
+    if (st != TGP_OK) return st;
+    if (d->stats.n_roots == 0) return TGP_OK;
+    if (!out_dev) return fail(ctx, TGP_EINVAL, "NULL output");
+    HCHK(ctx, hipSetDevice(ctx->device));
+    st = build_plan(ctx, d, dom->cases);
+    if (st != TGP_OK) return st;
+    const Plan &P = d->plan;
+    const int K = choose_K(ctx, dom->cases);
+    float *cache = nullptr;
+    st = run_fill(ctx, d, dom, K, &cache);
+    if (st != TGP_OK) return st;
+    InterpArgs a;
+    fill_args(a, dom, P, cache);
+    a.progs = P.store_dev;
+    a.n_progs = P.n_store;
+    choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
+    a.out = out_dev;
+    HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
+    const size_t row = sizeof(float) * (size_t)dom->cases;
+    for (int64_t r = 0; r < d->stats.n_roots; ++r)
+        if (P.dup_src[r] >= 0)
+            HCHK(ctx, hipMemcpyAsync((char *)out_dev + row * r, (char *)out_dev + row * P.dup_src[r], row,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+    record_work(ctx, d, dom, false);
+    return TGP_OK;
+}
+
+tgp_status tgp_last_work(tgp_ctx ctx, tgp_work_stats *out) {
+    if (!ctx || !out) return fail(ctx, TGP_EINVAL, "NULL argument");
+    *out = ctx->work;
+    return TGP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// tgp_internal.h -- definitions shared by the host runtime and the HIP
+// kernels of libtgp (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tgp.h"
+
+namespace tgp {
+
+// Arity of each public opcode (Table 1).
+constexpr int kArity[TGP_NUM_OPS] = {
+    0, 0,        // var const
+    2, 2, 2, 2,  // add sub mult div
+    1, 1, 1,     // sin cos tan
+    1, 1, 2,     // exp log pow
+    2, 2, 2, 1,  // min max mdist neg
+    1, 1, 1, 3,  // sqrt sign abs clip
+    2, 1, 3,     // mod frac if
+    1, 1, 1, 2, 3  // step sstep sstepp len lerp
+};
+
+// Interpreter instruction codes.  An instruction is a uint2: .x = code |
+// (aux << 8), .y = the FP32 bits of a constant.  aux is the cache slot of
+// I_CACHE.  Function opcodes are the public opcode plus kFnBase.
+enum : uint32_t {
+    I_X = 0, I_Y = 1, I_Z = 2, I_CONST = 3, I_CACHE = 4, I_END = 5,
+    kFnBase = 8,
+    I_NUM = kFnBase + TGP_NUM_OPS
+};
+
+// One program of the interpreter: a postfix instruction stream that leaves a
+// single value per case.  dest is the cache slot (cache fill), the output row
+// (evaluate) or the partial-sum row (fitness); chan is the target channel.
+struct ProgDesc {
+    uint32_t code_off;
+    uint32_t len;
+    int32_t dest;
+    int32_t chan;
+};
+
+// Launch arguments of the interpreter kernel.
+struct InterpArgs {
+    const uint2 *code;           // all instructions, padded by one I_END
+    const ProgDesc *progs;       // n_progs programs
+    int32_t n_progs;
+    int32_t n_stripes;           // items = n_progs * n_stripes
+    int32_t tiles_per_stripe;    // tiles of 64*K cases per item
+    int32_t n_cases;
+    int32_t ndim;
+    int32_t shape[3];
+    int32_t stride[3];
+    const float *coord[3];       // per-axis coordinate tables
+    const float *cache;          // [slots][n_cases]
+    float *out;                  // STORE: [dest][n_cases]
+    const float *target;         // REDUCE: [chan][n_cases]
+    float2 *partial;             // REDUCE: [dest][n_stripes] (sum, compensation)
+};
+
+// Instantiated kernel variants (cases per lane K, stack registers D).
+struct Variant {
+    int K;
+    int D;
+};
+
+hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s);
+bool interp_variant_exists(int K, int D);
+int interp_max_stack();   // largest D compiled
+
+// Finalize: per individual, FP64 sum of its channels' partial rows.
+hipError_t launch_finalize(const float2 *partial, const int32_t *ind_rows, int32_t n_ind,
+                           int32_t n_ch, int32_t n_stripes, double n_terms, int32_t loss,
+                           double *out, hipStream_t s);
+
+// DAG construction kernels (k_dag.hip).
+struct DagDevice {
+    int64_t T = 0, R = 0, U = 0;
+    int32_t *node_op = nullptr;      // packed per node: op | var << 8
+    float *node_value = nullptr;
+    int32_t *node_kid = nullptr;     // [U][3]
+    int32_t *node_height = nullptr;
+    int32_t *roots = nullptr;        // [R]
+    int32_t *mult = nullptr;         // [U]
+    int32_t *indeg = nullptr;        // [U]
+};
+
+struct DagBuildResult {
+    int status;        // tgp_status
+    int64_t bad_tree;  // offending tree for EPARSE/EOP/EINVAL
+    int64_t T, U, max_height, max_stack, max_var, tree_internal;
+};
+
+// Builds the DAG of R trees given device tokens/offsets; allocates dev
+// arrays (hipMalloc) that the caller frees with dag_device_free.
+DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
+                                int64_t T, DagDevice *dev, hipStream_t s, char *err, size_t errlen);
+void dag_device_free(DagDevice *dev);
+
+}  // namespace tgp

@@ -1,0 +1,255 @@
+"""Python binding of libtgp (ctypes): argument marshalling only.
+
+Every step of the evaluation runs in the HIP library; this module converts
+numpy / torch arguments to the pointers and sizes of the C ABI in
+include/tgp.h and turns non-zero status codes into exceptions.  Device
+buffers are torch tensors on the context's GPU; the context orders its work
+on the current torch stream of that device unless told otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(_HERE, "libtgp.so")
+
+TOKEN_DTYPE = np.dtype([("op", "u1"), ("var", "u1"), ("pad", "<u2"), ("value", "<f4")])
+RMSE, MSE = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+STATUS = {0: "TGP_OK", -1: "TGP_EINVAL", -2: "TGP_EPARSE", -3: "TGP_EDEPTH", -4: "TGP_EOP",
+          -5: "TGP_ENOMEM", -6: "TGP_EHIP", -7: "TGP_ESHAPE", -8: "TGP_EBUSY"}
+
+
+class TgpError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Population(ctypes.Structure):
+    _fields_ = [("n_individuals", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("offsets", ctypes.c_void_p), ("tokens", ctypes.c_void_p),
+                ("memory", ctypes.c_int32)]
+
+
+class DagStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "tree_nodes", "tree_internal", "dag_nodes", "dag_internal", "shared_internal",
+        "max_stack", "max_height", "n_roots", "max_var")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class WorkStats(ctypes.Structure):
+    _fields_ = [("credited_node_evals", ctypes.c_int64), ("executed_node_evals", ctypes.c_int64),
+                ("cached_nodes", ctypes.c_int64), ("cache_levels", ctypes.c_int64),
+                ("programs", ctypes.c_int64), ("instructions", ctypes.c_int64),
+                ("algorithmic_valu", ctypes.c_double), ("cache_bytes_read", ctypes.c_int64),
+                ("cache_bytes_written", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+I32, I64 = ctypes.c_int32, ctypes.c_int64
+
+# (name, restype, argtypes) of every exported function of include/tgp.h
+SIGNATURES = [
+    ("tgp_ctx_create", I32, [ctypes.c_int, P, PP]),
+    ("tgp_ctx_destroy", None, [P]),
+    ("tgp_ctx_set_stream", I32, [P, P]),
+    ("tgp_last_error", ctypes.c_char_p, [P]),
+    ("tgp_ctx_set_cache_budget", I32, [P, ctypes.c_size_t]),
+    ("tgp_ctx_set_tuning", I32, [P, I32, I32]),
+    ("tgp_debug_set_hash_bits", I32, [I32]),
+    ("tgp_domain_create", I32, [P, I32, P, P, P, PP]),
+    ("tgp_domain_destroy", None, [P]),
+    ("tgp_domain_cases", I64, [P]),
+    ("tgp_build_dag", I32, [P, ctypes.POINTER(_Population), PP]),
+    ("tgp_dag_stats_get", I32, [P, ctypes.POINTER(DagStats)]),
+    ("tgp_dag_export", I32, [P, P, P, P, P, P]),
+    ("tgp_dag_destroy", None, [P]),
+    ("tgp_evaluate", I32, [P, P, P, P]),
+    ("tgp_fitness", I32, [P, P, P, P, I32, P]),
+    ("tgp_last_work", I32, [P, ctypes.POINTER(WorkStats)]),
+]
+
+
+def lib():
+    """Load libtgp.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY):
+            raise RuntimeError(f"{LIBRARY} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIBRARY)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = lib().tgp_last_error(ctx)
+        raise TgpError(status, msg.decode() if msg else "")
+
+
+def _stream_of(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """tgp_ctx: a device, a HIP stream and the library's scratch memory."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = device
+        h = ctypes.c_void_p()
+        s = _stream_of(device) if stream is None else ctypes.c_void_p(stream)
+        _check(lib().tgp_ctx_create(device, s, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().tgp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(lib().tgp_ctx_set_stream(self.h, ctypes.c_void_p(stream)), self.h)
+
+    def set_cache_budget(self, nbytes: int):
+        _check(lib().tgp_ctx_set_cache_budget(self.h, nbytes), self.h)
+
+    def set_tuning(self, cases_per_lane: int = 0, tiles_per_item: int = 0):
+        _check(lib().tgp_ctx_set_tuning(self.h, cases_per_lane, tiles_per_item), self.h)
+
+    def last_work(self) -> dict:
+        w = WorkStats()
+        _check(lib().tgp_last_work(self.h, ctypes.byref(w)), self.h)
+        return w.as_dict()
+
+
+def debug_set_hash_bits(bits: int):
+    _check(lib().tgp_debug_set_hash_bits(bits))
+
+
+class Domain:
+    """tgp_domain: an N-D grid of fitness cases (coordinates on the device)."""
+
+    def __init__(self, ctx: Context, shape, lo=None, hi=None):
+        self.ctx = ctx
+        shape = np.ascontiguousarray(shape, dtype=np.int64)
+        self.shape = tuple(int(v) for v in shape)
+        lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+        hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().tgp_domain_create(ctx.h, len(shape), shape.ctypes.data,
+                                       None if lo_a is None else lo_a.ctypes.data,
+                                       None if hi_a is None else hi_a.ctypes.data,
+                                       ctypes.byref(h)), ctx.h)
+        self.h = h
+        self.cases = int(lib().tgp_domain_cases(h))
+
+    def close(self):
+        if self.h:
+            lib().tgp_domain_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Dag:
+    """tgp_dag: a population hash-consed on the GPU."""
+
+    def __init__(self, ctx: Context, tokens, offsets, n_individuals: int, n_channels: int = 1):
+        self.ctx = ctx
+        pop = _Population()
+        pop.n_individuals = n_individuals
+        pop.n_channels = n_channels
+        keep = []
+        if hasattr(tokens, "data_ptr"):          # torch tensors on the device
+            pop.memory = MEM_DEVICE
+            pop.offsets = offsets.data_ptr()
+            pop.tokens = tokens.data_ptr()
+        else:
+            t = np.ascontiguousarray(tokens, dtype=TOKEN_DTYPE)
+            o = np.ascontiguousarray(offsets, dtype=np.int64)
+            keep += [t, o]
+            pop.memory = MEM_HOST
+            pop.offsets = o.ctypes.data
+            pop.tokens = t.ctypes.data
+        h = ctypes.c_void_p()
+        _check(lib().tgp_build_dag(ctx.h, ctypes.byref(pop), ctypes.byref(h)), ctx.h)
+        self.h = h
+        self.n_individuals = n_individuals
+        self.n_channels = n_channels
+
+    @staticmethod
+    def from_population(ctx: Context, pop) -> "Dag":
+        return Dag(ctx, pop.tokens, pop.offsets, pop.n_individuals, pop.n_channels)
+
+    def stats(self) -> dict:
+        s = DagStats()
+        _check(lib().tgp_dag_stats_get(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def export(self) -> dict:
+        st = self.stats()
+        U, R = st["dag_nodes"], st["n_roots"]
+        nodes = np.zeros(U, TOKEN_DTYPE)
+        children = np.zeros((U, 3), np.int32)
+        roots = np.zeros(R, np.int32)
+        mult = np.zeros(U, np.int32)
+        indeg = np.zeros(U, np.int32)
+        _check(lib().tgp_dag_export(self.h, nodes.ctypes.data, children.ctypes.data,
+                                    roots.ctypes.data, mult.ctypes.data, indeg.ctypes.data))
+        return dict(nodes=nodes, children=children, roots=roots, multiplicity=mult,
+                    indegree=indeg, **st)
+
+    def close(self):
+        if self.h:
+            lib().tgp_dag_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_dag(ctx: Context, pop) -> Dag:
+    return Dag.from_population(ctx, pop)
+
+
+def evaluate(ctx: Context, dag: Dag, dom: Domain, out):
+    """Per-case values of every tree into out (torch float32, [n_roots, cases])."""
+    _check(lib().tgp_evaluate(ctx.h, dag.h, dom.h, ctypes.c_void_p(out.data_ptr())), ctx.h)
+    return out
+
+
+def fitness(ctx: Context, dag: Dag, dom: Domain, target, loss: int, out):
+    """RMSE/MSE per individual into out (torch float64, [n_individuals])."""
+    _check(lib().tgp_fitness(ctx.h, dag.h, dom.h, ctypes.c_void_p(target.data_ptr()), loss,
+                             ctypes.c_void_p(out.data_ptr())), ctx.h)
+    return out
