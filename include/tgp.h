@@ -210,20 +210,41 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, float *out_dev
 tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, const float *target_dev,
                        int32_t loss, double *out_dev);
 
-/* Work counts of the last tgp_evaluate / tgp_fitness on ctx (for reports):
- * credited = dag_nodes x cases x ... as defined in the fields. */
+/* Work counts of the last tgp_evaluate / tgp_fitness on ctx (for reports).
+ * VALU figures are lane-slots: cases x the per-operator instruction counts of
+ * the compiled interpreter (a cost model, documented with the library). */
 typedef struct {
-    int64_t credited_node_evals; /* DAG nodes reachable from the roots x cases */
+    int64_t credited_node_evals; /* DAG nodes x cases (each distinct subtree once) */
     int64_t executed_node_evals; /* interpreter instructions run x cases */
     int64_t cached_nodes;        /* subtrees materialised in the cache */
+    int64_t stack_spills;        /* of which cached only to bound the register stack */
     int64_t cache_levels;        /* dependent cache-fill launches */
     int64_t programs;            /* root programs (distinct (root, channel) pairs) */
     int64_t instructions;        /* total program length */
-    double algorithmic_valu;     /* VALU lane-slots by the op cost model x cases */
+    double algorithmic_valu;     /* every DAG node once, cost model x cases */
+    double executed_valu_fill;   /* cache-fill launches, cost model x cases */
+    double executed_valu_roots;  /* root-program launch, cost model x cases */
     int64_t cache_bytes_read;    /* HBM bytes of cache loads (algorithmic) */
     int64_t cache_bytes_written; /* HBM bytes of cache stores (algorithmic) */
 } tgp_work_stats;
 tgp_status tgp_last_work(tgp_ctx ctx, tgp_work_stats *out);
+
+/* Phase times of the last tgp_build_dag and tgp_fitness / tgp_evaluate on
+ * ctx.  Device times come from HIP events recorded on the context's stream
+ * around the launches, and are only taken while timing is enabled
+ * (tgp_ctx_set_timing); tgp_last_timing blocks until those events complete. */
+typedef struct {
+    double build_dag_ms;  /* host wall time of the blocking tgp_build_dag */
+    double plan_ms;       /* host wall time of planning and program upload */
+    double fill_ms;       /* device time of the cache-fill launches */
+    double interp_ms;     /* device time of the root-program launch */
+    double finalize_ms;   /* device time of the per-individual finalize */
+    int64_t interp_items; /* work items (waves) of the root-program launch */
+    int32_t cases_per_lane;
+    int32_t tiles_per_item;
+} tgp_timing;
+tgp_status tgp_ctx_set_timing(tgp_ctx ctx, int32_t enable);
+tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
-        lib.orc_eval.argtypes = [P, P, i64, ctypes.c_int, P, P, P, P, i64, P, P, P, ctypes.c_int]
+        lib.orc_eval.argtypes = [P, P, i64, ctypes.c_int, P, P, P, P, i64, P, P, P, P, ctypes.c_int]
         lib.orc_eval.restype = ctypes.c_int
         lib.orc_fitness.argtypes = [P, P, i64, ctypes.c_int, i64, ctypes.c_int, P]
         lib.orc_fitness.restype = ctypes.c_int
@@ -66,11 +66,13 @@ def coords(n: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
 
 
 def evaluate(tokens, offsets, shape, lo=None, hi=None, cases=None, variants=False,
-             nthreads: int = 0):
+             nthreads: int = 0, bound=False):
     """Per-case values of every tree.
 
-    Returns v64 [n_roots][n_cases] (float64), and with variants=True also
-    (v32r [n_roots][n_cases] float64, stab [n_roots][n_cases] uint8 flags).
+    Returns v64 [n_roots][n_cases] (float64); with variants=True the tuple
+    (v64, v32r, stab) with the O32r values and the uint8 stability flags, and
+    with bound=True as well, (v64, v32r, stab, ebound) with the running error
+    bound of every root.
     """
     tokens = np.ascontiguousarray(tokens, dtype=_TOKEN)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -87,15 +89,19 @@ def evaluate(tokens, offsets, shape, lo=None, hi=None, cases=None, variants=Fals
         n_cases = len(cases)
         cptr = cases
     v64 = np.empty((n_roots, n_cases), dtype=np.float64)
+    variants = variants or bound
     v32 = np.empty_like(v64) if variants else None
     st = np.empty((n_roots, n_cases), dtype=np.uint8) if variants else None
+    eb = np.empty_like(v64) if bound else None
     rc = _load().orc_eval(_ptr(tokens), _ptr(offsets), n_roots, nd, _ptr(shape), _ptr(lo),
                           _ptr(hi), _ptr(cptr), n_cases, _ptr(v64), _ptr(v32), _ptr(st),
-                          int(nthreads))
+                          _ptr(eb), int(nthreads))
     if rc == -1000000000:
         raise ValueError("bad domain or case list")
     if rc < 0:
         raise ValueError(f"malformed tree {-rc - 1}")
+    if bound:
+        return v64, v32, st, eb
     return (v64, v32, st) if variants else v64
 
 
@@ -124,7 +130,16 @@ def render_target(trees, shape, lo=None, hi=None):
     np.cumsum(lens, out=offsets[1:])
     toks = np.concatenate(trees).astype(_TOKEN)
     v = evaluate(toks, offsets, shape, lo, hi)
-    t = v.astype(np.float32)
+    with np.errstate(over="ignore", invalid="ignore"):
+        t = v.astype(np.float32)
     if not np.all(np.isfinite(t)):
         return None
     return t
+
+
+def target_renderer(shape, lo=None, hi=None):
+    """render(tree) for popgen.pick_target: O64 rounded to FP32, None if non-finite."""
+    def render(tree):
+        t = render_target([tree], shape, lo, hi)
+        return None if t is None else t[0]
+    return render

@@ -14,14 +14,22 @@
  *     squared error (Sec. 4.1, Table 2) or the mean squared error.
  *
  * It walks each tree recursively, one fitness case at a time, in double
- * precision (mode O64).  For the parity contract it can also evaluate three
- * FP32-shaped variants of the same walk (each operator result computed in
- * FP64 from the operands and then rounded to FP32 (O32r), or rounded and then
- * pushed one FP32 ulp up (O32u) or down (O32d) whenever the rounding was
- * inexact) and record, at every operator with a discontinuity, which side of
- * it each variant took.  A case is "stable" when all four variants agree on
- * every such side, the O64 result is finite, and each FP32 variant is finite
- * and within 1e-6 * max(|O64|, 1) of it.
+ * precision (mode O64).  For the parity contract it can also run, in the
+ * same walk, (a) O32r: every operator computed in FP64 from its operands and
+ * rounded to FP32, the way an FP32 tensor engine with correctly rounded
+ * operators would compute, and (b) a first-order running error bound in the
+ * manner of Wilkinson's forward error analysis: the bound of a node is the
+ * sum over its operands of |partial derivative| x operand bound, plus the
+ * rounding error an FP32 implementation of the operator may add (1 ulp for
+ * add/sub/mult/div/sqrt/mdist/frac/mod, 4 ulp for the library functions).
+ * At every operator with a discontinuity (protected division, log, sqrt,
+ * pow, sign, step, if, mod, frac, tan, lerp) the walk also checks that the
+ * O64 operand lies more than 4 bounds away from the discontinuity (or is
+ * exactly on it with a zero bound) and that O32r falls on the same side.
+ * A case is "stable" when those checks pass, O64 and O32r are finite, and
+ * the bound of the root is at most 5e-6 * max(|O64|, 1), half the per-case
+ * tolerance of the parity contract: to first order, no FP32 evaluation with
+ * operators of the assumed accuracy can then miss O64 by more than that.
  *
  * Readings of points the paper leaves open (each one a deliberate choice):
  *   sin/cos are sin(pi x) and cos(pi x) (Table 1 prints them swapped);
@@ -316,49 +324,155 @@ static double ev64(const onode *n, int32_t i, const double *xyz)
     return apply(p->op, a, b, c, &br);
 }
 
-/* Four variants at once: v[0] = O64, v[1] = O32r, v[2] = O32u, v[3] = O32d. */
-static void round_variant(double r, double *out3)
-{
-    float f = (float)r;
-    out3[0] = (double)f;
-    if (isnan(r) || (double)f == r || isinf(f)) {
-        out3[1] = out3[2] = (double)f;
-        return;
-    }
-    out3[1] = (double)nextafterf(f, INFINITY);
-    out3[2] = (double)nextafterf(f, -INFINITY);
-}
-
 static int same_branch(double a, double b)
 {
     return a == b || (isnan(a) && isnan(b));
 }
 
-static void ev4(const onode *n, int32_t i, const double *xyz, double *v, int *trace_ok)
+/* Rounding error an FP32 implementation of the operator may add, relative. */
+#define U_CR 1.1920928955078125e-07   /* 2^-23: one ulp, correctly rounded ops */
+#define U_LIB 4.76837158203125e-07    /* 2^-21: four ulp, library functions */
+#define MARGIN 4.0
+
+static double contrib(double deriv, double e)
+{
+    return e == 0.0 ? 0.0 : fabs(deriv) * e;
+}
+
+/* Is x at least MARGIN bounds away from the point p (or exactly on it with a
+ * zero bound)? */
+static int clear_of(double x, double p, double e)
+{
+    if (e == 0.0)
+        return 1;
+    return fabs(x - p) > MARGIN * e;
+}
+
+static double dist_to_int(double x)
+{
+    return fabs(x - rint(x));
+}
+
+/* One node in O64 (v), O32r (r) and the running bound (e); *ok is cleared
+ * when a discontinuity is too close or O32r falls on another side. */
+static void evb(const onode *n, int32_t i, const double *xyz, double *v, double *r, double *e, int *ok)
 {
     const onode *p = &n[i];
     if (p->op == OV_VAR) {
-        v[0] = v[1] = v[2] = v[3] = xyz[p->var];
+        *v = *r = xyz[p->var];
+        *e = 0.0;
         return;
     }
     if (p->op == OV_CONST) {
-        v[0] = v[1] = v[2] = v[3] = (double)p->value;
+        *v = *r = (double)p->value;
+        *e = 0.0;
         return;
     }
-    double k[3][4] = {{0}};
+    double kv[3] = {0, 0, 0}, kr[3] = {0, 0, 0}, ke[3] = {0, 0, 0};
     int ar = orc_arity[p->op];
     for (int j = 0; j < ar; j++)
-        ev4(n, p->kid[j], xyz, k[j], trace_ok);
-    double br0, brm, r;
-    v[0] = apply(p->op, k[0][0], k[1][0], k[2][0], &br0);
-    for (int m = 1; m < 4; m++) {
-        double rr[3];
-        r = apply(p->op, k[0][m], k[1][m], k[2][m], &brm);
-        if (!same_branch(br0, brm))
-            *trace_ok = 0;
-        round_variant(r, rr);
-        v[m] = rr[m - 1];
+        evb(n, p->kid[j], xyz, &kv[j], &kr[j], &ke[j], ok);
+    double br0, br1;
+    const double a = kv[0], b = kv[1], c = kv[2];
+    const double ea = ke[0], eb = ke[1], ec = ke[2];
+    const double val = apply(p->op, a, b, c, &br0);
+    *r = (double)(float)apply(p->op, kr[0], kr[1], kr[2], &br1);
+    if (!same_branch(br0, br1))
+        *ok = 0;
+    *v = val;
+    double err = 0.0;
+    const double av = fabs(val);
+    double s, co;
+    switch (p->op) {
+    case OV_ADD:
+    case OV_SUB: err = ea + eb + U_CR * av; break;
+    case OV_MULT: err = contrib(b, ea) + contrib(a, eb) + U_CR * av; break;
+    case OV_DIV:
+        if (b == 0.0) {
+            if (eb != 0.0) *ok = 0;
+            err = 0.0;
+        } else {
+            if (!clear_of(b, 0.0, eb)) *ok = 0;
+            err = contrib(1.0 / b, ea) + contrib(a / (b * b), eb) + U_CR * av;
+        }
+        break;
+    case OV_SIN: sincospi64(a, &s, &co); err = contrib(M_PI * co, ea) + U_LIB * av; break;
+    case OV_COS: sincospi64(a, &s, &co); err = contrib(M_PI * s, ea) + U_LIB * av; break;
+    case OV_TAN:
+        sincospi64(a, &s, &co);
+        if (!clear_of(fabs(a - floor(a)), 0.5, ea)) *ok = 0;
+        err = contrib(M_PI / (co * co), ea) + U_LIB * av;
+        break;
+    case OV_EXP: err = contrib(val, ea) + U_LIB * av; break;
+    case OV_LOG:
+        if (!clear_of(a, 0.0, ea)) *ok = 0;
+        err = a > 0.0 ? contrib(1.0 / a, ea) + U_LIB * av : 0.0;
+        break;
+    case OV_POW:
+        if (a == 0.0 && b == 0.0) {
+            if (ea != 0.0 || eb != 0.0) *ok = 0;
+            err = 0.0;
+            break;
+        }
+        if (!clear_of(a, 0.0, ea)) *ok = 0;
+        if (a < 0.0 && eb != 0.0 && dist_to_int(b) <= MARGIN * eb) *ok = 0;
+        if (a != 0.0 && isfinite(val))
+            err = contrib(b * val / a, ea) + (a > 0.0 ? contrib(val * log(a), eb) : 0.0) + U_LIB * av;
+        break;
+    case OV_MIN:
+    case OV_MAX: err = ea > eb ? ea : eb; break;
+    case OV_MDIST: err = 0.5 * (ea + eb) + U_CR * av; break;
+    case OV_NEG:
+    case OV_ABS: err = ea; break;
+    case OV_SQRT:
+        if (!clear_of(a, 0.0, ea)) *ok = 0;
+        err = a > 0.0 ? contrib(0.5 / sqrt(a), ea) + U_CR * av : 0.0;
+        break;
+    case OV_SIGN:
+    case OV_STEP:
+        if (!clear_of(a, 0.0, ea)) *ok = 0;
+        err = 0.0;
+        break;
+    case OV_CLIP:
+        err = ea > eb ? ea : eb;
+        err = err > ec ? err : ec;
+        break;
+    case OV_MOD:
+        if (b == 0.0) {
+            if (eb != 0.0) *ok = 0;
+            err = 0.0;
+        } else {
+            const double q = a / b;
+            const double eq = (ea + fabs(q) * eb) / fabs(b);
+            if (eq != 0.0 && dist_to_int(q) <= MARGIN * eq) *ok = 0;
+            err = ea + contrib(floor(q), eb) + U_CR * av;
+        }
+        break;
+    case OV_FRAC:
+        if (ea != 0.0 && dist_to_int(a) <= MARGIN * ea) *ok = 0;
+        err = ea + U_CR * av;
+        break;
+    case OV_IF:
+        if (!clear_of(a, 0.0, ea)) *ok = 0;
+        err = a != 0.0 ? eb : ec;
+        break;
+    case OV_SSTEP: err = contrib(6.0 * a - 6.0 * a * a, ea) + U_LIB * av; break;
+    case OV_SSTEPP: err = contrib(30.0 * a * a * (a - 1.0) * (a - 1.0), ea) + U_LIB * av; break;
+    case OV_LEN:
+        err = val == 0.0 ? ea + eb : contrib(a / val, ea) + contrib(b / val, eb) + U_LIB * av;
+        break;
+    case OV_LERP: {
+        const double fz = c - floor(c);
+        if (ec != 0.0 && dist_to_int(c) <= MARGIN * ec) *ok = 0;
+        err = contrib(1.0 - fz, ea) + contrib(fz, eb) + contrib(b - a, ec) + U_LIB * av;
+        break;
     }
+    }
+    if (!isfinite(val))
+        err = 0.0;   /* an exact special value; its class is checked instead */
+    else if (!isfinite(err))
+        *ok = 0;
+    *e = err;
 }
 
 static int nonfinite_class(double v)
@@ -377,15 +491,17 @@ static int nonfinite_class(double v)
  *   v64:   out [n_roots][n_cases] O64 values (required).
  *   v32r:  out [n_roots][n_cases] O32r values, or NULL.
  *   stab:  out [n_roots][n_cases] flags, or NULL: bit0 = stable finite case,
- *          bit1 = every FP32 variant non-finite of one class with agreeing
- *          branch sides (that class is then the required one).
- *   When v32r or stab is given, the four-variant walk runs; otherwise only O64.
+ *          bit1 = O32r and the FP32 rounding of O64 are non-finite of one
+ *          class, clear of every discontinuity (that class is then required).
+ *   ebound: out [n_roots][n_cases] running error bound of the root, or NULL.
+ *   When any of v32r, stab, ebound is given the checked walk runs; otherwise
+ *   only O64.
  * Returns 0, or -(1 + r) when tree r is malformed, or -1000000000 on bad args.
  */
 int orc_eval(const orc_token *tokens, const int64_t *offsets, int64_t n_roots,
              int ndim, const int64_t *shape, const double *lo, const double *hi,
              const int64_t *cases, int64_t n_cases,
-             double *v64, double *v32r, uint8_t *stab, int nthreads)
+             double *v64, double *v32r, uint8_t *stab, double *ebound, int nthreads)
 {
     odomain d;
     if (make_domain(ndim, shape, lo, hi, &d) != 0)
@@ -406,7 +522,7 @@ int orc_eval(const orc_token *tokens, const int64_t *offsets, int64_t n_roots,
         }
     }
     if (rc == 0) {
-        int four = (v32r != NULL) || (stab != NULL);
+        int four = (v32r != NULL) || (stab != NULL) || (ebound != NULL);
         int64_t work = n_roots * n_cases;
 #ifdef _OPENMP
         if (nthreads > 0)
@@ -425,26 +541,23 @@ int orc_eval(const orc_token *tokens, const int64_t *offsets, int64_t n_roots,
                     v64[q] = ev64(t->n, t->count - 1, xyz);
                     continue;
                 }
-                double v[4];
+                double v, r32, e;
                 int ok = 1;
-                ev4(t->n, t->count - 1, xyz, v, &ok);
-                v64[q] = v[0];
+                evb(t->n, t->count - 1, xyz, &v, &r32, &e, &ok);
+                v64[q] = v;
                 if (v32r)
-                    v32r[q] = v[1];
+                    v32r[q] = r32;
+                if (ebound)
+                    ebound[q] = e;
                 if (stab) {
                     uint8_t f = 0;
-                    int fin = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]);
-                    if (ok && fin) {
-                        double sc = fabs(v[0]) > 1.0 ? fabs(v[0]) : 1.0;
-                        int close = 1;
-                        for (int m = 1; m < 4; m++)
-                            if (fabs(v[m] - v[0]) > 1e-6 * sc)
-                                close = 0;
-                        if (close)
-                            f |= 1;
-                    }
-                    int cl = nonfinite_class(v[1]);
-                    if (ok && cl && nonfinite_class(v[2]) == cl && nonfinite_class(v[3]) == cl)
+                    const double sc = fabs(v) > 1.0 ? fabs(v) : 1.0;
+                    if (ok && isfinite(v) && isfinite(r32) && e <= 5e-6 * sc && fabs(r32 - v) <= 5e-6 * sc)
+                        f |= 1;
+                    const int cl = nonfinite_class(r32);
+                    const int cv = nonfinite_class((double)(float)v);
+                    if (ok && cl && cl == cv &&
+                        (!isfinite(v) || fabs(v) - e > 3.4028235677973366e38 * (1.0 + 5.9604644775390625e-08)))
                         f |= 2;
                     stab[q] = f;
                 }

@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -49,7 +50,22 @@ struct tgp_ctx_s {
     int force_K = 0;  // 0 = automatic
     int force_tiles = 0;
     DevBuf partial, cache;
+    bool timing = false;
+    bool ev_ready = false;
+    hipEvent_t ev[6] = {};  // fill begin/end, interp begin/end, finalize begin/end
+    bool fill_recorded = false;
+    tgp_timing times{};
 };
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+static void record(tgp_ctx ctx, int i) {
+    if (ctx->timing && ctx->ev_ready) hipEventRecord(ctx->ev[i], ctx->stream);
+}
 
 struct tgp_domain_s {
     tgp_ctx ctx = nullptr;
@@ -64,6 +80,7 @@ struct tgp_domain_s {
 struct Plan {
     int64_t cases = -1;
     int32_t n_slots = 0;
+    int64_t n_spills = 0;               // cached only to bound the register stack
     std::vector<int32_t> level_first;   // fill programs of level l: [level_first[l], level_first[l+1])
     int32_t n_fill = 0;
     int32_t n_reduce = 0;               // programs for (root, channel)
@@ -76,6 +93,8 @@ struct Plan {
     int64_t instructions = 0;
     double exec_per_case = 0;           // instructions run per case, fitness form
     double valu_dag_per_case = 0;       // cost-model slots of each DAG node once
+    double valu_fill_per_case = 0;      // cost-model slots run by the fill programs
+    double valu_roots_per_case = 0;     // cost-model slots run by the reduce programs
     int64_t cache_reads_per_case = 0;   // I_CACHE instructions executed, fitness form
     void release() {
         hipFree(code_dev);
@@ -191,6 +210,8 @@ void tgp_ctx_destroy(tgp_ctx ctx) {
     hipStreamSynchronize(ctx->stream);
     hipFree(ctx->partial.p);
     hipFree(ctx->cache.p);
+    if (ctx->ev_ready)
+        for (auto &e : ctx->ev) hipEventDestroy(e);
     delete ctx;
 }
 
@@ -205,6 +226,37 @@ const char *tgp_last_error(tgp_ctx ctx) { return ctx ? ctx->err.c_str() : g_err.
 tgp_status tgp_ctx_set_cache_budget(tgp_ctx ctx, size_t bytes) {
     if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
     ctx->cache_budget = bytes;
+    return TGP_OK;
+}
+
+tgp_status tgp_ctx_set_timing(tgp_ctx ctx, int32_t enable) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    if (enable && !ctx->ev_ready) {
+        HCHK(ctx, hipSetDevice(ctx->device));
+        for (auto &e : ctx->ev) HCHK(ctx, hipEventCreate(&e));
+        ctx->ev_ready = true;
+    }
+    ctx->timing = enable != 0;
+    return TGP_OK;
+}
+
+tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out) {
+    if (!ctx || !out) return fail(ctx, TGP_EINVAL, "NULL argument");
+    tgp_timing t = ctx->times;
+    t.fill_ms = t.interp_ms = t.finalize_ms = 0;
+    if (ctx->timing && ctx->ev_ready) {
+        HCHK(ctx, hipEventSynchronize(ctx->ev[5]));
+        float ms = 0;
+        if (ctx->fill_recorded) {
+            HCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+            t.fill_ms = ms;
+        }
+        HCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+        t.interp_ms = ms;
+        HCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]));
+        t.finalize_ms = ms;
+    }
+    *out = t;
     return TGP_OK;
 }
 
@@ -280,6 +332,7 @@ int64_t tgp_domain_cases(tgp_domain d) { return d ? d->cases : -1; }
 tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
     if (!ctx || !pop || !out) return fail(ctx, TGP_EINVAL, "NULL argument");
     *out = nullptr;
+    const double t0 = now_ms();
     if (pop->n_individuals < 0 || pop->n_channels < 1)
         return fail(ctx, TGP_EINVAL, "n_individuals < 0 or n_channels < 1");
     if (pop->memory != TGP_MEM_HOST && pop->memory != TGP_MEM_DEVICE)
@@ -380,6 +433,7 @@ tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
         d->stats.max_var = br.max_var;
     }
     *out = d;
+    ctx->times.build_dag_ms = now_ms() - t0;
     return TGP_OK;
 }
 
@@ -427,6 +481,7 @@ struct Planner {
     std::vector<uint8_t> cached;
     std::vector<int32_t> slot, level;
     std::vector<double> cost;
+    int64_t spills = 0;
 
     Planner(const tgp_dag_s &dag, int stack, size_t slots) : d(dag), D(stack), budget_slots(slots) {}
 
@@ -443,33 +498,15 @@ struct Planner {
             for (int j = 0; j < arity(n); ++j) c += cost[d.kid[3 * n + j]];
             cost[n] = c;
         }
-        // Top-down: how often each node would be evaluated, and whether
-        // caching it pays for its HBM traffic.
-        std::vector<double> uses(U, 0.0);
-        for (int64_t n = 0; n < U; ++n) uses[n] = rootrefs[n];
-        size_t used = 0;
-        for (int64_t n = U - 1; n >= 0; --n) {
-            if (arity(n) > 0 && uses[n] >= 2 && used < budget_slots) {
-                const double save = cost[n] * (uses[n] - 1);
-                const double pay = kCacheAccessCost * (uses[n] + 1);
-                if (save > pay) {
-                    cached[n] = 1;
-                    ++used;
-                }
-            }
-            const double contrib = cached[n] ? 1.0 : uses[n];
-            if (contrib > 0)
-                for (int j = 0; j < arity(n); ++j) uses[d.kid[3 * n + j]] += contrib;
-        }
-        // Bottom-up: bound the register stack of every program.
+        // Bottom-up: bound the register stack of every program.  A node
+        // whose children cannot be evaluated left to right within D slots
+        // gets its most demanding child's subtree spilled to a cache row.
         std::vector<int32_t> need(U, 1);
         auto ref_need = [&](int32_t c) { return cached[c] ? 1 : need[c]; };
+        size_t used = 0;
         for (int64_t n = 0; n < U; ++n) {
             const int a = arity(n);
-            if (a == 0) {
-                need[n] = 1;
-                continue;
-            }
+            if (a == 0) continue;
             for (;;) {
                 int worst = 0, wj = -1;
                 for (int j = 0; j < a; ++j) {
@@ -484,13 +521,31 @@ struct Planner {
                     break;
                 }
                 const int32_t c = d.kid[3 * n + wj];
-                cached[c] = 1;  // spill this child's subtree to a cache row
+                cached[c] = 1;
                 ++used;
             }
         }
+        spills = (int64_t)used;
         if (used > budget_slots) {
             why = "the subtree cache needed to bound the evaluator stack exceeds the cache budget";
             return TGP_ENOMEM;
+        }
+        // Top-down: how often each node would be evaluated, and whether
+        // caching it pays for its HBM traffic (within the remaining budget).
+        std::vector<double> uses(U, 0.0);
+        for (int64_t n = 0; n < U; ++n) uses[n] = rootrefs[n];
+        for (int64_t n = U - 1; n >= 0; --n) {
+            if (!cached[n] && arity(n) > 0 && uses[n] >= 2 && used < budget_slots) {
+                const double save = cost[n] * (uses[n] - 1);
+                const double pay = kCacheAccessCost * (uses[n] + 1);
+                if (save > pay) {
+                    cached[n] = 1;
+                    ++used;
+                }
+            }
+            const double contrib = cached[n] ? 1.0 : uses[n];
+            if (contrib > 0)
+                for (int j = 0; j < arity(n); ++j) uses[d.kid[3 * n + j]] += contrib;
         }
         // Levels and slots.
         std::vector<int32_t> dep(U, 0);
@@ -513,7 +568,8 @@ struct Planner {
     }
 
     // Postfix program of node n (n itself is expanded even when cached).
-    void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads) const {
+    // Adds the cost-model slots of its instructions to *valu.
+    void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads, double *valu) const {
         std::vector<std::pair<int32_t, int32_t>> st;  // (node, next child)
         st.push_back({root, 0});
         while (!st.empty()) {
@@ -530,8 +586,10 @@ struct Planner {
             if (n != root && cached[n]) {
                 ins.x = I_CACHE | ((uint32_t)slot[n] << 8);
                 ++cache_reads;
+                *valu += 1.0;
             } else {
                 const int o = op(n);
+                *valu += kOpCost[o];
                 if (o == TGP_VAR) {
                     const int v = (d.op[n] >> 8) & 0xff;
                     ins.x = v == 0 ? I_X : (v == 1 ? I_Y : I_Z);
@@ -551,9 +609,17 @@ struct Planner {
 
 }  // namespace
 
+static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases);
+
 static tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
+    const double t0 = now_ms();
+    tgp_status st = d->plan.cases == cases ? TGP_OK : build_plan_impl(ctx, d, cases);
+    ctx->times.plan_ms = now_ms() - t0;
+    return st;
+}
+
+static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     Plan &P = d->plan;
-    if (P.cases == cases) return TGP_OK;
     P.release();
     const int64_t U = d->stats.dag_nodes, R = d->stats.n_roots;
     const int n_ch = d->n_ch;
@@ -605,10 +671,11 @@ static tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.level_first.assign(max_level + 2, 0);
     std::vector<std::vector<ProgDesc>> by_level(max_level + 1);
     int64_t cache_reads_fill = 0;
+    double valu_fill = 0;
     for (int32_t n : cached_nodes) {
         ProgDesc pd{};
         pd.code_off = (uint32_t)code.size();
-        pl.emit(n, code, cache_reads_fill);
+        pl.emit(n, code, cache_reads_fill, &valu_fill);
         pd.len = (uint32_t)(code.size() - pd.code_off);
         pd.dest = pl.slot[n];
         pd.chan = 0;
@@ -627,19 +694,24 @@ static tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     int64_t cache_reads_roots = 0;
     double exec_roots = 0;
     std::vector<int64_t> reads_of(U, 0);
+    std::vector<double> valu_of(U, 0.0);
     for (int32_t n : store_list) {
         root_code[n] = (uint32_t)code.size();
         int64_t cr = 0;
-        pl.emit(n, code, cr);
+        double v = 0;
+        pl.emit(n, code, cr, &v);
         reads_of[n] = cr;
+        valu_of[n] = v;
         root_len[n] = (uint32_t)(code.size() - root_code[n]);
     }
+    double valu_roots = 0;
     for (size_t p = 0; p < reduce_list.size(); ++p) {
         const int32_t n = reduce_list[p].first;
         ProgDesc pd{root_code[n], root_len[n], (int32_t)p, reduce_list[p].second};
         reduce.push_back(pd);
         exec_roots += root_len[n] - 1;
         cache_reads_roots += reads_of[n];
+        valu_roots += valu_of[n];
     }
     for (int32_t n : store_list) {
         ProgDesc pd{root_code[n], root_len[n], store_of[n], 0};
@@ -656,9 +728,12 @@ static tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     for (int64_t n = 0; n < U; ++n) valu += kOpCost[d->op[n] & 0xff];
     P.exec_per_case = exec_fill + exec_roots;
     P.valu_dag_per_case = valu;
+    P.valu_fill_per_case = valu_fill;
+    P.valu_roots_per_case = valu_roots;
     P.cache_reads_per_case = cache_reads_fill + cache_reads_roots;
     P.instructions = (int64_t)code.size();
     P.n_slots = (int32_t)cached_nodes.size();
+    P.n_spills = pl.spills;
     P.n_fill = (int32_t)fill.size();
     P.n_reduce = (int32_t)reduce.size();
     P.n_store = (int32_t)store.size();
@@ -723,11 +798,14 @@ static void fill_args(InterpArgs &a, tgp_domain dom, const Plan &P, const float 
 static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float **cache_out) {
     const Plan &P = d->plan;
     *cache_out = nullptr;
+    ctx->fill_recorded = false;
     if (P.n_slots == 0) return TGP_OK;
     const size_t bytes = sizeof(float) * (size_t)P.n_slots * (size_t)dom->cases;
     HCHK(ctx, ensure(ctx->cache, bytes));
     float *cache = (float *)ctx->cache.p;
     *cache_out = cache;
+    record(ctx, 0);
+    ctx->fill_recorded = ctx->timing;
     for (size_t l = 0; l + 1 < P.level_first.size(); ++l) {
         const int32_t b = P.level_first[l], e = P.level_first[l + 1];
         if (e == b) continue;
@@ -739,6 +817,7 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
         a.out = cache;
         HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
     }
+    record(ctx, 1);
     return TGP_OK;
 }
 
@@ -758,10 +837,13 @@ static void record_work(tgp_ctx ctx, tgp_dag d, tgp_domain dom, bool fitness) {
     w.credited_node_evals = d->stats.dag_nodes * dom->cases;
     w.executed_node_evals = (int64_t)(P.exec_per_case * cases);
     w.cached_nodes = P.n_slots;
+    w.stack_spills = P.n_spills;
     w.cache_levels = (int64_t)P.level_first.size() - 1;
     w.programs = fitness ? P.n_reduce : P.n_store;
     w.instructions = P.instructions;
     w.algorithmic_valu = P.valu_dag_per_case * cases;
+    w.executed_valu_fill = P.valu_fill_per_case * cases;
+    w.executed_valu_roots = P.valu_roots_per_case * cases;
     w.cache_bytes_written = (int64_t)P.n_slots * dom->cases * 4;
     w.cache_bytes_read = P.cache_reads_per_case * dom->cases * 4;
 }
@@ -791,9 +873,16 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     a.target = target_dev;
     HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.n_stripes));
     a.partial = (float2 *)ctx->partial.p;
+    record(ctx, 2);
     HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream));
+    record(ctx, 3);
+    record(ctx, 4);
     HCHK(ctx, launch_finalize(a.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.n_stripes,
                               (double)d->n_ch * (double)dom->cases, loss, out_dev, ctx->stream));
+    record(ctx, 5);
+    ctx->times.interp_items = (int64_t)a.n_progs * a.n_stripes;
+    ctx->times.cases_per_lane = K;
+    ctx->times.tiles_per_item = a.tiles_per_stripe;
     record_work(ctx, d, dom, true);
     return TGP_OK;
 }
@@ -817,7 +906,14 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     a.n_progs = P.n_store;
     choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
     a.out = out_dev;
+    record(ctx, 2);
     HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
+    record(ctx, 3);
+    record(ctx, 4);
+    record(ctx, 5);
+    ctx->times.interp_items = (int64_t)a.n_progs * a.n_stripes;
+    ctx->times.cases_per_lane = K;
+    ctx->times.tiles_per_item = a.tiles_per_stripe;
     const size_t row = sizeof(float) * (size_t)dom->cases;
     for (int64_t r = 0; r < d->stats.n_roots; ++r)
         if (P.dup_src[r] >= 0)

@@ -477,17 +477,51 @@ class DomainSpec:
         return int(np.prod(self.shape))
 
 
+@dataclass
+class TargetSpec:
+    """A target tensor rendered from seeded full trees, one per channel.
+
+    Channel c first tries seed + c; a tree whose rendering has a non-finite
+    value is redrawn with the seed n_channels higher, until one is finite.
+    """
+    depth: int
+    seed: int
+    functions: tuple = F18
+    ndim: int = 2
+    n_channels: int = 1
+
+    def tree(self, channel: int, attempt: int) -> np.ndarray:
+        return full_tree(self.depth, self.seed + channel + attempt * self.n_channels,
+                         self.functions, self.ndim)
+
+
+def pick_target(spec: TargetSpec, render, max_attempts: int = 10000):
+    """render(tree) -> 1-D float32 values over the domain, or None when any
+    value is non-finite.  Returns (trees, float32 [n_channels][cases])."""
+    trees, rows = [], []
+    for c in range(spec.n_channels):
+        for attempt in range(max_attempts):
+            t = spec.tree(c, attempt)
+            v = render(t)
+            if v is not None:
+                trees.append(t)
+                rows.append(np.asarray(v, dtype=np.float32).reshape(-1))
+                break
+        else:
+            raise RuntimeError("no finite target tree found")
+    return trees, np.stack(rows)
+
+
 def workload_c1(seed: int = 1):
     """50 ramped half-and-half trees, depths 2-6, F6, on a 64x64 grid in [-1, 1]."""
     pop = ramped_half_and_half(50, 2, 6, seed, F6, 2)
-    return pop, DomainSpec((64, 64)), [full_tree(4, seed + 1, F6, 2)]
+    return pop, DomainSpec((64, 64)), TargetSpec(4, seed + 1, F6, 2, 1)
 
 
 def workload_c3(seed: int = 6, n: int = 1000, side: int = 1024):
     """1000 individuals x 3 channel trees, ramped half-and-half depths 2-12, F18, 1024x1024."""
     pop = ramped_half_and_half(n, 2, 12, seed, F18, 2, n_channels=3)
-    targets = [full_tree(8, seed + 1 + c, F18, 2) for c in range(3)]
-    return pop, DomainSpec((side, side)), targets
+    return pop, DomainSpec((side, side)), TargetSpec(8, seed + 1, F18, 2, 3)
 
 
 def workload_c2(seed: int = 3, generations: int = None, n: int = 500, side: int = 256):
@@ -499,7 +533,7 @@ def workload_c2(seed: int = 3, generations: int = None, n: int = 500, side: int 
     for _ in range(generations):
         pop = breed(pop, rng, F18, 2, max_depth=10)
     pop.meta.update(kind="bred", generations=generations, seed=seed)
-    return pop, DomainSpec((side, side)), [full_tree(4, seed + 2, F18, 2)]
+    return pop, DomainSpec((side, side)), TargetSpec(4, seed + 2, F18, 2, 1)
 
 
 # The first generation of neutral breeding (seed 4 on the seed-3 start) at

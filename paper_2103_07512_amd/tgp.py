@@ -46,10 +46,22 @@ class DagStats(ctypes.Structure):
 
 class WorkStats(ctypes.Structure):
     _fields_ = [("credited_node_evals", ctypes.c_int64), ("executed_node_evals", ctypes.c_int64),
-                ("cached_nodes", ctypes.c_int64), ("cache_levels", ctypes.c_int64),
+                ("cached_nodes", ctypes.c_int64), ("stack_spills", ctypes.c_int64),
+                ("cache_levels", ctypes.c_int64),
                 ("programs", ctypes.c_int64), ("instructions", ctypes.c_int64),
-                ("algorithmic_valu", ctypes.c_double), ("cache_bytes_read", ctypes.c_int64),
+                ("algorithmic_valu", ctypes.c_double), ("executed_valu_fill", ctypes.c_double),
+                ("executed_valu_roots", ctypes.c_double), ("cache_bytes_read", ctypes.c_int64),
                 ("cache_bytes_written", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("build_dag_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
+                ("fill_ms", ctypes.c_double), ("interp_ms", ctypes.c_double),
+                ("finalize_ms", ctypes.c_double), ("interp_items", ctypes.c_int64),
+                ("cases_per_lane", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -79,6 +91,8 @@ SIGNATURES = [
     ("tgp_evaluate", I32, [P, P, P, P]),
     ("tgp_fitness", I32, [P, P, P, P, I32, P]),
     ("tgp_last_work", I32, [P, ctypes.POINTER(WorkStats)]),
+    ("tgp_ctx_set_timing", I32, [P, I32]),
+    ("tgp_last_timing", I32, [P, ctypes.POINTER(Timing)]),
 ]
 
 
@@ -138,6 +152,14 @@ class Context:
 
     def set_tuning(self, cases_per_lane: int = 0, tiles_per_item: int = 0):
         _check(lib().tgp_ctx_set_tuning(self.h, cases_per_lane, tiles_per_item), self.h)
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().tgp_ctx_set_timing(self.h, 1 if enable else 0), self.h)
+
+    def last_timing(self) -> dict:
+        t = Timing()
+        _check(lib().tgp_last_timing(self.h, ctypes.byref(t)), self.h)
+        return t.as_dict()
 
     def last_work(self) -> dict:
         w = WorkStats()

@@ -352,9 +352,9 @@ def test_fitness_closed_forms():
 
 
 def test_fitness_matches_numpy_sum():
-    pop, dom, tgt = pg.workload_c1()
+    pop, dom, spec = pg.workload_c1()
     v = oracle.evaluate(pop.tokens, pop.offsets, dom.shape)
-    T = oracle.render_target(tgt, dom.shape)
+    _, T = pg.pick_target(spec, oracle.target_renderer(dom.shape))
     f = oracle.fitness(v, T, pop.n_individuals)
     with np.errstate(all="ignore"):
         want = np.sqrt(np.mean((v - T.astype(float)) ** 2, axis=1))
