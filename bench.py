@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cases-per-lane", type=int, default=0)
     ap.add_argument("--tiles-per-item", type=int, default=0)
+    ap.add_argument("--no-reorder", action="store_true")
+    ap.add_argument("--cache-access-cost", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build evaluates a population on a single MI355X "
@@ -110,6 +112,7 @@ def main():
     pop, dspec, tspec, loss = load_workload(args.workload)
     ctx = tgp.Context(0)
     ctx.set_tuning(args.cases_per_lane, args.tiles_per_item)
+    ctx.set_plan(not args.no_reorder, args.cache_access_cost)
     dom = tgp.Domain(ctx, dspec.shape)
 
     def render(tree):

@@ -155,6 +155,16 @@ tgp_status tgp_ctx_set_cache_budget(tgp_ctx ctx, size_t bytes);
  * either; a fitness changes only through the order of its compensated sums. */
 tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles_per_item);
 
+/* Planning options.  reorder_children != 0 (default) evaluates the children
+ * of every node in decreasing order of the stack they need (Sethi and
+ * Ullman's order), which keeps programs within the register stack; 0 keeps
+ * left-to-right order and spills more subtrees to cache rows.
+ * cache_access_cost is the price, in VALU lane-slots per case, of one 4-byte
+ * cache-row access (default 20); a shared subtree is cached when recomputing
+ * it costs more than its accesses; a negative value caches only the
+ * subtrees needed to bound the stack.  Values never depend on either. */
+tgp_status tgp_ctx_set_plan(tgp_ctx ctx, int32_t reorder_children, double cache_access_cost);
+
 /* Test hook: keep only the low `bits` bits of the DAG builder's 64-bit key
  * hash (0 = all bits), forcing collisions so that the full-key comparison is
  * exercised.  Process-wide; the DAG produced must not change. */

@@ -17,6 +17,14 @@ operators) are compiled once as out-of-line functions that take and return
 the K-vectors by value in registers; the cheap operators are written into
 every block.
 
+The planner evaluates the children of a node in decreasing order of the
+stack they need (Sethi and Ullman's order), which keeps programs within a
+few slots.  An operator whose children were evaluated in another order than
+left to right reads its operands from the permuted slots: non-commutative
+binary operators have a reversed form (opcode REV_BASE + op) and the
+ternary operators one form per permutation (PERM_BASE + 6 t + p, with t the
+index in TERNARY and p the index of the evaluation order in PERMS).
+
 Run:  python gen_interp.py          writes interp_gen.inc beside this file
       python gen_interp.py --check  exits 1 when interp_gen.inc is stale
 """
@@ -36,6 +44,11 @@ FUNCS = [
     ("step", 23, 1), ("sstep", 24, 1), ("sstepp", 25, 1), ("len", 26, 2), ("lerp", 27, 3),
 ]
 FN_BASE = 8
+REV_BASE = 40
+PERM_BASE = 72
+REVERSIBLE = ("sub", "div", "pow", "mod")
+TERNARY = ("clip", "if", "lerp")
+PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
 # Operators compiled once, out of line.
 CALLED = {"sin", "cos", "tan", "exp", "log", "pow", "mod", "sstep", "sstepp", "len", "lerp"}
 DEPTHS = [8]
@@ -73,10 +86,14 @@ def body_for_depth(D):
     e("        const int32_t (&cidx)[K], FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
-    e("    uint2 ins;")
+    e("    // The next instruction is fetched one dispatch ahead so that the scalar")
+    e("    // load overlaps the current operator's vector work.")
+    e("    uint2 ins, nxt = *ip;")
+    e("    ++ip;")
     for S in range(D + 1):
         e(f"L{S}:")
-        e("    ins = *ip;")
+        e("    ins = nxt;")
+        e("    nxt = *ip;")
         e("    ++ip;")
         e("    switch (ins.x & 0xffu) {")
         if S < D:
@@ -96,12 +113,22 @@ def body_for_depth(D):
             e("    }")
         if S == 1:
             e("    case I_END: res = s0; return;")
+        variants = []
         for name, op, ar in FUNCS:
+            variants.append((FN_BASE + op, name, ar, tuple(range(ar))))
+            if name in REVERSIBLE:
+                variants.append((REV_BASE + op, name, ar, (1, 0)))
+            if name in TERNARY:
+                t = TERNARY.index(name)
+                for p, order in enumerate(PERMS):
+                    if p:
+                        variants.append((PERM_BASE + 6 * t + p, name, ar, order))
+        for c, name, ar, order in variants:
             if S < ar:
                 continue
-            c = FN_BASE + op
-            src = [f"s{S - ar + i}" for i in range(ar)]
             dst = S - ar
+            # child i was evaluated order.index(i)-th, so it sits in slot dst + that position
+            src = [f"s{dst + order.index(i)}" for i in range(ar)]
             if name in CALLED:
                 e(f"    case {c}: s{dst} = vcall_{name}<K>({', '.join(src)}); goto L{dst + 1};")
             else:

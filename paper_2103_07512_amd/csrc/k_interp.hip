@@ -5,7 +5,9 @@
 // fitness cases of the domain.  Here one wave runs one program; each of its
 // 64 lanes owns K cases of a tile of 64*K consecutive cases (case k of lane l
 // is tile_base + 64*k + l, so every load and store is coalesced), and a wave
-// walks tiles_per_stripe consecutive tiles.  The operand stack lives in
+// walks tiles_per_stripe consecutive tiles.  Work items are numbered program
+// by program (programs come longest first), so the longest work starts first
+// and the tail of a launch is made of short items.  The operand stack lives in
 // registers (see gen_interp.py), terminals come from per-axis coordinate
 // tables, constants from the instruction stream, and cached subtree values
 // from the HBM cache rows.
@@ -68,8 +70,8 @@ template <int K, int D, int MODE>
 __global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
     const int lane = threadIdx.x;
     const uint32_t item = blockIdx.x;
-    const uint32_t p = item % (uint32_t)a.n_progs;
-    const uint32_t stripe = item / (uint32_t)a.n_progs;
+    const uint32_t p = item / (uint32_t)a.n_stripes;
+    const uint32_t stripe = item - p * (uint32_t)a.n_stripes;
     const ProgDesc pd = a.progs[p];
     const uint2 *code = a.code + pd.code_off;
     const int32_t n = a.n_cases;

@@ -49,6 +49,8 @@ struct tgp_ctx_s {
     tgp_work_stats work{};
     int force_K = 0;  // 0 = automatic
     int force_tiles = 0;
+    int reorder = 1;                     // Sethi-Ullman child order
+    double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
     bool timing = false;
     bool ev_ready = false;
@@ -173,8 +175,8 @@ static const double kOpCost[TGP_NUM_OPS] = {
 };
 // Writing a cache row once and reading it back, in VALU-slot equivalents per
 // case: 4 bytes of HBM traffic at 8 TB/s against 256 CUs x 64 lanes x 2.4 GHz
-// of VALU issue is about 20 slots per access.
-static const double kCacheAccessCost = 20.0;
+// of VALU issue is about 20 slots per access (the default of
+// tgp_ctx_set_plan's cache_access_cost).
 
 // --------------------------------------------------------------- contexts
 extern "C" {
@@ -269,6 +271,13 @@ tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles
     if (tiles_per_item < 0) return fail(ctx, TGP_EINVAL, "tiles_per_item < 0");
     ctx->force_K = cases_per_lane;
     ctx->force_tiles = tiles_per_item;
+    return TGP_OK;
+}
+
+tgp_status tgp_ctx_set_plan(tgp_ctx ctx, int32_t reorder_children, double cache_access_cost) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    ctx->reorder = reorder_children != 0;
+    ctx->cache_access_cost = cache_access_cost;
     return TGP_OK;
 }
 
@@ -479,9 +488,13 @@ struct Planner {
     int D;
     size_t budget_slots;
     std::vector<uint8_t> cached;
+    std::vector<uint8_t> perm;  // evaluation order of each node's children (index in kPerms)
     std::vector<int32_t> slot, level;
     std::vector<double> cost;
     int64_t spills = 0;
+
+    bool reorder = true;
+    double access_cost = 20.0;
 
     Planner(const tgp_dag_s &dag, int stack, size_t slots) : d(dag), D(stack), budget_slots(slots) {}
 
@@ -498,30 +511,41 @@ struct Planner {
             for (int j = 0; j < arity(n); ++j) c += cost[d.kid[3 * n + j]];
             cost[n] = c;
         }
-        // Bottom-up: bound the register stack of every program.  A node
-        // whose children cannot be evaluated left to right within D slots
-        // gets its most demanding child's subtree spilled to a cache row.
+        // Bottom-up: bound the register stack of every program.  Children are
+        // evaluated in decreasing order of the stack they need (Sethi-Ullman);
+        // a node whose children still cannot be evaluated within D slots gets
+        // its most demanding child's subtree spilled to a cache row.
         std::vector<int32_t> need(U, 1);
+        perm.assign(U, 0);
         auto ref_need = [&](int32_t c) { return cached[c] ? 1 : need[c]; };
         size_t used = 0;
         for (int64_t n = 0; n < U; ++n) {
             const int a = arity(n);
             if (a == 0) continue;
             for (;;) {
-                int worst = 0, wj = -1;
-                for (int j = 0; j < a; ++j) {
-                    const int v = j + ref_need(d.kid[3 * n + j]);
-                    if (v > worst) {
-                        worst = v;
-                        wj = j;
+                int r[3] = {0, 0, 0};
+                for (int j = 0; j < a; ++j) r[j] = ref_need(d.kid[3 * n + j]);
+                // stable sort of child positions by need, largest first
+                int best_p = 0, best = 1 << 30;
+                const int n_orders = reorder ? (a == 3 ? 6 : (a == 2 ? 2 : 1)) : 1;
+                for (int p = 0; p < n_orders; ++p) {
+                    const uint8_t *o = a == 2 ? (p ? kPerms[2] : kPerms[0]) : kPerms[p];
+                    int v = 0;
+                    for (int i = 0; i < a; ++i) v = std::max(v, i + r[o[i]]);
+                    if (v < best) {
+                        best = v;
+                        best_p = a == 2 ? (p ? 2 : 0) : p;
                     }
                 }
-                if (worst <= D) {
-                    need[n] = worst;
+                if (best <= D) {
+                    need[n] = best;
+                    perm[n] = (uint8_t)best_p;
                     break;
                 }
-                const int32_t c = d.kid[3 * n + wj];
-                cached[c] = 1;
+                int wj = 0;
+                for (int j = 1; j < a; ++j)
+                    if (r[j] > r[wj]) wj = j;
+                cached[d.kid[3 * n + wj]] = 1;
                 ++used;
             }
         }
@@ -535,9 +559,9 @@ struct Planner {
         std::vector<double> uses(U, 0.0);
         for (int64_t n = 0; n < U; ++n) uses[n] = rootrefs[n];
         for (int64_t n = U - 1; n >= 0; --n) {
-            if (!cached[n] && arity(n) > 0 && uses[n] >= 2 && used < budget_slots) {
+            if (!cached[n] && access_cost >= 0 && arity(n) > 0 && uses[n] >= 2 && used < budget_slots) {
                 const double save = cost[n] * (uses[n] - 1);
-                const double pay = kCacheAccessCost * (uses[n] + 1);
+                const double pay = access_cost * (uses[n] + 1);
                 if (save > pay) {
                     cached[n] = 1;
                     ++used;
@@ -570,14 +594,14 @@ struct Planner {
     // Postfix program of node n (n itself is expanded even when cached).
     // Adds the cost-model slots of its instructions to *valu.
     void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads, double *valu) const {
-        std::vector<std::pair<int32_t, int32_t>> st;  // (node, next child)
+        std::vector<std::pair<int32_t, int32_t>> st;  // (node, children emitted)
         st.push_back({root, 0});
         while (!st.empty()) {
             auto &top = st.back();
             const int32_t n = top.first;
             const bool leafish = arity(n) == 0 || (n != root && cached[n]);
             if (!leafish && top.second < arity(n)) {
-                const int32_t c = d.kid[3 * n + top.second];
+                const int32_t c = d.kid[3 * n + kPerms[perm[n]][top.second]];
                 ++top.second;
                 st.push_back({c, 0});
                 continue;
@@ -596,8 +620,12 @@ struct Planner {
                 } else if (o == TGP_CONST) {
                     ins.x = I_CONST;
                     memcpy(&ins.y, &d.value[n], 4);
-                } else {
+                } else if (perm[n] == 0 || (kArity[o] == 2 && is_commutative(o))) {
                     ins.x = kFnBase + o;
+                } else if (kArity[o] == 2) {
+                    ins.x = kRevBase + o;
+                } else {
+                    ins.x = kPermBase + 6 * ternary_index(o) + perm[n];
                 }
             }
             code.push_back(ins);
@@ -654,6 +682,8 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     const int D = interp_max_stack();
     size_t budget_slots = (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
     Planner pl(*d, D, budget_slots);
+    pl.reorder = ctx->reorder != 0;
+    pl.access_cost = ctx->cache_access_cost;
     std::string why;
     tgp_status st = pl.decide(rootrefs, why);
     if (st != TGP_OK) return fail(ctx, st, "%s", why.c_str());
@@ -758,7 +788,9 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
 }
 
 // Work split: each work item is one program over tiles_per_stripe tiles of
-// 64*K cases; aim for enough items to fill 256 CUs several times over.
+// 64*K cases.  Items are kept short (at most 16 tiles) so that a launch of
+// programs of very different lengths balances over 256 CUs, but long enough
+// that the per-item setup (program descriptor, partial-sum write) stays small.
 static void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
                          int32_t *tiles_per) {
     const int64_t tile = 64 * (int64_t)K;
@@ -767,10 +799,9 @@ static void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int
     if (ctx->force_tiles > 0) {
         tps = ctx->force_tiles;
     } else {
-        const int64_t target_items = 65536;
-        int64_t want_stripes = (target_items + n_progs - 1) / std::max<int64_t>(n_progs, 1);
-        want_stripes = std::max<int64_t>(1, std::min(want_stripes, n_tiles));
-        tps = (n_tiles + want_stripes - 1) / want_stripes;
+        const int64_t target_items = 1 << 19;
+        const int64_t total = n_tiles * std::max<int64_t>(n_progs, 1);
+        tps = std::max<int64_t>(1, std::min<int64_t>(16, total / target_items));
     }
     tps = std::max<int64_t>(1, std::min(tps, n_tiles));
     *tiles_per = (int32_t)tps;

@@ -24,11 +24,27 @@ constexpr int kArity[TGP_NUM_OPS] = {
 // Interpreter instruction codes.  An instruction is a uint2: .x = code |
 // (aux << 8), .y = the FP32 bits of a constant.  aux is the cache slot of
 // I_CACHE.  Function opcodes are the public opcode plus kFnBase.
+// Operators whose children were evaluated out of left-to-right order (to
+// bound the stack, Sethi-Ullman order) use the permuted forms: kRevBase + op
+// for a reversed non-commutative binary operator, kPermBase + 6 t + p for
+// ternary operator t (clip, if, lerp) whose children were evaluated in the
+// order kPerms[p].
 enum : uint32_t {
     I_X = 0, I_Y = 1, I_Z = 2, I_CONST = 3, I_CACHE = 4, I_END = 5,
     kFnBase = 8,
-    I_NUM = kFnBase + TGP_NUM_OPS
+    kRevBase = 40,
+    kPermBase = 72,
 };
+
+constexpr uint8_t kPerms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+inline bool is_commutative(int op) {
+    return op == TGP_ADD || op == TGP_MULT || op == TGP_MIN || op == TGP_MAX || op == TGP_MDIST ||
+           op == TGP_LEN;
+}
+inline int ternary_index(int op) {
+    return op == TGP_CLIP ? 0 : (op == TGP_IF ? 1 : (op == TGP_LERP ? 2 : -1));
+}
 
 // One program of the interpreter: a postfix instruction stream that leaves a
 // single value per case.  dest is the cache slot (cache fill), the output row

@@ -80,6 +80,7 @@ SIGNATURES = [
     ("tgp_last_error", ctypes.c_char_p, [P]),
     ("tgp_ctx_set_cache_budget", I32, [P, ctypes.c_size_t]),
     ("tgp_ctx_set_tuning", I32, [P, I32, I32]),
+    ("tgp_ctx_set_plan", I32, [P, I32, ctypes.c_double]),
     ("tgp_debug_set_hash_bits", I32, [I32]),
     ("tgp_domain_create", I32, [P, I32, P, P, P, PP]),
     ("tgp_domain_destroy", None, [P]),
@@ -152,6 +153,9 @@ class Context:
 
     def set_tuning(self, cases_per_lane: int = 0, tiles_per_item: int = 0):
         _check(lib().tgp_ctx_set_tuning(self.h, cases_per_lane, tiles_per_item), self.h)
+
+    def set_plan(self, reorder_children: bool = True, cache_access_cost: float = 20.0):
+        _check(lib().tgp_ctx_set_plan(self.h, 1 if reorder_children else 0, cache_access_cost), self.h)
 
     def set_timing(self, enable: bool = True):
         _check(lib().tgp_ctx_set_timing(self.h, 1 if enable else 0), self.h)
