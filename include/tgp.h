@@ -256,6 +256,65 @@ typedef struct {
 tgp_status tgp_ctx_set_timing(tgp_ctx ctx, int32_t enable);
 tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out);
 
+/* ----------------------------------------------------- batched fitness */
+
+/* One fitness evaluation of a batch: the arguments of tgp_fitness. */
+typedef struct {
+    tgp_dag dag;
+    tgp_domain domain;
+    const float *target_dev; /* [n_channels][cases] on the device */
+    int32_t loss;            /* TGP_RMSE or TGP_MSE */
+    double *out_dev;         /* [n_individuals] on the device */
+} tgp_job;
+
+typedef struct tgp_batch_s *tgp_batch;
+
+/* A batch evaluates many populations of uneven sizes and domain shapes (for
+ * instance one generation of many GP runs) together: one persistent launch
+ * per cache-fill level, one persistent launch for every job's root programs
+ * fused with the error reduction, one finalize for every individual.  With
+ * use_graph != 0 the launches of a step are captured once as a HIP graph
+ * and replayed (recaptured only when the batch outgrows its buffers).
+ * Results equal tgp_fitness on each job up to the order of the compensated
+ * sums.  A batch belongs to its context and its thread. */
+tgp_status tgp_batch_create(tgp_ctx ctx, int32_t use_graph, tgp_batch *out);
+/* Evaluate n_jobs fitness jobs (asynchronous on the context stream; the host
+ * arrays are read during the call).  Blocks until the previous step of this
+ * batch has consumed its uploads. */
+tgp_status tgp_batch_run(tgp_batch batch, int32_t n_jobs, const tgp_job *jobs);
+void tgp_batch_destroy(tgp_batch batch);
+/* Launch form of later batched steps: persistent != 0 runs resident waves
+ * that draw work items from atomic counters (the default), 0 one wave per
+ * work item. */
+tgp_status tgp_ctx_set_batch_form(tgp_ctx ctx, int32_t persistent);
+/* tgp_batch_run on a graph-replayed batch that the context keeps. */
+tgp_status tgp_fitness_batch(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs);
+
+typedef struct {
+    int64_t jobs, pairs, items, levels;  /* last step: jobs, programs, work items, fill levels */
+    int64_t captures, replays;           /* graph captures and launches so far */
+    int64_t credited_node_evals;         /* last step: sum of DAG nodes x cases */
+    double pack_ms;                      /* last step: host planning and packing */
+    int32_t tiles_per_item, cases_per_lane;
+    int32_t persistent;                  /* launch form of the last step */
+} tgp_batch_stats;
+tgp_status tgp_batch_stats_get(tgp_batch batch, tgp_batch_stats *out);
+
+/* Autotuner: times cases-per-lane K in {2, 4} x the cap on tiles per work
+ * item in {4, 16} x the batched launch form (persistent waves drawing items
+ * from partitioned atomic counters, or one wave per item) on the given jobs
+ * (a warm-up and a timed batched run each) and installs the fastest in ctx.
+ * With cache_path != NULL the choice is appended to that file (one JSON
+ * object per line, keyed by the workload's size class) and reused without
+ * timing for a later workload of the same class. */
+typedef struct {
+    int32_t cases_per_lane, tiles_cap, persistent;
+    int32_t candidates, from_cache;
+    double best_ms;
+} tgp_tune_result;
+tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const char *cache_path,
+                        tgp_tune_result *out);
+
 #ifdef __cplusplus
 }
 #endif

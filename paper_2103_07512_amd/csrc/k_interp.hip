@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "ops_device.h"
 #include "tgp_internal.h"
 
@@ -66,14 +68,10 @@ __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const
     run_prog_d8<K>(ip, xv, yv, zv, cache, n_cases, cidx, res);
 }
 
+// One work item: program `code` over tiles_per_stripe tiles of one stripe.
 template <int K, int D, int MODE>
-__global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
-    const int lane = threadIdx.x;
-    const uint32_t item = blockIdx.x;
-    const uint32_t p = item / (uint32_t)a.n_stripes;
-    const uint32_t stripe = item - p * (uint32_t)a.n_stripes;
-    const ProgDesc pd = a.progs[p];
-    const uint2 *code = a.code + pd.code_off;
+__device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, int32_t dest, int32_t chan,
+                                         uint32_t stripe, int lane) {
     const int32_t n = a.n_cases;
     const int64_t tile_cases = 64 * K;
     const int64_t first = (int64_t)stripe * a.tiles_per_stripe * tile_cases;
@@ -114,12 +112,12 @@ __global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
         FV<K> res;
         run_prog<K, D>(code, xv, yv, zv, a.cache, n, cidx, res);
         if constexpr (MODE == MODE_STORE) {
-            float *row = a.out + (size_t)pd.dest * (size_t)n;
+            float *row = a.out + (size_t)dest * (size_t)n;
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (valid[k]) row[cidx[k]] = res.v[k];
         } else {
-            const float *trow = a.target + (size_t)pd.chan * (size_t)n;
+            const float *trow = a.target + (size_t)chan * (size_t)n;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float e = res.v[k] - trow[cidx[k]];
@@ -135,18 +133,119 @@ __global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
             kahan_merge(ks, kc, s2, c2);
         }
         if (lane == 0)
-            a.partial[(size_t)pd.dest * (size_t)a.n_stripes + stripe] = make_float2(ks, kc);
+            a.partial[(size_t)dest * (size_t)a.n_stripes + stripe] = make_float2(ks, kc);
     }
+}
+
+template <int K, int D, int MODE>
+__global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
+    const uint32_t item = blockIdx.x;
+    const uint32_t p = item / (uint32_t)a.job.n_stripes;
+    const uint32_t stripe = item - p * (uint32_t)a.job.n_stripes;
+    const ProgDesc pd = a.progs[p];
+    run_item<K, D, MODE>(a.job, a.job.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
+}
+
+// Batched interpreter, two launch forms over the work items of group g
+// (items ordered longest program first; pair p owns items item_first[p] ..
+// item_first[p + 1] - 1, one per stripe).
+//
+// Persistent form: a fixed grid of resident waves.  The items are dealt into
+// 8 interleaved partitions (item i belongs to partition i mod 8), each with
+// its own atomic counter, so that claims from the chip's 8 XCDs rarely meet
+// on one address; a wave starts on partition blockIdx mod 8, claims CH items
+// per atomic, and when its partition is exhausted it helps the others.  The
+// loops are bounded: every counter only grows, and a wave leaves a
+// partition once its counter passes the partition's size.
+// Descriptors are read through the constant address space: the loads are
+// then known to be invariant, so the compiler keeps them scalar and may load
+// them again instead of spilling them across the interpreter.
+template <typename T>
+__device__ __forceinline__ T load_const(const T *p) {
+    T r;
+    __builtin_memcpy(&r, (const __attribute__((address_space(4))) void *)(p), sizeof(T));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t load_const_u32(const uint32_t *p) {
+    typedef const __attribute__((address_space(4))) uint32_t cword;
+    return *(cword *)(p);
+}
+
+constexpr uint32_t kParts = 8;
+constexpr uint32_t kChunk = 4;
+
+__device__ __forceinline__ uint32_t find_pair(const uint32_t *__restrict__ item_first, uint32_t lo,
+                                              uint32_t hi, uint32_t item) {
+    // the last pair p in [lo, hi) with item_first[p] <= item
+    while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (load_const_u32(item_first + m) <= item) lo = m;
+        else hi = m;
+    }
+    return lo;
+}
+
+template <int K, int D, int MODE>
+__global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
+                                              const PairDesc *__restrict__ pairs,
+                                              const uint32_t *__restrict__ item_first,
+                                              const GroupDesc *__restrict__ groups, int32_t g,
+                                              uint32_t *__restrict__ counters) {
+    const GroupDesc gd = load_const(groups + g);
+    const uint32_t n_items = gd.item_end - gd.item_begin;
+    const uint32_t first_part = blockIdx.x % kParts;
+    for (uint32_t q = 0; q < kParts; ++q) {
+        const uint32_t part = (first_part + q) % kParts;
+        const uint32_t n_part = n_items > part ? (n_items - part + kParts - 1) / kParts : 0;
+        uint32_t lo = gd.pair_begin;
+        for (;;) {
+            uint32_t k0 = 0;
+            if (threadIdx.x == 0) k0 = atomicAdd(&counters[g * kParts + part], kChunk);
+            k0 = __builtin_amdgcn_readfirstlane(k0);
+            if (k0 >= n_part) break;
+            const uint32_t k1 = k0 + kChunk < n_part ? k0 + kChunk : n_part;
+            for (uint32_t k = k0; k < k1; ++k) {
+                const uint32_t item = gd.item_begin + part + kParts * k;
+                lo = find_pair(item_first, lo, gd.pair_end, item);
+                const PairDesc pd = load_const(pairs + lo);
+                const JobDesc jd = load_const(jobs + pd.job);
+                const uint32_t stripe = item - load_const_u32(item_first + lo);
+                run_item<K, D, MODE>(jd, jd.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
+            }
+        }
+    }
+}
+
+// Direct form: one wave per item (grid = the group's item count, or more);
+// the hardware dispatcher hands out the waves in item order.
+template <int K, int D, int MODE>
+__global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__ jobs,
+                                                     const PairDesc *__restrict__ pairs,
+                                                     const uint32_t *__restrict__ item_first,
+                                                     const GroupDesc *__restrict__ groups, int32_t g) {
+    const GroupDesc gd = load_const(groups + g);
+    const uint32_t item = gd.item_begin + blockIdx.x;
+    if (item >= gd.item_end) return;
+    const uint32_t lo = find_pair(item_first, gd.pair_begin, gd.pair_end, item);
+    const PairDesc pd = load_const(pairs + lo);
+    const JobDesc jd = load_const(jobs + pd.job);
+    run_item<K, D, MODE>(jd, jd.code + pd.code_off, pd.dest, pd.chan, item - load_const_u32(item_first + lo),
+                         threadIdx.x);
+}
+
+__global__ void k_reset(uint32_t *counters, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counters[i] = 0u;
 }
 
 // One block per individual: FP64 sum of the (sum - compensation) pairs of its
 // channels' partial rows, stripes in order, then a fixed-shape tree in LDS.
-__global__ __launch_bounds__(256) void k_finalize(const float2 *partial, const int32_t *ind_rows,
-                                                  int32_t n_ch, int32_t n_stripes, double n_terms,
-                                                  int32_t loss, double *out) {
+__device__ __forceinline__ void finalize_one(const float2 *partial, const int32_t *ind_rows,
+                                             int32_t n_ch, int32_t n_stripes, double n_terms,
+                                             int32_t loss, double *out, int i) {
     __shared__ double red[256];
     __shared__ int bad[256];
-    const int i = blockIdx.x;
     const int tid = threadIdx.x;
     double acc = 0.0;
     int nonfinite = 0;
@@ -180,16 +279,59 @@ __global__ __launch_bounds__(256) void k_finalize(const float2 *partial, const i
     }
 }
 
+__global__ __launch_bounds__(256) void k_finalize(const float2 *partial, const int32_t *ind_rows,
+                                                  int32_t n_ch, int32_t n_stripes, double n_terms,
+                                                  int32_t loss, double *out) {
+    finalize_one(partial, ind_rows, n_ch, n_stripes, n_terms, loss, out, blockIdx.x);
+}
+
+// Batched finalize: block b is global individual b; blocks past the batch's
+// individuals return at once (the grid is sized for the batch's capacity).
+__global__ __launch_bounds__(256) void k_finalize_batch(const FinJob *jobs, const int32_t *n_jobs,
+                                                        const uint32_t *n_ind) {
+    const uint32_t b = blockIdx.x;
+    if (b >= *n_ind) return;
+    int32_t lo = 0, hi = *n_jobs;  // last job with ind_begin <= b
+    while (hi - lo > 1) {
+        const int32_t m = (lo + hi) >> 1;
+        if (jobs[m].ind_begin <= b) lo = m;
+        else hi = m;
+    }
+    const FinJob f = jobs[lo];
+    finalize_one(f.partial, f.ind_rows, f.n_ch, f.n_stripes, f.n_terms, f.loss, f.out,
+                 (int)(b - f.ind_begin));
+}
+
 // ------------------------------------------------------------- launchers
 template <int K, int D>
 static hipError_t launch_kd(bool store, const InterpArgs &a, hipStream_t s) {
-    const uint32_t items = (uint32_t)a.n_progs * (uint32_t)a.n_stripes;
+    const uint32_t items = (uint32_t)a.n_progs * (uint32_t)a.job.n_stripes;
     if (items == 0) return hipSuccess;
     if (store)
         hipLaunchKernelGGL((k_interp<K, D, MODE_STORE>), dim3(items), dim3(64), 0, s, a);
     else
         hipLaunchKernelGGL((k_interp<K, D, MODE_REDUCE>), dim3(items), dim3(64), 0, s, a);
     return hipGetLastError();
+}
+
+template <int K, int D>
+static const void *batch_fn(bool store, bool persistent) {
+    if (persistent)
+        return store ? (const void *)k_batch<K, D, MODE_STORE> : (const void *)k_batch<K, D, MODE_REDUCE>;
+    return store ? (const void *)k_batch_direct<K, D, MODE_STORE>
+                 : (const void *)k_batch_direct<K, D, MODE_REDUCE>;
+}
+
+template <int K, int D>
+static int grid_bd(bool store) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (store)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_STORE>, 64, 0);
+    else
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_REDUCE>, 64, 0);
+    return std::max(1, per_cu) * std::max(1, cus);
 }
 
 #ifndef TGP_VARIANTS
@@ -212,12 +354,42 @@ hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStrea
     return hipErrorInvalidValue;
 }
 
+const void *batch_kernel(int K, int D, bool store, bool persistent) {
+#define X(k, d) if (K == k && D == d) return batch_fn<k, d>(store, persistent);
+    TGP_VARIANTS(X)
+#undef X
+    return nullptr;
+}
+
+int batch_grid(int K, int D, bool store) {
+#define X(k, d) if (K == k && D == d) return grid_bd<k, d>(store);
+    TGP_VARIANTS(X)
+#undef X
+    return 0;
+}
+
+hipError_t launch_reset(uint32_t *counters, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, counters, n);
+    return hipGetLastError();
+}
+
+const void *reset_kernel() { return (const void *)k_reset; }
+const void *finalize_batch_kernel() { return (const void *)k_finalize_batch; }
+uint32_t batch_parts() { return kParts; }
+
 hipError_t launch_finalize(const float2 *partial, const int32_t *ind_rows, int32_t n_ind,
                            int32_t n_ch, int32_t n_stripes, double n_terms, int32_t loss,
                            double *out, hipStream_t s) {
     if (n_ind == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(n_ind), dim3(256), 0, s, partial, ind_rows, n_ch, n_stripes,
                        n_terms, loss, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
+                                 int32_t grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_batch, dim3(grid), dim3(256), 0, s, jobs, n_jobs, n_ind);
     return hipGetLastError();
 }
 

@@ -27,107 +27,16 @@
 #include <unordered_map>
 #include <vector>
 
-#include "tgp_internal.h"
+#include "runtime_internal.h"
 
 namespace tgp {
 extern uint32_t g_debug_hash_bits;
 }
 
-using namespace tgp;
-
-// ------------------------------------------------------------------ objects
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-};
-
-struct tgp_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    size_t cache_budget = 0;
-    std::string err;
-    tgp_work_stats work{};
-    int force_K = 0;  // 0 = automatic
-    int force_tiles = 0;
-    int reorder = 1;                     // Sethi-Ullman child order
-    double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
-    DevBuf partial, cache;
-    bool timing = false;
-    bool ev_ready = false;
-    hipEvent_t ev[6] = {};  // fill begin/end, interp begin/end, finalize begin/end
-    bool fill_recorded = false;
-    tgp_timing times{};
-};
-
-static double now_ms() {
-    return std::chrono::duration<double, std::milli>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
-
-static void record(tgp_ctx ctx, int i) {
-    if (ctx->timing && ctx->ev_ready) hipEventRecord(ctx->ev[i], ctx->stream);
-}
-
-struct tgp_domain_s {
-    tgp_ctx ctx = nullptr;
-    int32_t ndim = 0;
-    int64_t shape[3] = {1, 1, 1};
-    int64_t stride[3] = {1, 1, 1};
-    int64_t cases = 0;
-    float *coord[3] = {nullptr, nullptr, nullptr};
-};
-
-// A compiled evaluation plan of one DAG for one case count.
-struct Plan {
-    int64_t cases = -1;
-    int32_t n_slots = 0;
-    int64_t n_spills = 0;               // cached only to bound the register stack
-    std::vector<int32_t> level_first;   // fill programs of level l: [level_first[l], level_first[l+1])
-    int32_t n_fill = 0;
-    int32_t n_reduce = 0;               // programs for (root, channel)
-    int32_t n_store = 0;                // programs for distinct roots
-    std::vector<int32_t> store_rows;    // for each root r: the store program's dest row, or -1
-    std::vector<int32_t> dup_src;       // for each root r: row r copies row dup_src[r] (-1: none)
-    uint2 *code_dev = nullptr;
-    ProgDesc *fill_dev = nullptr, *reduce_dev = nullptr, *store_dev = nullptr;
-    int32_t *ind_rows_dev = nullptr;
-    int64_t instructions = 0;
-    double exec_per_case = 0;           // instructions run per case, fitness form
-    double valu_dag_per_case = 0;       // cost-model slots of each DAG node once
-    double valu_fill_per_case = 0;      // cost-model slots run by the fill programs
-    double valu_roots_per_case = 0;     // cost-model slots run by the reduce programs
-    int64_t cache_reads_per_case = 0;   // I_CACHE instructions executed, fitness form
-    void release() {
-        hipFree(code_dev);
-        hipFree(fill_dev);
-        hipFree(reduce_dev);
-        hipFree(store_dev);
-        hipFree(ind_rows_dev);
-        code_dev = nullptr;
-        fill_dev = reduce_dev = store_dev = nullptr;
-        ind_rows_dev = nullptr;
-        cases = -1;
-    }
-};
-
-struct tgp_dag_s {
-    tgp_ctx ctx = nullptr;
-    int32_t n_ind = 0, n_ch = 0;
-    tgp_dag_stats stats{};
-    DagDevice dev;
-    // host copies
-    std::vector<int32_t> op;   // op | var << 8
-    std::vector<float> value;
-    std::vector<int32_t> kid;  // [U][3]
-    std::vector<int32_t> roots, mult, indeg, height;
-    Plan plan;
-};
-
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
 
-static tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
+tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -138,32 +47,11 @@ static tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
     return st;
 }
 
-#define HCHK(ctx, x)                                                                           \
-    do {                                                                                       \
-        hipError_t _e = (x);                                                                   \
-        if (_e != hipSuccess)                                                                  \
-            return fail(ctx, TGP_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
-    } while (0)
-
-static hipError_t ensure(DevBuf &b, size_t bytes) {
-    if (b.cap >= bytes && b.p) return hipSuccess;
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        if (e != hipSuccess) return e;
-        b.p = nullptr;
-        b.cap = 0;
-    }
-    size_t want = std::max<size_t>(bytes, 256);
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e == hipSuccess) b.cap = want;
-    return e;
-}
-
 // --------------------------------------------------------------- cost model
 // VALU issue slots per case of each operator in the fused interpreter on
 // gfx950 (counted from the compiled instruction sequences; terminals cost
 // the register move that places them on the stack).
-static const double kOpCost[TGP_NUM_OPS] = {
+const double kOpCost[TGP_NUM_OPS] = {
     1,  1,           // var const
     1,  1,  1, 11,   // add sub mult div
     21, 21, 46,      // sin cos tan
@@ -210,6 +98,7 @@ void tgp_ctx_destroy(tgp_ctx ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
+    tgp_batch_destroy(ctx->batch);
     hipFree(ctx->partial.p);
     hipFree(ctx->cache.p);
     if (ctx->ev_ready)
@@ -271,6 +160,7 @@ tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles
     if (tiles_per_item < 0) return fail(ctx, TGP_EINVAL, "tiles_per_item < 0");
     ctx->force_K = cases_per_lane;
     ctx->force_tiles = tiles_per_item;
+    ctx->tile_cap = 0;
     return TGP_OK;
 }
 
@@ -639,7 +529,7 @@ struct Planner {
 
 static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases);
 
-static tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
+tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     const double t0 = now_ms();
     tgp_status st = d->plan.cases == cases ? TGP_OK : build_plan_impl(ctx, d, cases);
     ctx->times.plan_ms = now_ms() - t0;
@@ -778,11 +668,15 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     if (e == hipSuccess) e = up((void **)&P.reduce_dev, reduce.data(), sizeof(ProgDesc) * reduce.size());
     if (e == hipSuccess) e = up((void **)&P.store_dev, store.data(), sizeof(ProgDesc) * store.size());
     if (e == hipSuccess) e = up((void **)&P.ind_rows_dev, ind_rows.data(), sizeof(int32_t) * ind_rows.size());
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // host vectors die here
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         P.release();
         return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
     }
+    P.code_host = std::move(code);
+    P.fill_host = std::move(fill);
+    P.reduce_host = std::move(reduce);
+    P.ind_rows_host = std::move(ind_rows);
     P.cases = cases;
     return TGP_OK;
 }
@@ -791,7 +685,7 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
 // 64*K cases.  Items are kept short (at most 16 tiles) so that a launch of
 // programs of very different lengths balances over 256 CUs, but long enough
 // that the per-item setup (program descriptor, partial-sum write) stays small.
-static void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
+void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
                          int32_t *tiles_per) {
     const int64_t tile = 64 * (int64_t)K;
     const int64_t n_tiles = (cases + tile - 1) / tile;
@@ -801,29 +695,35 @@ static void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int
     } else {
         const int64_t target_items = 1 << 19;
         const int64_t total = n_tiles * std::max<int64_t>(n_progs, 1);
-        tps = std::max<int64_t>(1, std::min<int64_t>(16, total / target_items));
+        const int64_t cap = ctx->tile_cap > 0 ? ctx->tile_cap : 16;
+        tps = std::max<int64_t>(1, std::min<int64_t>(cap, total / target_items));
     }
     tps = std::max<int64_t>(1, std::min(tps, n_tiles));
     *tiles_per = (int32_t)tps;
     *stripes = (int32_t)((n_tiles + tps - 1) / tps);
 }
 
-static int choose_K(tgp_ctx ctx, int64_t cases) {
+int choose_K(tgp_ctx ctx, int64_t cases) {
     if (ctx->force_K) return ctx->force_K;
     return cases >= 64 * 4 * 4 ? 4 : 2;
 }
 
+void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache) {
+    memset(&j, 0, sizeof j);
+    j.code = code;
+    j.n_cases = (int32_t)dom->cases;
+    j.ndim = dom->ndim;
+    for (int k = 0; k < 3; ++k) {
+        j.shape[k] = (int32_t)dom->shape[k];
+        j.stride[k] = (int32_t)dom->stride[k];
+        j.coord[k] = dom->coord[k] ? dom->coord[k] : dom->coord[0];
+    }
+    j.cache = cache;
+}
+
 static void fill_args(InterpArgs &a, tgp_domain dom, const Plan &P, const float *cache) {
     memset(&a, 0, sizeof a);
-    a.code = P.code_dev;
-    a.n_cases = (int32_t)dom->cases;
-    a.ndim = dom->ndim;
-    for (int k = 0; k < 3; ++k) {
-        a.shape[k] = (int32_t)dom->shape[k];
-        a.stride[k] = (int32_t)dom->stride[k];
-        a.coord[k] = dom->coord[k] ? dom->coord[k] : dom->coord[0];
-    }
-    a.cache = cache;
+    fill_job(a.job, dom, P.code_dev, cache);
 }
 
 static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float **cache_out) {
@@ -844,15 +744,15 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
         fill_args(a, dom, P, cache);
         a.progs = P.fill_dev + b;
         a.n_progs = e - b;
-        choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
-        a.out = cache;
+        choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
+        a.job.out = cache;
         HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
     }
     record(ctx, 1);
     return TGP_OK;
 }
 
-static tgp_status check_eval_args(tgp_ctx ctx, tgp_dag d, tgp_domain dom) {
+tgp_status check_eval_args(tgp_ctx ctx, tgp_dag d, tgp_domain dom) {
     if (!ctx || !d || !dom) return fail(ctx, TGP_EINVAL, "NULL argument");
     if (d->ctx != ctx || dom->ctx != ctx) return fail(ctx, TGP_EINVAL, "handles of another context");
     if (d->stats.max_var >= dom->ndim)
@@ -900,20 +800,20 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     fill_args(a, dom, P, cache);
     a.progs = P.reduce_dev;
     a.n_progs = P.n_reduce;
-    choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
-    a.target = target_dev;
-    HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.n_stripes));
-    a.partial = (float2 *)ctx->partial.p;
+    choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
+    a.job.target = target_dev;
+    HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.job.n_stripes));
+    a.job.partial = (float2 *)ctx->partial.p;
     record(ctx, 2);
     HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream));
     record(ctx, 3);
     record(ctx, 4);
-    HCHK(ctx, launch_finalize(a.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.n_stripes,
+    HCHK(ctx, launch_finalize(a.job.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.job.n_stripes,
                               (double)d->n_ch * (double)dom->cases, loss, out_dev, ctx->stream));
     record(ctx, 5);
-    ctx->times.interp_items = (int64_t)a.n_progs * a.n_stripes;
+    ctx->times.interp_items = (int64_t)a.n_progs * a.job.n_stripes;
     ctx->times.cases_per_lane = K;
-    ctx->times.tiles_per_item = a.tiles_per_stripe;
+    ctx->times.tiles_per_item = a.job.tiles_per_stripe;
     record_work(ctx, d, dom, true);
     return TGP_OK;
 }
@@ -935,16 +835,16 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     fill_args(a, dom, P, cache);
     a.progs = P.store_dev;
     a.n_progs = P.n_store;
-    choose_split(ctx, a.n_progs, dom->cases, K, &a.n_stripes, &a.tiles_per_stripe);
-    a.out = out_dev;
+    choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
+    a.job.out = out_dev;
     record(ctx, 2);
     HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
     record(ctx, 3);
     record(ctx, 4);
     record(ctx, 5);
-    ctx->times.interp_items = (int64_t)a.n_progs * a.n_stripes;
+    ctx->times.interp_items = (int64_t)a.n_progs * a.job.n_stripes;
     ctx->times.cases_per_lane = K;
-    ctx->times.tiles_per_item = a.tiles_per_stripe;
+    ctx->times.tiles_per_item = a.job.tiles_per_stripe;
     const size_t row = sizeof(float) * (size_t)dom->cases;
     for (int64_t r = 0; r < d->stats.n_roots; ++r)
         if (P.dup_src[r] >= 0)

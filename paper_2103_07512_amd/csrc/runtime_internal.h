@@ -1,0 +1,143 @@
+// runtime_internal.h -- host objects of libtgp shared by the translation
+// units of the runtime (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "tgp_internal.h"
+
+using namespace tgp;
+
+// ------------------------------------------------------------------ objects
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct tgp_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t cache_budget = 0;
+    std::string err;
+    tgp_work_stats work{};
+    int force_K = 0;  // 0 = automatic
+    int force_tiles = 0;
+    int tile_cap = 0;  // cap on automatic tiles per item (0 = 16)
+    int batch_persistent = 1;  // batched launches: persistent waves (1) or one wave per item
+    tgp_batch batch = nullptr;  // kept by tgp_fitness_batch
+    int reorder = 1;                     // Sethi-Ullman child order
+    double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
+    DevBuf partial, cache;
+    bool timing = false;
+    bool ev_ready = false;
+    hipEvent_t ev[6] = {};  // fill begin/end, interp begin/end, finalize begin/end
+    bool fill_recorded = false;
+    tgp_timing times{};
+};
+
+inline double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+inline void record(tgp_ctx ctx, int i) {
+    if (ctx->timing && ctx->ev_ready) hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+struct tgp_domain_s {
+    tgp_ctx ctx = nullptr;
+    int32_t ndim = 0;
+    int64_t shape[3] = {1, 1, 1};
+    int64_t stride[3] = {1, 1, 1};
+    int64_t cases = 0;
+    float *coord[3] = {nullptr, nullptr, nullptr};
+};
+
+// A compiled evaluation plan of one DAG for one case count.
+struct Plan {
+    int64_t cases = -1;
+    int32_t n_slots = 0;
+    int64_t n_spills = 0;               // cached only to bound the register stack
+    std::vector<int32_t> level_first;   // fill programs of level l: [level_first[l], level_first[l+1])
+    int32_t n_fill = 0;
+    int32_t n_reduce = 0;               // programs for (root, channel)
+    int32_t n_store = 0;                // programs for distinct roots
+    std::vector<int32_t> store_rows;    // for each root r: the store program's dest row, or -1
+    std::vector<int32_t> dup_src;       // for each root r: row r copies row dup_src[r] (-1: none)
+    uint2 *code_dev = nullptr;
+    ProgDesc *fill_dev = nullptr, *reduce_dev = nullptr, *store_dev = nullptr;
+    int32_t *ind_rows_dev = nullptr;
+    // host copies (the batched path packs them into its own buffers)
+    std::vector<uint2> code_host;
+    std::vector<ProgDesc> fill_host, reduce_host;
+    std::vector<int32_t> ind_rows_host;
+    int64_t instructions = 0;
+    double exec_per_case = 0;           // instructions run per case, fitness form
+    double valu_dag_per_case = 0;       // cost-model slots of each DAG node once
+    double valu_fill_per_case = 0;      // cost-model slots run by the fill programs
+    double valu_roots_per_case = 0;     // cost-model slots run by the reduce programs
+    int64_t cache_reads_per_case = 0;   // I_CACHE instructions executed, fitness form
+    void release() {
+        hipFree(code_dev);
+        hipFree(fill_dev);
+        hipFree(reduce_dev);
+        hipFree(store_dev);
+        hipFree(ind_rows_dev);
+        code_dev = nullptr;
+        fill_dev = reduce_dev = store_dev = nullptr;
+        ind_rows_dev = nullptr;
+        cases = -1;
+    }
+};
+
+struct tgp_dag_s {
+    tgp_ctx ctx = nullptr;
+    int32_t n_ind = 0, n_ch = 0;
+    tgp_dag_stats stats{};
+    DagDevice dev;
+    // host copies
+    std::vector<int32_t> op;   // op | var << 8
+    std::vector<float> value;
+    std::vector<int32_t> kid;  // [U][3]
+    std::vector<int32_t> roots, mult, indeg, height;
+    Plan plan;
+};
+
+// ------------------------------------------------------------------ errors
+tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...);
+
+#define HCHK(ctx, x)                                                                           \
+    do {                                                                                       \
+        hipError_t _e = (x);                                                                   \
+        if (_e != hipSuccess)                                                                  \
+            return fail(ctx, TGP_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
+    } while (0)
+
+inline hipError_t ensure(DevBuf &b, size_t bytes) {
+    if (b.cap >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e == hipSuccess) b.cap = want;
+    return e;
+}
+
+
+// --------------------------------------------------------------- shared helpers
+extern const double kOpCost[TGP_NUM_OPS];
+tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases);
+void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
+                  int32_t *tiles_per);
+int choose_K(tgp_ctx ctx, int64_t cases);
+void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache);
+tgp_status check_eval_args(tgp_ctx ctx, tgp_dag d, tgp_domain dom);

@@ -56,13 +56,12 @@ struct ProgDesc {
     int32_t chan;
 };
 
-// Launch arguments of the interpreter kernel.
-struct InterpArgs {
-    const uint2 *code;           // all instructions, padded by one I_END
-    const ProgDesc *progs;       // n_progs programs
-    int32_t n_progs;
-    int32_t n_stripes;           // items = n_progs * n_stripes
-    int32_t tiles_per_stripe;    // tiles of 64*K cases per item
+// Everything a work item needs to know about the domain and the buffers of
+// the evaluation it belongs to.
+struct JobDesc {
+    const uint2 *code;           // all instructions of the job, padded by one I_END
+    int32_t n_stripes;           // work items per program
+    int32_t tiles_per_stripe;    // tiles of 64*K cases per work item
     int32_t n_cases;
     int32_t ndim;
     int32_t shape[3];
@@ -74,6 +73,41 @@ struct InterpArgs {
     float2 *partial;             // REDUCE: [dest][n_stripes] (sum, compensation)
 };
 
+// Launch arguments of the plain (one program set, one domain) interpreter:
+// work item i is program i / n_stripes, stripe i % n_stripes.
+struct InterpArgs {
+    JobDesc job;
+    const ProgDesc *progs;
+    int32_t n_progs;
+};
+
+// Batched evaluation: a pair is one program of one job; its work items are
+// item_first[p] .. item_first[p + 1] - 1 (one per stripe).  A group is a
+// contiguous range of pairs evaluated by one launch.
+struct PairDesc {
+    int32_t job;
+    uint32_t code_off;
+    int32_t dest;
+    int32_t chan;
+};
+
+struct GroupDesc {
+    uint32_t pair_begin, pair_end;
+    uint32_t item_begin, item_end;
+};
+
+// Finalize of one job in a batch.
+struct FinJob {
+    const float2 *partial;
+    const int32_t *ind_rows;
+    double *out;
+    double n_terms;
+    int32_t n_ch;
+    int32_t n_stripes;
+    int32_t loss;
+    uint32_t ind_begin;          // first global individual index of the job
+};
+
 // Instantiated kernel variants (cases per lane K, stack registers D).
 struct Variant {
     int K;
@@ -81,6 +115,17 @@ struct Variant {
 };
 
 hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s);
+// Batched interpreter kernels (for graph nodes): the persistent form takes
+// (jobs, pairs, item_first, groups, g, counters[groups x batch_parts()]),
+// the direct form (jobs, pairs, item_first, groups, g) with one wave per item.
+const void *batch_kernel(int K, int D, bool store, bool persistent);
+int batch_grid(int K, int D, bool store);  // resident waves of the persistent form
+uint32_t batch_parts();
+const void *reset_kernel();           // (uint32_t *counters, int32_t n)
+const void *finalize_batch_kernel();  // (const FinJob *, const int32_t *n_jobs, const uint32_t *n_ind)
+hipError_t launch_reset(uint32_t *counters, int32_t n, hipStream_t s);
+hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
+                                 int32_t grid, hipStream_t s);
 bool interp_variant_exists(int K, int D);
 int interp_max_stack();   // largest D compiled
 

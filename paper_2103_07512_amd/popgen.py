@@ -536,6 +536,32 @@ def workload_c2(seed: int = 3, generations: int = None, n: int = 500, side: int 
     return pop, DomainSpec((side, side)), TargetSpec(4, seed + 2, F18, 2, 1)
 
 
+def workload_c4(seed: int = 10, n_pops: int = 64):
+    """64 independent populations for one batched launch.
+
+    Population p: size round(exp(U[ln 20, ln 2000])), maximum depth
+    U{4..14}, ramped half-and-half from depth 2 over the 18-operator set; with
+    probability 1/8 a 3-D 64^3 domain (terminals gain z), otherwise a 2-D grid
+    of side 2^U{5..10}; target a full depth-4 tree.
+    Returns a list of (population, DomainSpec, TargetSpec).
+    """
+    rng = Rng(seed)
+    out = []
+    for p in range(n_pops):
+        size = int(round(math.exp(math.log(20) + rng.uniform() * (math.log(2000) - math.log(20)))))
+        d_max = 4 + rng.below(11)
+        three_d = rng.below(8) == 0
+        if three_d:
+            ndim, shape = 3, (64, 64, 64)
+        else:
+            side = 1 << (5 + rng.below(6))
+            ndim, shape = 2, (side, side)
+        pop_seed = seed * 1000 + 2 * p
+        pop = ramped_half_and_half(size, 2, d_max, pop_seed, F18, ndim)
+        out.append((pop, DomainSpec(shape), TargetSpec(4, pop_seed + 1, F18, ndim, 1)))
+    return out
+
+
 # The first generation of neutral breeding (seed 4 on the seed-3 start) at
 # which the 500-tree population shares 30-60% of its internal nodes; chosen
 # once and checked by a CPU test.

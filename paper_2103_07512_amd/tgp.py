@@ -67,6 +67,32 @@ class Timing(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("dag", ctypes.c_void_p), ("domain", ctypes.c_void_p), ("target_dev", ctypes.c_void_p),
+                ("loss", ctypes.c_int32), ("out_dev", ctypes.c_void_p)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("jobs", ctypes.c_int64), ("pairs", ctypes.c_int64), ("items", ctypes.c_int64),
+                ("levels", ctypes.c_int64), ("captures", ctypes.c_int64), ("replays", ctypes.c_int64),
+                ("credited_node_evals", ctypes.c_int64), ("pack_ms", ctypes.c_double),
+                ("tiles_per_item", ctypes.c_int32), ("cases_per_lane", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("cases_per_lane", ctypes.c_int32), ("tiles_cap", ctypes.c_int32),
+                ("persistent", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("best_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _lib = None
 P = ctypes.c_void_p
 PP = ctypes.POINTER(ctypes.c_void_p)
@@ -94,6 +120,13 @@ SIGNATURES = [
     ("tgp_last_work", I32, [P, ctypes.POINTER(WorkStats)]),
     ("tgp_ctx_set_timing", I32, [P, I32]),
     ("tgp_last_timing", I32, [P, ctypes.POINTER(Timing)]),
+    ("tgp_batch_create", I32, [P, I32, PP]),
+    ("tgp_batch_run", I32, [P, I32, ctypes.POINTER(Job)]),
+    ("tgp_batch_destroy", None, [P]),
+    ("tgp_fitness_batch", I32, [P, I32, ctypes.POINTER(Job)]),
+    ("tgp_ctx_set_batch_form", I32, [P, I32]),
+    ("tgp_batch_stats_get", I32, [P, ctypes.POINTER(BatchStats)]),
+    ("tgp_autotune", I32, [P, I32, ctypes.POINTER(Job), ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
 ]
 
 
@@ -156,6 +189,9 @@ class Context:
 
     def set_plan(self, reorder_children: bool = True, cache_access_cost: float = 20.0):
         _check(lib().tgp_ctx_set_plan(self.h, 1 if reorder_children else 0, cache_access_cost), self.h)
+
+    def set_batch_form(self, persistent: bool = True):
+        _check(lib().tgp_ctx_set_batch_form(self.h, 1 if persistent else 0), self.h)
 
     def set_timing(self, enable: bool = True):
         _check(lib().tgp_ctx_set_timing(self.h, 1 if enable else 0), self.h)
@@ -279,3 +315,59 @@ def fitness(ctx: Context, dag: Dag, dom: Domain, target, loss: int, out):
     _check(lib().tgp_fitness(ctx.h, dag.h, dom.h, ctypes.c_void_p(target.data_ptr()), loss,
                              ctypes.c_void_p(out.data_ptr())), ctx.h)
     return out
+
+
+def _jobs(jobs):
+    """jobs: iterable of (dag, domain, target tensor, loss, out tensor)."""
+    jobs = list(jobs)
+    arr = (Job * max(1, len(jobs)))()
+    for i, (dag, dom, target, loss, out) in enumerate(jobs):
+        arr[i].dag = dag.h
+        arr[i].domain = dom.h
+        arr[i].target_dev = target.data_ptr()
+        arr[i].loss = loss
+        arr[i].out_dev = out.data_ptr()
+    return arr, len(jobs)
+
+
+class Batch:
+    """tgp_batch: persistent, graph-replayed fitness of many populations."""
+
+    def __init__(self, ctx: Context, use_graph: bool = True):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().tgp_batch_create(ctx.h, 1 if use_graph else 0, ctypes.byref(h)), ctx.h)
+        self.h = h
+
+    def run(self, jobs):
+        arr, n = _jobs(jobs)
+        _check(lib().tgp_batch_run(self.h, n, arr), self.ctx.h)
+
+    def stats(self) -> dict:
+        st = BatchStats()
+        _check(lib().tgp_batch_stats_get(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().tgp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fitness_batch(ctx: Context, jobs):
+    arr, n = _jobs(jobs)
+    _check(lib().tgp_fitness_batch(ctx.h, n, arr), ctx.h)
+
+
+def autotune(ctx: Context, jobs, cache_path=None) -> dict:
+    arr, n = _jobs(jobs)
+    r = TuneResult()
+    _check(lib().tgp_autotune(ctx.h, n, arr, cache_path.encode() if cache_path else None,
+                              ctypes.byref(r)), ctx.h)
+    return r.as_dict()
