@@ -118,6 +118,49 @@ __global__ void k_level_scatter(const int32_t *height, int64_t T, int32_t *curso
     }
 }
 
+// The same two passes with the counters privatised in LDS (most tokens are
+// leaves, so the global forms above serialise on one address).  A block
+// takes kLvlPer tokens per thread and touches each global counter once.
+// Used when the tallest tree has at most kLvlBins levels; the order of the
+// tokens inside a level is not significant.
+constexpr int kLvlBins = 512;
+constexpr int kLvlPer = 16;
+
+__global__ void __launch_bounds__(256) k_level_hist_lds(const int32_t *height, int64_t T, int32_t H,
+                                                        int32_t *cnt) {
+    __shared__ int32_t c[kLvlBins];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) c[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kLvlPer + threadIdx.x;
+    for (int j = 0; j < kLvlPer; ++j) {
+        const int64_t t = base + (int64_t)j * blockDim.x;
+        if (t < T) atomicAdd(&c[height[t]], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < H; i += blockDim.x)
+        if (c[i]) atomicAdd(&cnt[i], c[i]);
+}
+
+__global__ void __launch_bounds__(256) k_level_scatter_lds(const int32_t *height, int64_t T, int32_t H,
+                                                           int32_t *cursor, int32_t *list) {
+    __shared__ int32_t c[kLvlBins];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) c[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kLvlPer + threadIdx.x;
+    int32_t h[kLvlPer], r[kLvlPer];
+    for (int j = 0; j < kLvlPer; ++j) {
+        const int64_t t = base + (int64_t)j * blockDim.x;
+        h[j] = t < T ? height[t] : -1;
+        r[j] = h[j] >= 0 ? atomicAdd(&c[h[j]], 1) : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < H; i += blockDim.x)
+        c[i] = c[i] ? atomicAdd(&cursor[i], c[i]) : 0;
+    __syncthreads();
+    for (int j = 0; j < kLvlPer; ++j)
+        if (h[j] >= 0) list[c[h[j]] + r[j]] = (int32_t)(base + (int64_t)j * blockDim.x);
+}
+
 // Key of token t: k0 = opcode | axis << 8 (the axis only for a variable);
 // k1 = constant bits or first child's canonical id; k2, k3 = further
 // children; unused fields are all-ones.
@@ -308,14 +351,8 @@ __global__ void k_emit_roots(const int32_t *root_tok, const int32_t *canon, cons
 
 static inline dim3 grid_for(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
-void dag_device_free(DagDevice *d) {
-    hipFree(d->node_op);
-    hipFree(d->node_value);
-    hipFree(d->node_kid);
-    hipFree(d->node_height);
-    hipFree(d->roots);
-    hipFree(d->mult);
-    hipFree(d->indeg);
+void dag_device_free(DagDevice *d, DevicePool &pool) {
+    pool.release(d->blob);
     *d = DagDevice{};
 }
 
@@ -332,8 +369,8 @@ void dag_device_free(DagDevice *d) {
 uint32_t g_debug_hash_bits = 0;  // set by tests to force hash collisions
 
 DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
-                                int64_t T, DagDevice *dev, hipStream_t s, char *err,
-                                size_t errlen) {
+                                int64_t T, DagDevice *dev, DevicePool &pool, hipStream_t s,
+                                char *err, size_t errlen) {
     DagBuildResult res{};
     res.status = TGP_OK;
     res.bad_tree = -1;
@@ -352,11 +389,11 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
     dev->R = R;
     while (cap < (uint64_t)(2 * T)) cap <<= 1;
 
-    DCHK(hipMalloc((void **)&kid, sizeof(int32_t) * 3 * T));
-    DCHK(hipMalloc((void **)&height, sizeof(int32_t) * T));
-    DCHK(hipMalloc((void **)&stk, sizeof(int32_t) * T));
-    DCHK(hipMalloc((void **)&root_tok, sizeof(int32_t) * R));
-    DCHK(hipMalloc((void **)&st, sizeof(BuildStatus)));
+    DCHK(pool.alloc((void **)&kid, sizeof(int32_t) * 3 * T));
+    DCHK(pool.alloc((void **)&height, sizeof(int32_t) * T));
+    DCHK(pool.alloc((void **)&stk, sizeof(int32_t) * T));
+    DCHK(pool.alloc((void **)&root_tok, sizeof(int32_t) * R));
+    DCHK(pool.alloc((void **)&st, sizeof(BuildStatus)));
     hs.first_error = ~0ull;
     hs.max_height = 0;
     hs.max_var = -1;
@@ -384,9 +421,14 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
     res.tree_internal = hs.n_internal;
     {
         const int64_t H = hs.max_height + 1;
-        DCHK(hipMalloc((void **)&cnt, sizeof(int32_t) * H));
+        DCHK(pool.alloc((void **)&cnt, sizeof(int32_t) * H));
         DCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * H, s));
-        hipLaunchKernelGGL(k_level_hist, grid_for(T), dim3(256), 0, s, height, T, cnt);
+        const bool lds = H <= kLvlBins;
+        if (lds)
+            hipLaunchKernelGGL(k_level_hist_lds, grid_for(T, 256 * kLvlPer), dim3(256), 0, s, height, T,
+                               (int32_t)H, cnt);
+        else
+            hipLaunchKernelGGL(k_level_hist, grid_for(T), dim3(256), 0, s, height, T, cnt);
         DCHK(hipGetLastError());
         hcnt.resize(H);
         DCHK(hipMemcpyAsync(hcnt.data(), cnt, sizeof(int32_t) * H, hipMemcpyDeviceToHost, s));
@@ -394,11 +436,15 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
         std::vector<int32_t> start(H + 1, 0);
         for (int64_t h = 0; h < H; ++h) start[h + 1] = start[h] + hcnt[h];
         DCHK(hipMemcpyAsync(cnt, start.data(), sizeof(int32_t) * H, hipMemcpyHostToDevice, s));
-        DCHK(hipMalloc((void **)&list, sizeof(int32_t) * T));
-        hipLaunchKernelGGL(k_level_scatter, grid_for(T), dim3(256), 0, s, height, T, cnt, list);
+        DCHK(pool.alloc((void **)&list, sizeof(int32_t) * T));
+        if (lds)
+            hipLaunchKernelGGL(k_level_scatter_lds, grid_for(T, 256 * kLvlPer), dim3(256), 0, s, height,
+                               T, (int32_t)H, cnt, list);
+        else
+            hipLaunchKernelGGL(k_level_scatter, grid_for(T), dim3(256), 0, s, height, T, cnt, list);
         DCHK(hipGetLastError());
-        DCHK(hipMalloc((void **)&canon, sizeof(int32_t) * T));
-        DCHK(hipMalloc((void **)&table, sizeof(int32_t) * cap));
+        DCHK(pool.alloc((void **)&canon, sizeof(int32_t) * T));
+        DCHK(pool.alloc((void **)&table, sizeof(int32_t) * cap));
         DCHK(hipMemsetAsync(table, 0xff, sizeof(int32_t) * cap, s));
         for (int64_t h = 0; h < H; ++h) {
             const int32_t n = hcnt[h];
@@ -410,8 +456,8 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
                                canon, table, (uint64_t)(cap - 1), g_debug_hash_bits);
         }
         DCHK(hipGetLastError());
-        DCHK(hipMalloc((void **)&flag, sizeof(int32_t) * T));
-        DCHK(hipMalloc((void **)&pos, sizeof(int32_t) * T));
+        DCHK(pool.alloc((void **)&flag, sizeof(int32_t) * T));
+        DCHK(pool.alloc((void **)&pos, sizeof(int32_t) * T));
         hipLaunchKernelGGL(k_flags, grid_for(T), dim3(256), 0, s, canon, T, flag);
         DCHK(exclusive_scan(flag, pos, T, s));
         int32_t last[2] = {0, 0};
@@ -421,15 +467,17 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
         U = (int64_t)last[0] + last[1];
         res.U = U;
         dev->U = U;
-        DCHK(hipMalloc((void **)&dev->node_op, sizeof(int32_t) * U));
-        DCHK(hipMalloc((void **)&dev->node_value, sizeof(float) * U));
-        DCHK(hipMalloc((void **)&dev->node_kid, sizeof(int32_t) * 3 * U));
-        DCHK(hipMalloc((void **)&dev->node_height, sizeof(int32_t) * U));
-        DCHK(hipMalloc((void **)&dev->roots, sizeof(int32_t) * R));
-        DCHK(hipMalloc((void **)&dev->mult, sizeof(int32_t) * U));
-        DCHK(hipMalloc((void **)&dev->indeg, sizeof(int32_t) * U));
-        DCHK(hipMemsetAsync(dev->mult, 0, sizeof(int32_t) * U, s));
-        DCHK(hipMemsetAsync(dev->indeg, 0, sizeof(int32_t) * U, s));
+        // One block, in the order of DagDevice::blob_bytes: op, value, kid[3],
+        // height, mult, indeg (U each), roots (R).
+        DCHK(pool.alloc((void **)&dev->blob, DagDevice::blob_bytes(U, R)));
+        dev->node_op = dev->blob;
+        dev->node_value = reinterpret_cast<float *>(dev->blob + U);
+        dev->node_kid = dev->blob + 2 * U;
+        dev->node_height = dev->blob + 5 * U;
+        dev->mult = dev->blob + 6 * U;
+        dev->indeg = dev->blob + 7 * U;
+        dev->roots = dev->blob + 8 * U;
+        DCHK(hipMemsetAsync(dev->mult, 0, sizeof(int32_t) * 2 * U, s));
         hipLaunchKernelGGL(k_emit_nodes, grid_for(T), dim3(256), 0, s, tok, canon, pos, height, T,
                            dev->node_op, dev->node_value, dev->node_height);
         hipLaunchKernelGGL(k_emit_edges, grid_for(T), dim3(256), 0, s, canon, pos, kid, T,
@@ -437,21 +485,21 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
         hipLaunchKernelGGL(k_emit_roots, grid_for(R), dim3(256), 0, s, root_tok, canon, pos, R,
                            dev->roots);
         DCHK(hipGetLastError());
-        DCHK(hipStreamSynchronize(s));
     }
 done:
-    hipFree(kid);
-    hipFree(height);
-    hipFree(stk);
-    hipFree(root_tok);
-    hipFree(st);
-    hipFree(cnt);
-    hipFree(list);
-    hipFree(canon);
-    hipFree(table);
-    hipFree(flag);
-    hipFree(pos);
-    if (res.status != TGP_OK) dag_device_free(dev);
+    hipStreamSynchronize(s);  // every kernel that used the scratch has finished
+    pool.release(kid);
+    pool.release(height);
+    pool.release(stk);
+    pool.release(root_tok);
+    pool.release(st);
+    pool.release(cnt);
+    pool.release(list);
+    pool.release(canon);
+    pool.release(table);
+    pool.release(flag);
+    pool.release(pos);
+    if (res.status != TGP_OK) dag_device_free(dev, pool);
     return res;
 }
 

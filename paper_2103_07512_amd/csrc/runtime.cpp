@@ -36,6 +36,36 @@ extern uint32_t g_debug_hash_bits;
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
 
+hipError_t ctx_pinned(tgp_ctx ctx, size_t bytes, void **out) {
+    if (ctx->pin_pending) {
+        hipError_t e = hipEventSynchronize(ctx->pin_ev);
+        if (e != hipSuccess) return e;
+        ctx->pin_pending = false;
+    }
+    if (ctx->pin_cap < bytes) {
+        if (ctx->pin) hipHostFree(ctx->pin);
+        ctx->pin = nullptr;
+        ctx->pin_cap = 0;
+        size_t want = 1 << 20;
+        while (want < bytes) want <<= 1;
+        hipError_t e = hipHostMalloc(&ctx->pin, want, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        ctx->pin_cap = want;
+    }
+    *out = ctx->pin;
+    return hipSuccess;
+}
+
+hipError_t ctx_pinned_enqueued(tgp_ctx ctx) {
+    if (!ctx->pin_ev) {
+        hipError_t e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(ctx->pin_ev, ctx->stream);
+    if (e == hipSuccess) ctx->pin_pending = true;
+    return e;
+}
+
 tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -101,6 +131,9 @@ void tgp_ctx_destroy(tgp_ctx ctx) {
     tgp_batch_destroy(ctx->batch);
     hipFree(ctx->partial.p);
     hipFree(ctx->cache.p);
+    ctx->pool.drain();
+    if (ctx->pin) hipHostFree(ctx->pin);
+    if (ctx->pin_ev) hipEventDestroy(ctx->pin_ev);
     if (ctx->ev_ready)
         for (auto &e : ctx->ev) hipEventDestroy(e);
     delete ctx;
@@ -252,13 +285,16 @@ tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
                     return fail(ctx, TGP_EINVAL, "offsets decrease at tree %lld", (long long)r);
             T = pop->offsets[R];
             if (T > 0x7fffffffLL) return fail(ctx, TGP_EINVAL, "more than 2^31-1 tokens");
-            HCHK(ctx, hipMalloc((void **)&off_own, sizeof(int64_t) * (R + 1)));
-            HCHK(ctx, hipMalloc((void **)&tok_own, sizeof(tgp_token) * std::max<int64_t>(T, 1)));
-            HCHK(ctx, hipMemcpyAsync(off_own, pop->offsets, sizeof(int64_t) * (R + 1),
-                                     hipMemcpyHostToDevice, ctx->stream));
-            if (T)
-                HCHK(ctx, hipMemcpyAsync(tok_own, pop->tokens, sizeof(tgp_token) * T,
-                                         hipMemcpyHostToDevice, ctx->stream));
+            // offsets and tokens in one block, through the pinned staging
+            const size_t ob = sizeof(int64_t) * (R + 1), tb = sizeof(tgp_token) * T;
+            void *stage = nullptr;
+            HCHK(ctx, ctx->pool.alloc((void **)&off_own, ob + tb));
+            tok_own = reinterpret_cast<tgp_token *>(off_own + R + 1);
+            HCHK(ctx, ctx_pinned(ctx, ob + tb, &stage));
+            memcpy(stage, pop->offsets, ob);
+            if (T) memcpy((char *)stage + ob, pop->tokens, tb);
+            HCHK(ctx, hipMemcpyAsync(off_own, stage, ob + tb, hipMemcpyHostToDevice, ctx->stream));
+            HCHK(ctx, ctx_pinned_enqueued(ctx));
             off_dev = off_own;
             tok_dev = tok_own;
         } else {
@@ -283,9 +319,9 @@ tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
     d->stats.max_var = -1;
     if (R > 0) {
         char msg[256] = "";
-        DagBuildResult br = build_dag_device(tok_dev, off_dev, R, T, &d->dev, ctx->stream, msg, sizeof msg);
-        hipFree(off_own);
-        hipFree(tok_own);
+        DagBuildResult br =
+            build_dag_device(tok_dev, off_dev, R, T, &d->dev, ctx->pool, ctx->stream, msg, sizeof msg);
+        ctx->pool.release(off_own);  // build_dag_device has synchronised the stream
         if (br.status != TGP_OK) {
             delete d;
             return fail(ctx, (tgp_status)br.status, "build_dag: %s", msg);
@@ -298,18 +334,23 @@ tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
         d->roots.resize(R);
         d->mult.resize(U);
         d->indeg.resize(U);
-        hipError_t e = hipSuccess;
-        auto cp = [&](void *dst, const void *src, size_t n) {
-            if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, ctx->stream);
-        };
-        cp(d->op.data(), d->dev.node_op, sizeof(int32_t) * U);
-        cp(d->value.data(), d->dev.node_value, sizeof(float) * U);
-        cp(d->kid.data(), d->dev.node_kid, sizeof(int32_t) * 3 * U);
-        cp(d->height.data(), d->dev.node_height, sizeof(int32_t) * U);
-        cp(d->roots.data(), d->dev.roots, sizeof(int32_t) * R);
-        cp(d->mult.data(), d->dev.mult, sizeof(int32_t) * U);
-        cp(d->indeg.data(), d->dev.indeg, sizeof(int32_t) * U);
+        // one readback of the whole DAG block through the pinned staging
+        const size_t bytes = DagDevice::blob_bytes(U, R);
+        void *stage = nullptr;
+        hipError_t e = ctx_pinned(ctx, bytes, &stage);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(stage, d->dev.blob, bytes, hipMemcpyDeviceToHost, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess) {
+            const int32_t *h = static_cast<const int32_t *>(stage);
+            memcpy(d->op.data(), h, sizeof(int32_t) * U);
+            memcpy(d->value.data(), h + U, sizeof(float) * U);
+            memcpy(d->kid.data(), h + 2 * U, sizeof(int32_t) * 3 * U);
+            memcpy(d->height.data(), h + 5 * U, sizeof(int32_t) * U);
+            memcpy(d->mult.data(), h + 6 * U, sizeof(int32_t) * U);
+            memcpy(d->indeg.data(), h + 7 * U, sizeof(int32_t) * U);
+            memcpy(d->roots.data(), h + 8 * U, sizeof(int32_t) * R);
+        }
         if (e != hipSuccess) {
             tgp_dag_destroy(d);
             return fail(ctx, TGP_EHIP, "DAG readback: %s", hipGetErrorString(e));
@@ -362,9 +403,11 @@ tgp_status tgp_dag_export(tgp_dag dag, tgp_token *nodes, int32_t *children, int3
 
 void tgp_dag_destroy(tgp_dag dag) {
     if (!dag) return;
-    if (dag->ctx) hipSetDevice(dag->ctx->device);
-    dag->plan.release();
-    dag_device_free(&dag->dev);
+    tgp_ctx ctx = dag->ctx;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);  // no queued kernel reads the blocks any more
+    dag->plan.release(ctx->pool);
+    dag_device_free(&dag->dev, ctx->pool);
     delete dag;
 }
 
@@ -538,7 +581,10 @@ tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
 
 static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     Plan &P = d->plan;
-    P.release();
+    if (P.blob) {
+        HCHK(ctx, hipStreamSynchronize(ctx->stream));
+        P.release(ctx->pool);
+    }
     const int64_t U = d->stats.dag_nodes, R = d->stats.n_roots;
     const int n_ch = d->n_ch;
     // distinct programs
@@ -658,21 +704,37 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.n_reduce = (int32_t)reduce.size();
     P.n_store = (int32_t)store.size();
 
-    auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
-        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
-        if (e == hipSuccess && bytes) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream);
-        return e;
-    };
-    hipError_t e = up((void **)&P.code_dev, code.data(), sizeof(uint2) * code.size());
-    if (e == hipSuccess) e = up((void **)&P.fill_dev, fill.data(), sizeof(ProgDesc) * fill.size());
-    if (e == hipSuccess) e = up((void **)&P.reduce_dev, reduce.data(), sizeof(ProgDesc) * reduce.size());
-    if (e == hipSuccess) e = up((void **)&P.store_dev, store.data(), sizeof(ProgDesc) * store.size());
-    if (e == hipSuccess) e = up((void **)&P.ind_rows_dev, ind_rows.data(), sizeof(int32_t) * ind_rows.size());
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    // One device block (256-byte aligned parts) filled by one copy from the
+    // pinned staging; later launches on the stream see it in order.
+    const size_t part[5] = {sizeof(uint2) * code.size(), sizeof(ProgDesc) * fill.size(),
+                            sizeof(ProgDesc) * reduce.size(), sizeof(ProgDesc) * store.size(),
+                            sizeof(int32_t) * ind_rows.size()};
+    const void *src[5] = {code.data(), fill.data(), reduce.data(), store.data(), ind_rows.data()};
+    size_t off[5], total = 0;
+    for (int i = 0; i < 5; ++i) {
+        off[i] = total;
+        total += (part[i] + 255) & ~(size_t)255;
+    }
+    void *stage = nullptr;
+    hipError_t e = ctx->pool.alloc(&P.blob, total);
+    if (e == hipSuccess) e = ctx_pinned(ctx, total, &stage);
+    if (e == hipSuccess) {
+        for (int i = 0; i < 5; ++i)
+            if (part[i]) memcpy((char *)stage + off[i], src[i], part[i]);
+        e = hipMemcpyAsync(P.blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
+    }
+    if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
     if (e != hipSuccess) {
-        P.release();
+        hipStreamSynchronize(ctx->stream);
+        P.release(ctx->pool);
         return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
     }
+    char *b = static_cast<char *>(P.blob);
+    P.code_dev = reinterpret_cast<uint2 *>(b + off[0]);
+    P.fill_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
+    P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
+    P.store_dev = reinterpret_cast<ProgDesc *>(b + off[3]);
+    P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[4]);
     P.code_host = std::move(code);
     P.fill_host = std::move(fill);
     P.reduce_host = std::move(reduce);

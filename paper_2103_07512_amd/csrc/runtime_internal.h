@@ -32,6 +32,11 @@ struct tgp_ctx_s {
     int reorder = 1;                     // Sethi-Ullman child order
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
+    DevicePool pool;             // DAG, plan and population blocks
+    void *pin = nullptr;         // pinned staging for uploads and readbacks
+    size_t pin_cap = 0;
+    hipEvent_t pin_ev = nullptr; // recorded after the last copy out of `pin`
+    bool pin_pending = false;
     bool timing = false;
     bool ev_ready = false;
     hipEvent_t ev[6] = {};  // fill begin/end, interp begin/end, finalize begin/end
@@ -69,6 +74,7 @@ struct Plan {
     int32_t n_store = 0;                // programs for distinct roots
     std::vector<int32_t> store_rows;    // for each root r: the store program's dest row, or -1
     std::vector<int32_t> dup_src;       // for each root r: row r copies row dup_src[r] (-1: none)
+    void *blob = nullptr;               // one pool block holding the arrays below
     uint2 *code_dev = nullptr;
     ProgDesc *fill_dev = nullptr, *reduce_dev = nullptr, *store_dev = nullptr;
     int32_t *ind_rows_dev = nullptr;
@@ -82,12 +88,10 @@ struct Plan {
     double valu_fill_per_case = 0;      // cost-model slots run by the fill programs
     double valu_roots_per_case = 0;     // cost-model slots run by the reduce programs
     int64_t cache_reads_per_case = 0;   // I_CACHE instructions executed, fitness form
-    void release() {
-        hipFree(code_dev);
-        hipFree(fill_dev);
-        hipFree(reduce_dev);
-        hipFree(store_dev);
-        hipFree(ind_rows_dev);
+    // The caller guarantees that no queued kernel still reads the block.
+    void release(DevicePool &pool) {
+        pool.release(blob);
+        blob = nullptr;
         code_dev = nullptr;
         fill_dev = reduce_dev = store_dev = nullptr;
         ind_rows_dev = nullptr;
@@ -132,6 +136,12 @@ inline hipError_t ensure(DevBuf &b, size_t bytes) {
     return e;
 }
 
+
+// Pinned staging of at least `bytes`, free to be overwritten (waits for the
+// copy that last read it).
+hipError_t ctx_pinned(tgp_ctx ctx, size_t bytes, void **out);
+// Marks the staging as read by copies enqueued on the context stream.
+hipError_t ctx_pinned_enqueued(tgp_ctx ctx);
 
 // --------------------------------------------------------------- shared helpers
 extern const double kOpCost[TGP_NUM_OPS];

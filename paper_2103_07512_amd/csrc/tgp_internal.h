@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <unordered_map>
+#include <vector>
+
 #include "../../include/tgp.h"
 
 namespace tgp {
@@ -134,9 +137,50 @@ hipError_t launch_finalize(const float2 *partial, const int32_t *ind_rows, int32
                            int32_t n_ch, int32_t n_stripes, double n_terms, int32_t loss,
                            double *out, hipStream_t s);
 
+// A caching allocator of device memory: blocks are kept by power-of-two size
+// class and handed out again instead of being freed, so that building DAGs
+// and plans step after step does not pay hipMalloc/hipFree (hipFree also
+// waits for the whole device).  Blocks are only released to the pool once
+// the work that used them is known to be complete (the callers synchronise
+// their stream first).  Owned by one context, used by one thread.
+struct DevicePool {
+    std::vector<std::vector<void *>> free_;
+    std::unordered_map<void *, int> cls_;
+    static int class_of(size_t bytes) {
+        int c = 8;  // 256 bytes minimum
+        while (((size_t)1 << c) < bytes) ++c;
+        return c;
+    }
+    hipError_t alloc(void **p, size_t bytes) {
+        const int c = class_of(bytes);
+        if ((int)free_.size() <= c) free_.resize(c + 1);
+        if (!free_[c].empty()) {
+            *p = free_[c].back();
+            free_[c].pop_back();
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc(p, (size_t)1 << c);
+        if (e == hipSuccess) cls_[*p] = c;
+        return e;
+    }
+    void release(void *p) {
+        if (!p) return;
+        auto it = cls_.find(p);
+        if (it == cls_.end()) return;
+        free_[it->second].push_back(p);
+    }
+    // Frees every block ever handed out (the owner is going away).
+    void drain() {
+        for (auto &kv : cls_) hipFree(kv.first);
+        cls_.clear();
+        free_.clear();
+    }
+};
+
 // DAG construction kernels (k_dag.hip).
 struct DagDevice {
     int64_t T = 0, R = 0, U = 0;
+    int32_t *blob = nullptr;         // one pool block holding every array below
     int32_t *node_op = nullptr;      // packed per node: op | var << 8
     float *node_value = nullptr;
     int32_t *node_kid = nullptr;     // [U][3]
@@ -144,6 +188,7 @@ struct DagDevice {
     int32_t *roots = nullptr;        // [R]
     int32_t *mult = nullptr;         // [U]
     int32_t *indeg = nullptr;        // [U]
+    static size_t blob_bytes(int64_t U, int64_t R) { return sizeof(int32_t) * (8 * U + R); }
 };
 
 struct DagBuildResult {
@@ -152,10 +197,12 @@ struct DagBuildResult {
     int64_t T, U, max_height, max_stack, max_var, tree_internal;
 };
 
-// Builds the DAG of R trees given device tokens/offsets; allocates dev
-// arrays (hipMalloc) that the caller frees with dag_device_free.
+// Builds the DAG of R trees given device tokens/offsets; allocates the dev
+// arrays from the pool (returned with dag_device_free once the stream has
+// passed every use).
 DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
-                                int64_t T, DagDevice *dev, hipStream_t s, char *err, size_t errlen);
-void dag_device_free(DagDevice *dev);
+                                int64_t T, DagDevice *dev, DevicePool &pool, hipStream_t s,
+                                char *err, size_t errlen);
+void dag_device_free(DagDevice *dev, DevicePool &pool);
 
 }  // namespace tgp
