@@ -315,6 +315,82 @@ typedef struct {
 tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const char *cache_path,
                         tgp_tune_result *out);
 
+/* ------------------------------------------------------------- serving */
+
+/* A server evaluates the per-generation populations of many concurrent GP
+ * runs (TensorGP's evaluation step of Sec. 3.1, once per generation of each
+ * run) with continuous batching: a request loop admits each submitted
+ * population when a slot and device memory for its cached subtrees are free,
+ * and every batched step on the GPU carries one slab of cases of every
+ * admitted request, so a request that arrives while others run joins at the
+ * next step instead of waiting for them to finish.  Subtree results are
+ * kept in a device cache across requests, keyed by the subtree's structure
+ * and the domain, and reused by later generations (the effect noted in
+ * Sec. 4.2), with least-recently-used eviction when space is needed.
+ *
+ * A request's fitness values do not depend on what else is being served: its
+ * slabs, work split and summation order are chosen from the request alone,
+ * and a resident subtree holds the same FP32 values the request would
+ * compute.  The server has two threads of its own and its own HIP streams on
+ * the context's device; submit, wait, ticket_info, stats and end_run may be
+ * called from any thread.  The context passed in is only read at creation
+ * (device, tuning) and stays free for its owner to use. */
+typedef struct tgp_server_s *tgp_server;
+
+/* cache_budget_bytes: device memory reserved for resident subtree results (0:
+ * a quarter of the device's memory); max_active: requests evaluated at once
+ * (0: 16).  Blocks while the cache memory is allocated. */
+tgp_status tgp_server_create(tgp_ctx ctx, size_t cache_budget_bytes, int32_t max_active, tgp_server *out);
+/* Waits for the admitted requests to finish; requests not admitted yet end
+ * with TGP_EBUSY.  Domains and targets of finished requests are not touched
+ * afterwards. */
+void tgp_server_destroy(tgp_server server);
+/* Work per slab, in instructions x cases (default 2^33): a request over more
+ * cases than this is evaluated in slabs of consecutive cases, one per step. */
+tgp_status tgp_server_set_slab_work(tgp_server server, double node_evals);
+
+/* Queue one fitness evaluation (does not block on the GPU).  pop must be in
+ * host memory (copied during the call); domain and target_dev (device,
+ * [n_channels][cases]) must stay valid until the request ends; out (host,
+ * [n_individuals] doubles) receives the fitness values before tgp_server_wait
+ * returns TGP_OK.  run_id groups the requests of one GP run (for
+ * tgp_server_end_run).  *ticket identifies the request. */
+tgp_status tgp_server_submit(tgp_server server, int64_t run_id, const tgp_population *pop,
+                             tgp_domain domain, const float *target_dev, int32_t loss, double *out,
+                             int64_t *ticket);
+/* Blocks until the request ends or timeout_us passes (timeout_us < 0: no
+ * limit).  Returns TGP_OK (out written), TGP_EBUSY on time-out, or the
+ * request's own error (TGP_EPARSE, TGP_EOP, TGP_ESHAPE, TGP_ENOMEM when its
+ * cached subtrees can never fit the cache budget, TGP_EHIP). */
+tgp_status tgp_server_wait(tgp_server server, int64_t ticket, int64_t timeout_us);
+/* Frees the run's resident subtrees (those still in use are freed when the
+ * requests using them end). */
+tgp_status tgp_server_end_run(tgp_server server, int64_t run_id);
+const char *tgp_server_last_error(tgp_server server);
+
+typedef struct {
+    int32_t status;        /* TGP_OK when done, TGP_EBUSY while queued or running, else its error */
+    int32_t slabs;         /* slabs the request's cases were split into */
+    double submit_ms, admit_ms, start_ms, done_ms; /* server clock (ms since creation) */
+    double latency_ms;     /* done - submit */
+    int64_t dag_nodes;     /* unique subtrees of the request's population */
+    int64_t credited_node_evals; /* dag_nodes x cases */
+    int32_t cache_hits;    /* cached subtrees read from earlier requests */
+    int32_t cache_new;     /* cached subtrees computed and kept by this request */
+} tgp_ticket_info;
+tgp_status tgp_server_ticket_info(tgp_server server, int64_t ticket, tgp_ticket_info *out);
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t steps, slabs;          /* batched steps launched, request slabs they carried */
+    int64_t cache_hits, cache_new, evictions, entries;
+    int64_t bytes_in_use, bytes_peak, bytes_capacity;  /* resident subtree cache */
+    int64_t credited_node_evals;   /* of completed requests */
+    int32_t max_active_seen;       /* most requests evaluated together */
+    int32_t pad;
+} tgp_server_stats;
+tgp_status tgp_server_stats_get(tgp_server server, tgp_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,8 @@ struct tgp_batch_s {
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraphNode_t> nodes;
     bool stale = true;
+    hipEvent_t staged_ev = nullptr;  // recorded after the uploads out of the staging buffers
+    bool staged = false;
     tgp_batch_stats stats{};
     // kernel argument storage (launch i reads args[i])
     int32_t n_counters = 0;
@@ -240,6 +242,7 @@ void tgp_batch_destroy(tgp_batch b) {
     hipSetDevice(b->ctx->device);
     hipStreamSynchronize(b->ctx->stream);
     batch_release_graph(b);
+    if (b->staged_ev) hipEventDestroy(b->staged_ev);
     b->jobs.release();
     b->pairs.release();
     b->item_first.release();
@@ -274,8 +277,46 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(ctx, TGP_EINVAL, "bad job list");
     HCHK(ctx, hipSetDevice(ctx->device));
     const double t0 = now_ms();
-    // The previous step's copies out of the staging buffers must be done.
-    HCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<StepJob> sj(n_jobs);
+    int64_t credited = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const tgp_job &J = jobs[j];
+        tgp_status st = check_eval_args(ctx, J.dag, J.domain);
+        if (st != TGP_OK) return fail(ctx, st, "job %d: %s", j, ctx->err.c_str());
+        if (J.loss != TGP_RMSE && J.loss != TGP_MSE) return fail(ctx, TGP_EINVAL, "job %d: bad loss", j);
+        if (J.dag->n_ind > 0 && (!J.target_dev || !J.out_dev))
+            return fail(ctx, TGP_EINVAL, "job %d: NULL target or output", j);
+        st = build_plan(ctx, J.dag, J.domain->cases);
+        if (st != TGP_OK) return fail(ctx, st, "job %d: %s", j, ctx->err.c_str());
+        StepJob &s = sj[j];
+        s.plan = &J.dag->plan;
+        s.domain = J.domain;
+        s.n_ind = J.dag->n_ind;
+        s.n_ch = J.dag->n_ch;
+        s.case_base = 0;
+        s.n_cases = (int32_t)J.domain->cases;
+        s.target = J.target_dev;
+        s.out = J.out_dev;
+        s.loss = J.loss;
+        credited += J.dag->stats.dag_nodes * J.domain->cases;
+    }
+    const double t_plan = now_ms() - t0;
+    tgp_status st = batch_step(b, n_jobs, sj.data(), credited);
+    b->stats.pack_ms += t_plan;
+    return st;
+}
+
+}  // extern "C"
+
+tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t credited) {
+    tgp_ctx ctx = b->ctx;
+    const double t0 = now_ms();
+    // The staging buffers are free once the copies of this batch's previous
+    // step have run (later steps on other batches need not be waited for).
+    if (b->staged) {
+        HCHK(ctx, hipEventSynchronize(b->staged_ev));
+        b->staged = false;
+    }
     int K = ctx->force_K ? ctx->force_K : 4;
     if (!interp_variant_exists(K, interp_max_stack())) K = 4;
     if (K != b->K) {
@@ -287,19 +328,9 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
         b->persistent = persistent;
         b->stale = true;
     }
-    // ---- plans
     int max_levels = 0;
-    for (int32_t j = 0; j < n_jobs; ++j) {
-        const tgp_job &J = jobs[j];
-        tgp_status st = check_eval_args(ctx, J.dag, J.domain);
-        if (st != TGP_OK) return fail(ctx, st, "job %d: %s", j, ctx->err.c_str());
-        if (J.loss != TGP_RMSE && J.loss != TGP_MSE) return fail(ctx, TGP_EINVAL, "job %d: bad loss", j);
-        if (J.dag->n_ind > 0 && (!J.target_dev || !J.out_dev))
-            return fail(ctx, TGP_EINVAL, "job %d: NULL target or output", j);
-        st = build_plan(ctx, J.dag, J.domain->cases);
-        if (st != TGP_OK) return fail(ctx, st, "job %d: %s", j, ctx->err.c_str());
-        max_levels = std::max(max_levels, (int)J.dag->plan.level_first.size() - 1);
-    }
+    for (int32_t j = 0; j < n_jobs; ++j)
+        max_levels = std::max(max_levels, (int)jobs[j].plan->level_first.size() - 1);
     if (max_levels > b->levels_cap) {
         b->levels_cap = std::max(max_levels, 2 * b->levels_cap);
         if (b->levels_cap > 63) return fail(ctx, TGP_EINVAL, "more than 63 cache-fill levels");
@@ -307,11 +338,10 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     }
     // ---- launch shape: tiles per item from the whole batch's work
     int64_t total_tiles = 0;
-    std::vector<int64_t> ntiles(n_jobs);
+    std::vector<int64_t> ntiles(n_jobs), tps(n_jobs);
     for (int32_t j = 0; j < n_jobs; ++j) {
-        const tgp_job &J = jobs[j];
-        ntiles[j] = (J.domain->cases + 64 * K - 1) / (64 * K);
-        total_tiles += ntiles[j] * std::max<int64_t>(J.dag->plan.n_reduce, 0);
+        ntiles[j] = (jobs[j].n_cases + 64 * K - 1) / (64 * K);
+        total_tiles += ntiles[j] * std::max<int64_t>(jobs[j].plan->n_reduce, 0);
     }
     const int cap = ctx->tile_cap > 0 ? ctx->tile_cap : 16;
     int64_t tps_all = ctx->force_tiles > 0
@@ -321,15 +351,16 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     size_t n_code = 0, n_rows = 0, n_cache = 0, n_partial = 0, n_pairs = 0;
     uint32_t n_ind = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
-        const Plan &P = jobs[j].dag->plan;
-        const int64_t tps = std::min<int64_t>(tps_all, ntiles[j]);
-        const int64_t stripes = (ntiles[j] + tps - 1) / tps;
-        n_code += P.code_host.size();
-        n_rows += P.ind_rows_host.size();
-        n_cache += (size_t)P.n_slots * (size_t)jobs[j].domain->cases;
+        const Plan &P = *jobs[j].plan;
+        const int64_t want = jobs[j].tiles_per_item > 0 ? jobs[j].tiles_per_item : tps_all;
+        tps[j] = std::max<int64_t>(1, std::min<int64_t>(want, ntiles[j]));
+        const int64_t stripes = (ntiles[j] + tps[j] - 1) / tps[j];
+        if (!jobs[j].code_dev) n_code += P.code_host.size();
+        if (!jobs[j].rows_dev) n_rows += P.ind_rows_host.size();
+        if (!jobs[j].cache) n_cache += (size_t)P.n_slots * (size_t)jobs[j].domain->cases;
         n_partial += (size_t)P.n_reduce * (size_t)stripes;
         n_pairs += P.fill_host.size() + P.reduce_host.size();
-        n_ind += (uint32_t)jobs[j].dag->n_ind;
+        n_ind += (uint32_t)jobs[j].n_ind;
     }
     const int G = b->levels_cap + 1;
     hipError_t e = hipSuccess;
@@ -371,42 +402,53 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     size_t code_at = 0, rows_at = 0, cache_at = 0, part_at = 0;
     uint32_t ind_at = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
-        const tgp_job &J = jobs[j];
-        const Plan &P = J.dag->plan;
-        const int64_t tps = std::min<int64_t>(tps_all, ntiles[j]);
-        const int64_t stripes = (ntiles[j] + tps - 1) / tps;
+        const StepJob &J = jobs[j];
+        const Plan &P = *J.plan;
+        const int64_t stripes = (ntiles[j] + tps[j] - 1) / tps[j];
+        const int64_t dom_cases = J.domain->cases;
         JobDesc &jd = b->h_jobs.h[j];
-        fill_job(jd, J.domain, b->code.d + code_at, b->cache.d + cache_at);
+        float *cache = J.cache ? const_cast<float *>(J.cache) : b->cache.d + cache_at;
+        fill_job(jd, J.domain, J.code_dev ? J.code_dev : b->code.d + code_at, cache);
+        jd.n_cases = J.n_cases;
+        jd.case_base = J.case_base;
+        jd.cache_stride = J.cache ? J.cache_stride : dom_cases;
+        jd.out = cache;
+        jd.out_stride = jd.cache_stride;
         jd.n_stripes = (int32_t)stripes;
-        jd.tiles_per_stripe = (int32_t)tps;
-        jd.out = b->cache.d + cache_at;
-        jd.target = J.target_dev;
+        jd.tiles_per_stripe = (int32_t)tps[j];
+        jd.target = J.target;
+        jd.target_stride = dom_cases;
         jd.partial = b->partial.d + part_at;
-        memcpy(b->h_code.h + code_at, P.code_host.data(), sizeof(uint2) * P.code_host.size());
-        memcpy(b->h_rows.h + rows_at, P.ind_rows_host.data(), sizeof(int32_t) * P.ind_rows_host.size());
+        if (!J.code_dev)
+            memcpy(b->h_code.h + code_at, P.code_host.data(), sizeof(uint2) * P.code_host.size());
+        if (!J.rows_dev)
+            memcpy(b->h_rows.h + rows_at, P.ind_rows_host.data(), sizeof(int32_t) * P.ind_rows_host.size());
         FinJob &f = b->h_fin.h[j];
         f.partial = jd.partial;
-        f.ind_rows = b->rows.d + rows_at;
-        f.out = J.out_dev;
-        f.n_terms = (double)J.dag->n_ch * (double)J.domain->cases;
-        f.n_ch = J.dag->n_ch;
+        f.ind_rows = J.rows_dev ? J.rows_dev : b->rows.d + rows_at;
+        f.out = J.out;
+        f.acc = J.acc;
+        f.first = J.acc ? J.first : 1;
+        f.last = J.acc ? J.last : 1;
+        f.n_terms = (double)J.n_ch * (double)dom_cases;
+        f.n_ch = J.n_ch;
         f.n_stripes = (int32_t)stripes;
         f.loss = J.loss;
         f.ind_begin = ind_at;
         for (size_t l = 0; l + 1 < P.level_first.size(); ++l)
             for (int32_t q = P.level_first[l]; q < P.level_first[l + 1]; ++q) {
                 const ProgDesc &pd = P.fill_host[q];
-                groups[l].push_back({(double)pd.len * tps, {j, pd.code_off, pd.dest, pd.chan},
+                groups[l].push_back({(double)pd.len * tps[j], {j, pd.code_off, pd.dest, pd.chan},
                                      (uint32_t)stripes});
             }
         for (const ProgDesc &pd : P.reduce_host)
-            groups[G - 1].push_back({(double)pd.len * tps, {j, pd.code_off, pd.dest, pd.chan},
+            groups[G - 1].push_back({(double)pd.len * tps[j], {j, pd.code_off, pd.dest, pd.chan},
                                      (uint32_t)stripes});
-        code_at += P.code_host.size();
-        rows_at += P.ind_rows_host.size();
-        cache_at += (size_t)P.n_slots * (size_t)J.domain->cases;
+        if (!J.code_dev) code_at += P.code_host.size();
+        if (!J.rows_dev) rows_at += P.ind_rows_host.size();
+        if (!J.cache) cache_at += (size_t)P.n_slots * (size_t)dom_cases;
         part_at += (size_t)P.n_reduce * (size_t)stripes;
-        ind_at += (uint32_t)J.dag->n_ind;
+        ind_at += (uint32_t)J.n_ind;
     }
     b->h_code.h[code_at] = uint2{I_END, 0};
     size_t pi = 0;
@@ -446,7 +488,10 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     up(b->scalars.d, b->h_scalars.h, sizeof(int32_t) * 2);
     up(b->code.d, b->h_code.h, sizeof(uint2) * (n_code + 1));
     up(b->rows.d, b->h_rows.h, sizeof(int32_t) * n_rows);
+    if (e == hipSuccess && !b->staged_ev) e = hipEventCreateWithFlags(&b->staged_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->staged_ev, ctx->stream);
     if (e != hipSuccess) return fail(ctx, TGP_EHIP, "batch upload: %s", hipGetErrorString(e));
+    b->staged = true;
     const int gs = batch_grid(K, interp_max_stack(), true), gr = batch_grid(K, interp_max_stack(), false);
     if (gs != b->grid_store || gr != b->grid_reduce) {
         b->grid_store = gs;
@@ -482,14 +527,14 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     b->stats.cases_per_lane = K;
     b->stats.persistent = b->persistent ? 1 : 0;
     b->stats.pack_ms = t1 - t0;
-    int64_t credited = 0;
-    for (int32_t j = 0; j < n_jobs; ++j) credited += jobs[j].dag->stats.dag_nodes * jobs[j].domain->cases;
     b->stats.credited_node_evals = credited;
     ctx->times.interp_items = (int64_t)item;
     ctx->times.cases_per_lane = K;
     ctx->times.tiles_per_item = (int32_t)tps_all;
     return TGP_OK;
 }
+
+extern "C" {
 
 tgp_status tgp_ctx_set_batch_form(tgp_ctx ctx, int32_t persistent) {
     if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");

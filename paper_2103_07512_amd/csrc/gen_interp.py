@@ -82,7 +82,7 @@ def body_for_depth(D):
     e(f"// at depth 1 (res = the program's value); a malformed program gives NaN.")
     e("template <int K>")
     e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
-    e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int32_t n_cases,")
+    e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
     e("        const int32_t (&cidx)[K], FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
@@ -106,7 +106,7 @@ def body_for_depth(D):
             e(f"        goto L{S + 1};")
             e("    }")
             e("    case I_CACHE: {")
-            e("        const float *row = cache + (size_t)(ins.x >> 8) * (size_t)n_cases;")
+            e("        const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
             e("#pragma unroll")
             e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];")
             e(f"        goto L{S + 1};")

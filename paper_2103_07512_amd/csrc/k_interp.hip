@@ -62,10 +62,10 @@ __device__ __forceinline__ void kahan_merge(float &s, float &c, float s2, float 
 
 template <int K, int D>
 __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const FV<K> &yv,
-                                         const FV<K> &zv, const float *cache, int32_t n_cases,
+                                         const FV<K> &zv, const float *cache, int64_t cache_stride,
                                          const int32_t (&cidx)[K], FV<K> &res) {
     static_assert(D == 8, "compiled stack size: 8");
-    run_prog_d8<K>(ip, xv, yv, zv, cache, n_cases, cidx, res);
+    run_prog_d8<K>(ip, xv, yv, zv, cache, cache_stride, cidx, res);
 }
 
 // One work item: program `code` over tiles_per_stripe tiles of one stripe.
@@ -75,6 +75,7 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
     const int32_t n = a.n_cases;
     const int64_t tile_cases = 64 * K;
     const int64_t first = (int64_t)stripe * a.tiles_per_stripe * tile_cases;
+    const int32_t gb = a.case_base;
 
     float ks = 0.0f, kc = 0.0f;
     for (int t = 0; t < a.tiles_per_stripe; ++t) {
@@ -86,7 +87,7 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
         for (int k = 0; k < K; ++k) {
             const int64_t c = base + 64 * k + lane;
             valid[k] = c < n;
-            cidx[k] = valid[k] ? (int32_t)c : n - 1;
+            cidx[k] = gb + (valid[k] ? (int32_t)c : n - 1);  // global case index
         }
         FV<K> xv, yv, zv;
 #pragma unroll
@@ -110,14 +111,14 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
             }
         }
         FV<K> res;
-        run_prog<K, D>(code, xv, yv, zv, a.cache, n, cidx, res);
+        run_prog<K, D>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, res);
         if constexpr (MODE == MODE_STORE) {
-            float *row = a.out + (size_t)dest * (size_t)n;
+            float *row = a.out + (size_t)dest * (size_t)a.out_stride;
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (valid[k]) row[cidx[k]] = res.v[k];
         } else {
-            const float *trow = a.target + (size_t)chan * (size_t)n;
+            const float *trow = a.target + (size_t)chan * (size_t)a.target_stride;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float e = res.v[k] - trow[cidx[k]];
@@ -243,7 +244,8 @@ __global__ void k_reset(uint32_t *counters, int32_t n) {
 // channels' partial rows, stripes in order, then a fixed-shape tree in LDS.
 __device__ __forceinline__ void finalize_one(const float2 *partial, const int32_t *ind_rows,
                                              int32_t n_ch, int32_t n_stripes, double n_terms,
-                                             int32_t loss, double *out, int i) {
+                                             int32_t loss, double *out, double *acc_in, int first,
+                                             int last, int i) {
     __shared__ double red[256];
     __shared__ int bad[256];
     const int tid = threadIdx.x;
@@ -269,9 +271,17 @@ __device__ __forceinline__ void finalize_one(const float2 *partial, const int32_
         __syncthreads();
     }
     if (tid == 0) {
-        const double s = red[0];
+        double s = red[0];
+        if (bad[0]) s = INFINITY;
+        if (acc_in) {  // one slab: running sum over the slabs in order
+            if (!first) s = acc_in[i] + s;
+            if (!last) {
+                acc_in[i] = s;
+                return;
+            }
+        }
         double f;
-        if (bad[0] || !isfinite(s))
+        if (!isfinite(s))
             f = INFINITY;
         else
             f = loss == TGP_RMSE ? sqrt(s / n_terms) : s / n_terms;
@@ -282,7 +292,7 @@ __device__ __forceinline__ void finalize_one(const float2 *partial, const int32_
 __global__ __launch_bounds__(256) void k_finalize(const float2 *partial, const int32_t *ind_rows,
                                                   int32_t n_ch, int32_t n_stripes, double n_terms,
                                                   int32_t loss, double *out) {
-    finalize_one(partial, ind_rows, n_ch, n_stripes, n_terms, loss, out, blockIdx.x);
+    finalize_one(partial, ind_rows, n_ch, n_stripes, n_terms, loss, out, nullptr, 1, 1, blockIdx.x);
 }
 
 // Batched finalize: block b is global individual b; blocks past the batch's
@@ -298,7 +308,7 @@ __global__ __launch_bounds__(256) void k_finalize_batch(const FinJob *jobs, cons
         else hi = m;
     }
     const FinJob f = jobs[lo];
-    finalize_one(f.partial, f.ind_rows, f.n_ch, f.n_stripes, f.n_terms, f.loss, f.out,
+    finalize_one(f.partial, f.ind_rows, f.n_ch, f.n_stripes, f.n_terms, f.loss, f.out, f.acc, f.first, f.last,
                  (int)(b - f.ind_begin));
 }
 

@@ -235,6 +235,8 @@ tgp_status tgp_domain_create(tgp_ctx ctx, int32_t ndim, const int64_t *shape, co
     }
     for (int k = 0; k < ndim; ++k) {
         const double l = lo ? lo[k] : -1.0, h = hi ? hi[k] : 1.0;
+        d->lo[k] = l;
+        d->hi[k] = h;
         std::vector<float> tab(shape[k]);
         for (int64_t i = 0; i < shape[k]; ++i) {
             const double v = shape[k] == 1 ? l : l + (h - l) * (double)i / (double)(shape[k] - 1);
@@ -421,6 +423,7 @@ struct Planner {
     int D;
     size_t budget_slots;
     std::vector<uint8_t> cached;
+    std::vector<uint8_t> pre;   // cached and already resident: read, never filled
     std::vector<uint8_t> perm;  // evaluation order of each node's children (index in kPerms)
     std::vector<int32_t> slot, level;
     std::vector<double> cost;
@@ -438,12 +441,19 @@ struct Planner {
     tgp_status decide(const std::vector<int32_t> &rootrefs, std::string &why) {
         const int64_t U = (int64_t)d.op.size();
         cached.assign(U, 0);
+        pre.assign(U, 0);
         cost.assign(U, 0.0);
         for (int64_t n = 0; n < U; ++n) {
             double c = kOpCost[op(n)];
             for (int j = 0; j < arity(n); ++j) c += cost[d.kid[3 * n + j]];
             cost[n] = c;
         }
+        // Subtrees whose values over this domain are already resident (kept
+        // from an earlier evaluation) are read instead of recomputed when
+        // recomputing costs more than the read.
+        if (!d.precached.empty() && access_cost >= 0)
+            for (int64_t n = 0; n < U; ++n)
+                if (d.precached[n] && arity(n) > 0 && cost[n] > access_cost) cached[n] = pre[n] = 1;
         // Bottom-up: bound the register stack of every program.  Children are
         // evaluated in decreasing order of the stack they need (Sethi-Ullman);
         // a node whose children still cannot be evaluated within D slots gets
@@ -500,10 +510,17 @@ struct Planner {
                     ++used;
                 }
             }
-            const double contrib = cached[n] ? 1.0 : uses[n];
+            const double contrib = pre[n] ? 0.0 : (cached[n] ? 1.0 : uses[n]);
             if (contrib > 0)
                 for (int j = 0; j < arity(n); ++j) uses[d.kid[3 * n + j]] += contrib;
         }
+        // A spill below a resident subtree that nothing else reads is dropped
+        // (its fill would be wasted).
+        for (int64_t n = 0; n < U; ++n)
+            if (cached[n] && !pre[n] && uses[n] == 0) {
+                cached[n] = 0;
+                --used;
+            }
         // Levels and slots.
         std::vector<int32_t> dep(U, 0);
         level.assign(U, -1);
@@ -516,7 +533,10 @@ struct Planner {
                 dp = std::max(dp, cached[c] ? level[c] + 1 : dep[c]);
             }
             dep[n] = dp;
-            if (cached[n]) {
+            if (pre[n]) {
+                level[n] = -1;  // available before the first fill level
+                slot[n] = ns++;
+            } else if (cached[n]) {
                 level[n] = dp;
                 slot[n] = ns++;
             }
@@ -541,7 +561,8 @@ struct Planner {
             }
             uint2 ins{0, 0};
             if (n != root && cached[n]) {
-                ins.x = I_CACHE | ((uint32_t)slot[n] << 8);
+                ins.x = I_CACHE;
+                ins.y = (uint32_t)slot[n];
                 ++cache_reads;
                 *valu += 1.0;
             } else {
@@ -634,11 +655,18 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
             cached_nodes.push_back((int32_t)n);
             max_level = std::max(max_level, pl.level[n]);
         }
+    P.slot_node.assign(cached_nodes.size(), -1);
+    P.slot_pre.assign(cached_nodes.size(), 0);
+    for (int32_t n : cached_nodes) {
+        P.slot_node[pl.slot[n]] = n;
+        P.slot_pre[pl.slot[n]] = pl.pre[n];
+    }
     P.level_first.assign(max_level + 2, 0);
     std::vector<std::vector<ProgDesc>> by_level(max_level + 1);
     int64_t cache_reads_fill = 0;
     double valu_fill = 0;
     for (int32_t n : cached_nodes) {
+        if (pl.pre[n]) continue;
         ProgDesc pd{};
         pd.code_off = (uint32_t)code.size();
         pl.emit(n, code, cache_reads_fill, &valu_fill);
@@ -704,37 +732,39 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.n_reduce = (int32_t)reduce.size();
     P.n_store = (int32_t)store.size();
 
-    // One device block (256-byte aligned parts) filled by one copy from the
-    // pinned staging; later launches on the stream see it in order.
-    const size_t part[5] = {sizeof(uint2) * code.size(), sizeof(ProgDesc) * fill.size(),
-                            sizeof(ProgDesc) * reduce.size(), sizeof(ProgDesc) * store.size(),
-                            sizeof(int32_t) * ind_rows.size()};
-    const void *src[5] = {code.data(), fill.data(), reduce.data(), store.data(), ind_rows.data()};
-    size_t off[5], total = 0;
-    for (int i = 0; i < 5; ++i) {
-        off[i] = total;
-        total += (part[i] + 255) & ~(size_t)255;
+    if (ctx->plan_upload) {
+        // One device block (256-byte aligned parts) filled by one copy from the
+        // pinned staging; later launches on the stream see it in order.
+        const size_t part[5] = {sizeof(uint2) * code.size(), sizeof(ProgDesc) * fill.size(),
+                                sizeof(ProgDesc) * reduce.size(), sizeof(ProgDesc) * store.size(),
+                                sizeof(int32_t) * ind_rows.size()};
+        const void *src[5] = {code.data(), fill.data(), reduce.data(), store.data(), ind_rows.data()};
+        size_t off[5], total = 0;
+        for (int i = 0; i < 5; ++i) {
+            off[i] = total;
+            total += (part[i] + 255) & ~(size_t)255;
+        }
+        void *stage = nullptr;
+        hipError_t e = ctx->pool.alloc(&P.blob, total);
+        if (e == hipSuccess) e = ctx_pinned(ctx, total, &stage);
+        if (e == hipSuccess) {
+            for (int i = 0; i < 5; ++i)
+                if (part[i]) memcpy((char *)stage + off[i], src[i], part[i]);
+            e = hipMemcpyAsync(P.blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
+        }
+        if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
+        if (e != hipSuccess) {
+            hipStreamSynchronize(ctx->stream);
+            P.release(ctx->pool);
+            return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
+        }
+        char *b = static_cast<char *>(P.blob);
+        P.code_dev = reinterpret_cast<uint2 *>(b + off[0]);
+        P.fill_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
+        P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
+        P.store_dev = reinterpret_cast<ProgDesc *>(b + off[3]);
+        P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[4]);
     }
-    void *stage = nullptr;
-    hipError_t e = ctx->pool.alloc(&P.blob, total);
-    if (e == hipSuccess) e = ctx_pinned(ctx, total, &stage);
-    if (e == hipSuccess) {
-        for (int i = 0; i < 5; ++i)
-            if (part[i]) memcpy((char *)stage + off[i], src[i], part[i]);
-        e = hipMemcpyAsync(P.blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
-    }
-    if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
-    if (e != hipSuccess) {
-        hipStreamSynchronize(ctx->stream);
-        P.release(ctx->pool);
-        return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
-    }
-    char *b = static_cast<char *>(P.blob);
-    P.code_dev = reinterpret_cast<uint2 *>(b + off[0]);
-    P.fill_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
-    P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
-    P.store_dev = reinterpret_cast<ProgDesc *>(b + off[3]);
-    P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[4]);
     P.code_host = std::move(code);
     P.fill_host = std::move(fill);
     P.reduce_host = std::move(reduce);
@@ -781,6 +811,8 @@ void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache)
         j.coord[k] = dom->coord[k] ? dom->coord[k] : dom->coord[0];
     }
     j.cache = cache;
+    j.case_base = 0;
+    j.cache_stride = j.out_stride = j.target_stride = dom->cases;
 }
 
 static void fill_args(InterpArgs &a, tgp_domain dom, const Plan &P, const float *cache) {

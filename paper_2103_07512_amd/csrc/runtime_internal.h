@@ -30,6 +30,7 @@ struct tgp_ctx_s {
     int batch_persistent = 1;  // batched launches: persistent waves (1) or one wave per item
     tgp_batch batch = nullptr;  // kept by tgp_fitness_batch
     int reorder = 1;                     // Sethi-Ullman child order
+    bool plan_upload = true;             // plans also kept on the device
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
     DevicePool pool;             // DAG, plan and population blocks
@@ -60,6 +61,7 @@ struct tgp_domain_s {
     int64_t shape[3] = {1, 1, 1};
     int64_t stride[3] = {1, 1, 1};
     int64_t cases = 0;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float *coord[3] = {nullptr, nullptr, nullptr};
 };
 
@@ -82,6 +84,8 @@ struct Plan {
     std::vector<uint2> code_host;
     std::vector<ProgDesc> fill_host, reduce_host;
     std::vector<int32_t> ind_rows_host;
+    std::vector<int32_t> slot_node;     // DAG node held by each cache slot
+    std::vector<uint8_t> slot_pre;      // slot already resident (no fill program)
     int64_t instructions = 0;
     double exec_per_case = 0;           // instructions run per case, fitness form
     double valu_dag_per_case = 0;       // cost-model slots of each DAG node once
@@ -109,6 +113,7 @@ struct tgp_dag_s {
     std::vector<float> value;
     std::vector<int32_t> kid;  // [U][3]
     std::vector<int32_t> roots, mult, indeg, height;
+    std::vector<uint8_t> precached;  // nodes whose values are resident (empty: none)
     Plan plan;
 };
 
@@ -142,6 +147,31 @@ inline hipError_t ensure(DevBuf &b, size_t bytes) {
 hipError_t ctx_pinned(tgp_ctx ctx, size_t bytes, void **out);
 // Marks the staging as read by copies enqueued on the context stream.
 hipError_t ctx_pinned_enqueued(tgp_ctx ctx);
+
+// One job of a batched step: a plan's programs over the cases
+// [case_base, case_base + n_cases) of a domain.
+struct StepJob {
+    const Plan *plan;             // host copies of the programs are used
+    tgp_domain domain;
+    int32_t n_ind = 0, n_ch = 0;
+    int32_t case_base = 0, n_cases = 0;
+    const float *target = nullptr;   // [n_ch][domain cases]
+    // Cache rows: with cache == nullptr the step allocates [slots][domain
+    // cases] rows itself (slot s is row s); otherwise the plan's slot numbers
+    // are rows of `cache` with stride cache_stride.
+    const float *cache = nullptr;
+    int64_t cache_stride = 0;
+    double *acc = nullptr;        // slab running sums (nullptr: whole domain)
+    int32_t first = 1, last = 1;  // first / last slab of the domain
+    double *out = nullptr;        // device, [n_ind]
+    int32_t loss = TGP_RMSE;
+    int32_t tiles_per_item = 0;   // 0: chosen from the whole step's work
+    // Programs and individual rows already on the device (nullptr: the step
+    // uploads the plan's host copies).
+    const uint2 *code_dev = nullptr;
+    const int32_t *rows_dev = nullptr;
+};
+tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t credited);
 
 // --------------------------------------------------------------- shared helpers
 extern const double kOpCost[TGP_NUM_OPS];

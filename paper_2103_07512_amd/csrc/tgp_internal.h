@@ -24,9 +24,10 @@ constexpr int kArity[TGP_NUM_OPS] = {
     1, 1, 1, 2, 3  // step sstep sstepp len lerp
 };
 
-// Interpreter instruction codes.  An instruction is a uint2: .x = code |
-// (aux << 8), .y = the FP32 bits of a constant.  aux is the cache slot of
-// I_CACHE.  Function opcodes are the public opcode plus kFnBase.
+// Interpreter instruction codes.  An instruction is a uint2: .x = code, .y =
+// the FP32 bits of a constant (I_CONST) or the cache row (I_CACHE: the row
+// starts cache_stride floats times .y past the job's cache base).  Function
+// opcodes are the public opcode plus kFnBase.
 // Operators whose children were evaluated out of left-to-right order (to
 // bound the stack, Sethi-Ullman order) use the permuted forms: kRevBase + op
 // for a reversed non-commutative binary operator, kPermBase + 6 t + p for
@@ -61,19 +62,24 @@ struct ProgDesc {
 
 // Everything a work item needs to know about the domain and the buffers of
 // the evaluation it belongs to.
+// A job covers the n_cases consecutive cases of the domain that start at
+// case case_base (all of it, or one slab of it); every per-case array below
+// is indexed by the global case index case_base + i.
 struct JobDesc {
     const uint2 *code;           // all instructions of the job, padded by one I_END
     int32_t n_stripes;           // work items per program
     int32_t tiles_per_stripe;    // tiles of 64*K cases per work item
-    int32_t n_cases;
+    int32_t n_cases;             // cases of the job
+    int32_t case_base;           // global index of its first case
     int32_t ndim;
     int32_t shape[3];
     int32_t stride[3];
-    const float *coord[3];       // per-axis coordinate tables
-    const float *cache;          // [slots][n_cases]
-    float *out;                  // STORE: [dest][n_cases]
-    const float *target;         // REDUCE: [chan][n_cases]
+    const float *coord[3];       // per-axis coordinate tables of the whole domain
+    const float *cache;          // I_CACHE row r: cache + r * cache_stride
+    float *out;                  // STORE: row dest at out + dest * out_stride
+    const float *target;         // REDUCE: channel chan at target + chan * target_stride
     float2 *partial;             // REDUCE: [dest][n_stripes] (sum, compensation)
+    int64_t cache_stride, out_stride, target_stride;
 };
 
 // Launch arguments of the plain (one program set, one domain) interpreter:
@@ -99,16 +105,22 @@ struct GroupDesc {
     uint32_t item_begin, item_end;
 };
 
-// Finalize of one job in a batch.
+// Finalize of one job in a batch.  Without acc the job covers the whole
+// domain and out receives the loss.  With acc (one FP64 running sum per
+// individual, a job over one slab of the domain) the slab's sum is added to
+// acc, and on the last slab the loss of the total goes to out.
 struct FinJob {
     const float2 *partial;
     const int32_t *ind_rows;
     double *out;
+    double *acc;
     double n_terms;
     int32_t n_ch;
     int32_t n_stripes;
     int32_t loss;
     uint32_t ind_begin;          // first global individual index of the job
+    int32_t first;               // acc holds nothing yet (first slab)
+    int32_t last;
 };
 
 // Instantiated kernel variants (cases per lane K, stack registers D).

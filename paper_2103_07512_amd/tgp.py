@@ -99,6 +99,28 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 I32, I64 = ctypes.c_int32, ctypes.c_int64
 
 # (name, restype, argtypes) of every exported function of include/tgp.h
+class TicketInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slabs", ctypes.c_int32),
+                ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("dag_nodes", ctypes.c_int64),
+                ("credited_node_evals", ctypes.c_int64), ("cache_hits", ctypes.c_int32),
+                ("cache_new", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "completed", "failed", "steps", "slabs", "cache_hits", "cache_new",
+        "evictions", "entries", "bytes_in_use", "bytes_peak", "bytes_capacity",
+        "credited_node_evals")] + [("max_active_seen", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_ if n != "pad"}
+
+
 SIGNATURES = [
     ("tgp_ctx_create", I32, [ctypes.c_int, P, PP]),
     ("tgp_ctx_destroy", None, [P]),
@@ -127,6 +149,16 @@ SIGNATURES = [
     ("tgp_ctx_set_batch_form", I32, [P, I32]),
     ("tgp_batch_stats_get", I32, [P, ctypes.POINTER(BatchStats)]),
     ("tgp_autotune", I32, [P, I32, ctypes.POINTER(Job), ctypes.c_char_p, ctypes.POINTER(TuneResult)]),
+    ("tgp_server_create", I32, [P, ctypes.c_size_t, I32, PP]),
+    ("tgp_server_destroy", None, [P]),
+    ("tgp_server_set_slab_work", I32, [P, ctypes.c_double]),
+    ("tgp_server_submit", I32, [P, I64, ctypes.POINTER(_Population), P, P, I32, P,
+                                ctypes.POINTER(I64)]),
+    ("tgp_server_wait", I32, [P, I64, I64]),
+    ("tgp_server_end_run", I32, [P, I64]),
+    ("tgp_server_last_error", ctypes.c_char_p, [P]),
+    ("tgp_server_ticket_info", I32, [P, I64, ctypes.POINTER(TicketInfo)]),
+    ("tgp_server_stats_get", I32, [P, ctypes.POINTER(ServerStats)]),
 ]
 
 
@@ -371,3 +403,84 @@ def autotune(ctx: Context, jobs, cache_path=None) -> dict:
     _check(lib().tgp_autotune(ctx.h, n, arr, cache_path.encode() if cache_path else None,
                               ctypes.byref(r)), ctx.h)
     return r.as_dict()
+
+
+class Server:
+    """tgp_server: continuous-batching fitness service for many concurrent GP runs.
+
+    submit() copies a host population and returns a ticket at once; wait()
+    blocks (with the GIL released) until that request's fitness values are in
+    its output array.  Safe to call from several Python threads.
+    """
+
+    def __init__(self, ctx: Context, cache_budget_bytes: int = 0, max_active: int = 0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().tgp_server_create(ctx.h, cache_budget_bytes, max_active, ctypes.byref(h)), ctx.h)
+        self.h = h
+        self._keep = {}
+
+    def _check(self, status):
+        if status != 0:
+            msg = lib().tgp_server_last_error(self.h)
+            raise TgpError(status, msg.decode() if msg else "")
+
+    def set_slab_work(self, node_evals: float):
+        self._check(lib().tgp_server_set_slab_work(self.h, float(node_evals)))
+
+    def submit(self, run_id: int, pop, domain: Domain, target, loss: int = RMSE, out=None):
+        """Queue pop (popgen.Population or (tokens, offsets, n_ind, n_ch)); returns the ticket.
+
+        out: float64 numpy array of n_individuals (allocated when None),
+        written when the request ends; keep it until wait() returns."""
+        if isinstance(pop, tuple):
+            tokens, offsets, n_ind, n_ch = pop
+        else:
+            tokens, offsets, n_ind, n_ch = pop.tokens, pop.offsets, pop.n_individuals, pop.n_channels
+        t = np.ascontiguousarray(tokens, dtype=TOKEN_DTYPE)
+        o = np.ascontiguousarray(offsets, dtype=np.int64)
+        if out is None:
+            out = np.empty(n_ind, np.float64)
+        assert out.dtype == np.float64 and out.flags.c_contiguous and out.size >= n_ind
+        p = _Population()
+        p.n_individuals = n_ind
+        p.n_channels = n_ch
+        p.offsets = o.ctypes.data
+        p.tokens = t.ctypes.data
+        p.memory = MEM_HOST
+        ticket = I64()
+        self._check(lib().tgp_server_submit(self.h, run_id, ctypes.byref(p), domain.h,
+                                            ctypes.c_void_p(target.data_ptr()), loss,
+                                            out.ctypes.data, ctypes.byref(ticket)))
+        self._keep[ticket.value] = (out, target, domain)
+        return ticket.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """The request's fitness array; TgpError (status TGP_EBUSY) on time-out."""
+        self._check(lib().tgp_server_wait(self.h, ticket, timeout_us))
+        return self._keep.pop(ticket)[0]
+
+    def end_run(self, run_id: int):
+        self._check(lib().tgp_server_end_run(self.h, run_id))
+
+    def ticket_info(self, ticket: int) -> dict:
+        t = TicketInfo()
+        self._check(lib().tgp_server_ticket_info(self.h, ticket, ctypes.byref(t)))
+        return t.as_dict()
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(lib().tgp_server_stats_get(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().tgp_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
