@@ -204,13 +204,20 @@ def test_admission_under_a_small_cache(env):
     for i, w in enumerate(works):
         close(results[i], w.plain(env))
     srv.close()
-    if max(need) > 2:
-        tiny = tgp.Server(ctx, row, 2)
-        t = tiny.submit(0, works[int(np.argmax(need))].pop, works[0].dom, works[0].target, 0)
-        with pytest.raises(tgp.TgpError) as e:
-            tiny.wait(t)
-        assert e.value.status == -5
-        tiny.close()
+    # A tree whose register stack must spill more subtrees than the cache
+    # holds can never be admitted: each complete binary subtree of depth 10
+    # below needs a stack of 11, so each spills one subtree, and the cache
+    # holds one row.
+    def full(d, v):
+        return v if d == 0 else f"add({full(d - 1, v)}, {full(d - 1, v)})"
+    deep = pg.parse(f"sub({full(10, 'x')}, {full(10, 'y')})")
+    pop = pg.Population(deep, np.array([0, len(deep)], np.int64), 1, 1)
+    tiny = tgp.Server(ctx, row, 2)
+    t = tiny.submit(0, pop, works[0].dom, works[0].target, 0)
+    with pytest.raises(tgp.TgpError) as e:
+        tiny.wait(t)
+    assert e.value.status == -5
+    tiny.close()
 
 
 def test_request_errors(env):
