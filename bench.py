@@ -43,6 +43,9 @@ WORKLOADS = {
           "depth-4 tree",
     "c4": "64 populations (sizes log-uniform 20-2000, depths 4-14, 18 operators), domains 2-D "
           "32^2-1024^2 or 3-D 64^3, RMSE; one batched persistent step vs 64 plain launches",
+    "c5": "16 concurrent GP runs (grids 512^2-4096^2, populations log-uniform 200-2000, bred "
+          "closed-loop from returned fitness, depth <= 12, 18 operators), RMSE; served with "
+          "continuous batching and a resident subtree cache",
 }
 
 
@@ -175,6 +178,173 @@ def bench_c4(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_c5(generations, loads, with_plain, warm_generations=2, log=None, configure=None):
+    """The serving workload: 16 GP runs, one request per generation each.
+
+    Pass 1 runs the closed loop (submit, wait, breed the next generation from
+    the returned fitness) and records every population.  Breeding is
+    deterministic given the fitness, so later passes replay the recorded
+    populations with the same per-run order:
+      * capacity: every run resubmits as soon as its previous request ends;
+      * loaded: exponential think times between a result and the next
+        request, with the mean set so that the offered work is `load` times
+        the measured capacity; latency percentiles (submit to fitness on the
+        host) over the requests after the warm-up generations;
+      * plain: one tgp_fitness per request, one after the other.
+    Each pass starts from an empty server.  Returns a dict.
+    """
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2103_07512_amd import popgen as pg
+    from paper_2103_07512_amd import tgp
+
+    def say(*a):
+        if log:
+            print(*a, file=log, flush=True)
+
+    dev = torch.device("cuda:0")
+    runs = pg.workload_c5()
+    ctx = tgp.Context(0)
+    doms, targets = {}, {}
+    for spec in runs:
+        dom = tgp.Domain(ctx, spec.shape)
+
+        def render(tree, dom=dom):
+            d = tgp.Dag(ctx, tree, np.array([0, len(tree)], np.int64), 1)
+            v = torch.empty(1, dom.cases, dtype=torch.float32, device=dev)
+            tgp.evaluate(ctx, d, dom, v)
+            return v[0].cpu().numpy() if bool(torch.isfinite(v).all()) else None
+
+        _, tgt = pg.pick_target(spec.target, render)
+        doms[spec.run] = dom
+        targets[spec.run] = torch.from_numpy(tgt).to(dev)
+    torch.cuda.synchronize()
+
+    pops = {spec.run: [] for spec in runs}
+    fits = {spec.run: [] for spec in runs}
+
+    def closed_loop(srv, spec):
+        pop = spec.first_population()
+        rng = pg.Rng(spec.breed_seed)
+        for g in range(generations):
+            pops[spec.run].append(pop)
+            t = srv.submit(spec.run, pop, doms[spec.run], targets[spec.run], tgp.RMSE)
+            f = srv.wait(t).copy()
+            fits[spec.run].append(f)
+            if g + 1 < generations:
+                pop = pg.breed(pop, rng, pg.F18, 2, max_depth=spec.max_depth, fitness=f)
+
+    def run_threads(target_fn):
+        th = [threading.Thread(target=target_fn, args=(spec,)) for spec in runs]
+        t0 = time.perf_counter()
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        return time.perf_counter() - t0
+
+    say("c5: closed loop with breeding")
+    srv = tgp.Server(ctx, 0, 16)
+    wall_gen = run_threads(lambda spec: closed_loop(srv, spec))
+    srv.close()
+
+    def replay(think_mean_s):
+        srv = tgp.Server(ctx, 0, 16)
+        if configure:
+            configure(srv)
+        infos, same = [], [True]
+        lock = threading.Lock()
+
+        def one(spec):
+            rng = np.random.default_rng(spec.think_seed)
+            for g, pop in enumerate(pops[spec.run]):
+                t = srv.submit(spec.run, pop, doms[spec.run], targets[spec.run], tgp.RMSE)
+                f = srv.wait(t)
+                info = srv.ticket_info(t)
+                ok = np.array_equal(np.asarray(f).view(np.uint64), fits[spec.run][g].view(np.uint64))
+                with lock:
+                    infos.append((g, info))
+                    same[0] &= bool(ok)
+                if think_mean_s > 0:
+                    time.sleep(float(rng.exponential(think_mean_s)))
+
+        wall = run_threads(one)
+        st = srv.stats()
+        srv.close()
+        credited = sum(i["credited_node_evals"] for _, i in infos)
+        lat = np.array([i["latency_ms"] for g, i in infos if g >= warm_generations])
+        ph = {"to_admission": [i["admit_ms"] - i["submit_ms"] for _, i in infos],
+              "prep": [i["prep_ms"] for _, i in infos],
+              "admitted_to_first_step": [i["start_ms"] - i["admit_ms"] for _, i in infos],
+              "running": [i["done_ms"] - i["start_ms"] for _, i in infos]}
+        phases = {k: {"mean_ms": float(np.mean(v)), "p50_ms": float(np.median(v))} for k, v in ph.items()}
+        return dict(wall_s=wall, node_evals_per_s=credited / wall, requests=len(infos), phases=phases,
+                    p50_ms=float(np.percentile(lat, 50)) if lat.size else None,
+                    p99_ms=float(np.percentile(lat, 99)) if lat.size else None,
+                    same_as_closed_loop=same[0], server=st, credited=credited)
+
+    say("c5: capacity")
+    cap = replay(0.0)
+    capacity = cap["node_evals_per_s"]
+    n_req = cap["requests"]
+    mean_work = cap["credited"] / n_req
+    out = {"generations": generations, "runs": len(runs), "requests": n_req,
+           "closed_loop_wall_s": wall_gen, "capacity": cap, "loaded": []}
+    for rho in loads:
+        think = len(runs) * mean_work / (rho * capacity)
+        say(f"c5: offered load {rho} (mean think {think * 1e3:.1f} ms)")
+        r = replay(think)
+        r.update(offered_load=rho, mean_think_ms=think * 1e3)
+        out["loaded"].append(r)
+    if with_plain:
+        say("c5: plain")
+        total, t0 = 0, time.perf_counter()
+        o = torch.empty(2048, dtype=torch.float64, device=dev)
+        agree = True
+        ctx.set_timing(True)
+        host_ms = gpu_ms = 0.0
+        for spec in runs:
+            for g, pop in enumerate(pops[spec.run]):
+                dag = tgp.build_dag(ctx, pop)
+                tgp.fitness(ctx, dag, doms[spec.run], targets[spec.run], tgp.RMSE, o)
+                f = o[:pop.n_individuals].cpu().numpy()
+                tm = ctx.last_timing()
+                host_ms += tm["build_dag_ms"] + tm["plan_ms"]
+                gpu_ms += tm["fill_ms"] + tm["interp_ms"] + tm["finalize_ms"]
+                total += dag.stats()["dag_nodes"] * doms[spec.run].cases
+                a, b = f, fits[spec.run][g]
+                fin = np.isfinite(b)
+                agree &= bool(np.array_equal(np.isfinite(a), fin) and
+                              np.all(np.abs(a[fin] - b[fin]) <= 1e-6 * np.abs(b[fin])))
+                dag.close()
+        wall = time.perf_counter() - t0
+        ctx.set_timing(False)
+        out["plain"] = dict(wall_s=wall, node_evals_per_s=total / wall, agree_within_1e6=agree,
+                            build_and_plan_ms=host_ms, kernels_ms=gpu_ms)
+        out["served_over_plain"] = capacity / (total / wall)
+    return out
+
+
+def bench_c5(args):
+    loads = [float(x) for x in args.loads.split(",") if x.strip()]
+    res = serve_c5(args.generations, loads, not args.no_plain, log=sys.stderr)
+    cap = res["capacity"]
+    line = {
+        "metric": METRIC, "value": cap["node_evals_per_s"], "unit": "node-evals/s", "n_gpus": 1,
+        "steps": res["requests"], "warmup": 0, "ms_per_step": cap["wall_s"] * 1e3 / res["requests"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c5"], "runs": res["runs"], "generations": res["generations"]},
+        "latency": [{"offered_load": r["offered_load"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                     "node_evals_per_s": r["node_evals_per_s"]} for r in res["loaded"]],
+        "detail": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +356,9 @@ def main():
     ap.add_argument("--tiles-per-item", type=int, default=0)
     ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--cache-access-cost", type=float, default=20.0)
+    ap.add_argument("--generations", type=int, default=20, help="serving workload: generations per run")
+    ap.add_argument("--loads", default="0.5,0.7,0.9", help="serving workload: offered loads")
+    ap.add_argument("--no-plain", action="store_true", help="serving workload: skip the plain pass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build evaluates a population on a single MI355X "
@@ -194,6 +367,8 @@ def main():
 
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
 
     import numpy as np
     import torch

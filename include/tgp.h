@@ -331,7 +331,7 @@ tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const 
  * A request's fitness values do not depend on what else is being served: its
  * slabs, work split and summation order are chosen from the request alone,
  * and a resident subtree holds the same FP32 values the request would
- * compute.  The server has two threads of its own and its own HIP streams on
+ * compute.  The server has threads of its own and its own HIP streams on
  * the context's device; submit, wait, ticket_info, stats and end_run may be
  * called from any thread.  The context passed in is only read at creation
  * (device, tuning) and stays free for its owner to use. */
@@ -345,9 +345,14 @@ tgp_status tgp_server_create(tgp_ctx ctx, size_t cache_budget_bytes, int32_t max
  * with TGP_EBUSY.  Domains and targets of finished requests are not touched
  * afterwards. */
 void tgp_server_destroy(tgp_server server);
-/* Work per slab, in instructions x cases (default 2^33): a request over more
- * cases than this is evaluated in slabs of consecutive cases, one per step. */
+/* Work per slab, in DAG nodes x cases (default 2^33): a request with more
+ * work than this is evaluated in slabs of consecutive cases, one per step. */
 tgp_status tgp_server_set_slab_work(tgp_server server, double node_evals);
+/* Launch shape of later steps: persistent waves (1) or one wave per work
+ * item (0, the default), or unchanged (-1); tiles of 64 x cases-per-lane
+ * cases per work item (0: chosen from each request's slab size; applies to
+ * requests admitted afterwards). */
+tgp_status tgp_server_set_launch(tgp_server server, int32_t persistent, int32_t tiles_per_item);
 
 /* Queue one fitness evaluation (does not block on the GPU).  pop must be in
  * host memory (copied during the call); domain and target_dev (device,
@@ -373,6 +378,7 @@ typedef struct {
     int32_t slabs;         /* slabs the request's cases were split into */
     double submit_ms, admit_ms, start_ms, done_ms; /* server clock (ms since creation) */
     double latency_ms;     /* done - submit */
+    double prep_ms;        /* DAG build, cache look-up and planning */
     int64_t dag_nodes;     /* unique subtrees of the request's population */
     int64_t credited_node_evals; /* dag_nodes x cases */
     int32_t cache_hits;    /* cached subtrees read from earlier requests */
@@ -388,6 +394,7 @@ typedef struct {
     int64_t credited_node_evals;   /* of completed requests */
     int32_t max_active_seen;       /* most requests evaluated together */
     int32_t pad;
+    double step_ms;                /* GPU time of the steps (first launch to last) */
 } tgp_server_stats;
 tgp_status tgp_server_stats_get(tgp_server server, tgp_server_stats *out);
 

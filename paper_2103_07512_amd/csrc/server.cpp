@@ -2,13 +2,13 @@
 // per-generation populations of many concurrent GP runs, with continuous
 // batching, admission against device memory and a resident subtree cache.
 //
-// Two threads of its own:
-//   * preparation takes submitted requests in arrival order, builds each
-//     population's DAG on its own stream, looks the DAG's subtrees up in the
-//     resident cache, plans the programs (a resident subtree becomes a cache
-//     read), and admits the request once an evaluation slot is free and the
-//     rows of the subtrees it will cache fit in the cache arena (unpinned
-//     entries are evicted least recently used first);
+// Threads of its own:
+//   * four preparation threads take submitted requests in arrival order; each
+//     builds the population's DAG on its own stream, looks the DAG's subtrees
+//     up in the resident cache, plans the programs (a resident subtree
+//     becomes a cache read), and admits the request once an evaluation slot
+//     is free and the rows of the subtrees it will cache fit in the cache
+//     arena (unpinned entries are evicted least recently used first);
 //   * execution keeps up to two batched steps in flight on its stream.  A
 //     step carries the next slab of cases of every admitted request: the
 //     cache fill of the slab, the root programs fused with the error
@@ -25,6 +25,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -42,6 +43,7 @@ namespace {
 
 constexpr int64_t kUnitFloats = 64;  // arena unit: 256 bytes
 constexpr int64_t kSlabQuantum = 1 << 16;
+constexpr int kPrepThreads = 4;
 
 uint64_t mix64(uint64_t z) {
     z += 0x9e3779b97f4a7c15ull;
@@ -110,7 +112,7 @@ struct Req {
     int status = TGP_EBUSY;
     bool finished = false;
     std::string err;
-    double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+    double t_submit = 0, t_prep = 0, prep_ms = 0, t_admit = 0, t_start = 0, t_done = 0;
 };
 using ReqP = std::shared_ptr<Req>;
 
@@ -118,16 +120,19 @@ using ReqP = std::shared_ptr<Req>;
 
 struct tgp_server_s {
     int device = 0;
-    hipStream_t prep_stream = nullptr, exec_stream = nullptr, copy_stream = nullptr;
-    tgp_ctx prep = nullptr, exec = nullptr;
+    hipStream_t prep_stream[kPrepThreads] = {}, exec_stream = nullptr, copy_stream = nullptr;
+    tgp_ctx prep[kPrepThreads] = {}, exec = nullptr;
     tgp_batch batch[2] = {nullptr, nullptr};
     hipEvent_t done_ev[2] = {nullptr, nullptr};
+    hipEvent_t begin_ev[2] = {nullptr, nullptr};  // before the step's first launch (timed)
     float *arena = nullptr;
     size_t arena_bytes = 0;
     std::unique_ptr<SubtreeCache> cache;
     int max_active = 16;
-    double slab_work = 8589934592.0;  // 2^33 instructions x cases
+    double slab_work = 8589934592.0;  // 2^33 DAG nodes x cases
     int K = 4;
+    int tiles = 0;                    // tiles per work item (0: from the slab size)
+    std::atomic<int> persistent{0};   // launch form of the steps (one wave per item)
 
     std::mutex m;
     std::condition_variable cv_prep, cv_exec, cv_done;
@@ -136,7 +141,7 @@ struct tgp_server_s {
     std::unordered_map<int64_t, ReqP> tickets;
     int64_t next_ticket = 1;
     bool stop = false, stop_exec = false;
-    std::thread prep_thr, exec_thr;
+    std::thread prep_thr[kPrepThreads], exec_thr;
     tgp_server_stats stats{};
     std::string err;
     std::chrono::steady_clock::time_point t0;
@@ -191,17 +196,18 @@ void end_request(tgp_server s, Req &r, int st, const std::string &msg) {
 }
 
 // ------------------------------------------------------------ preparation
-void prepare(tgp_server s, const ReqP &rp) {
+void prepare(tgp_server s, tgp_ctx pc, const ReqP &rp) {
     Req &r = *rp;
+    r.t_prep = s->now();
     if (r.n_ind == 0) {
         end_request(s, r, TGP_OK, "");
         return;
     }
     tgp_population pop{r.n_ind, r.n_ch, r.offsets.data(), r.tokens.data(), TGP_MEM_HOST};
     tgp_dag d = nullptr;
-    tgp_status st = tgp_build_dag(s->prep, &pop, &d);
+    tgp_status st = tgp_build_dag(pc, &pop, &d);
     if (st != TGP_OK) {
-        end_request(s, r, st, std::string("build_dag: ") + tgp_last_error(s->prep));
+        end_request(s, r, st, std::string("build_dag: ") + tgp_last_error(pc));
         return;
     }
     std::unique_ptr<tgp_dag_s, void (*)(tgp_dag)> guard(d, tgp_dag_destroy);
@@ -235,10 +241,10 @@ void prepare(tgp_server s, const ReqP &rp) {
         for (CacheEntry *e : hit)
             if (e) s->cache->unpin(e, false);
     };
-    st = build_plan(s->prep, d, r.dom->cases);
+    st = build_plan(pc, d, r.dom->cases);
     if (st != TGP_OK) {
         unpin_hits();
-        end_request(s, r, st, std::string("plan: ") + tgp_last_error(s->prep));
+        end_request(s, r, st, std::string("plan: ") + tgp_last_error(pc));
         return;
     }
     const Plan &P = d->plan;
@@ -258,6 +264,7 @@ void prepare(tgp_server s, const ReqP &rp) {
         for (int64_t n = 0; n < U; ++n)
             if (hit[n] && !read[n]) s->cache->unpin(hit[n], false);
     }
+    r.prep_ms = s->now() - r.t_prep;
     // Admission: a free slot, and arena rows for every subtree cached anew.
     const uint64_t len = (uint64_t)((r.dom->cases + kUnitFloats - 1) / kUnitFloats);
     {
@@ -312,14 +319,16 @@ void prepare(tgp_server s, const ReqP &rp) {
     for (ProgDesc &pd : r.plan.fill_host) pd.dest = (int32_t)r.entry[pd.dest]->off;
     // Slabs and work split, from this request alone.
     const int64_t cases = r.dom->cases;
-    const double per_case = std::max(1.0, P.exec_per_case);
+    // (from the DAG's size, not from the plan, which depends on what the
+    // cache holds at the time)
+    const double per_case = std::max<double>(1.0, (double)U);
     int64_t slab = (int64_t)(s->slab_work / per_case);
     slab = std::max<int64_t>(kSlabQuantum, slab / kSlabQuantum * kSlabQuantum);
     if (slab >= cases) slab = cases;
     r.slab = slab;
     r.n_slabs = (int32_t)((cases + slab - 1) / slab);
     const int64_t tiles = (slab + 64 * s->K - 1) / (64 * s->K);
-    r.tps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, tiles / 16));
+    r.tps = s->tiles > 0 ? s->tiles : (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, tiles / 16));
     guard.reset();
     {
         std::lock_guard<std::mutex> lk(s->m);
@@ -328,7 +337,7 @@ void prepare(tgp_server s, const ReqP &rp) {
     s->cv_exec.notify_one();
 }
 
-void prep_loop(tgp_server s) {
+void prep_loop(tgp_server s, int i) {
     hipSetDevice(s->device);
     for (;;) {
         ReqP r;
@@ -345,7 +354,7 @@ void prep_loop(tgp_server s) {
             r = s->queued.front();
             s->queued.pop_front();
         }
-        prepare(s, r);
+        prepare(s, s->prep[i], r);
     }
 }
 
@@ -471,8 +480,11 @@ void exec_loop(tgp_server s) {
                 credited += r->dag_nodes * (int64_t)j.n_cases;
             }
             if (!jobs.empty()) {
+                s->exec->batch_persistent = s->persistent.load();
+                hipError_t e = hipEventRecord(s->begin_ev[cur], s->exec_stream);
                 tgp_status st = batch_step(s->batch[cur], (int32_t)jobs.size(), jobs.data(), credited);
-                hipError_t e = st == TGP_OK ? hipEventRecord(s->done_ev[cur], s->exec_stream) : hipErrorUnknown;
+                if (e == hipSuccess)
+                    e = st == TGP_OK ? hipEventRecord(s->done_ev[cur], s->exec_stream) : hipErrorUnknown;
                 if (e != hipSuccess) {
                     // the step was not launched: its requests fail (after the
                     // steps in flight, which may use their buffers, are done)
@@ -499,6 +511,11 @@ void exec_loop(tgp_server s) {
             flights.pop_front();
             const hipError_t e = hipEventSynchronize(s->done_ev[f.b]);
             if (e != hipSuccess) hipStreamSynchronize(s->exec_stream);
+            float ms = 0;
+            if (e == hipSuccess && hipEventElapsedTime(&ms, s->begin_ev[f.b], s->done_ev[f.b]) == hipSuccess) {
+                std::lock_guard<std::mutex> lk(s->m);
+                s->stats.step_ms += ms;
+            }
             for (auto &it : f.items)
                 if (it.second || e != hipSuccess) {
                     if (!it.first->finished) retire(s, *it.first, e);
@@ -528,22 +545,29 @@ tgp_status tgp_server_create(tgp_ctx ctx, size_t cache_budget_bytes, int32_t max
     budget = budget / (kUnitFloats * 4) * (kUnitFloats * 4);
     if (budget / (kUnitFloats * 4) > 0x7fffffffull) return fail(ctx, TGP_EINVAL, "cache budget above 512 GiB");
     auto cleanup = [&](tgp_server_s *p) {
-        if (p->prep) tgp_ctx_destroy(p->prep);
+        for (auto &c : p->prep)
+            if (c) tgp_ctx_destroy(c);
         for (auto &b : p->batch)
             if (b) tgp_batch_destroy(b);
         if (p->exec) tgp_ctx_destroy(p->exec);
         for (auto &e : p->done_ev)
             if (e) hipEventDestroy(e);
-        if (p->prep_stream) hipStreamDestroy(p->prep_stream);
+        for (auto &e : p->begin_ev)
+            if (e) hipEventDestroy(e);
+        for (auto &q : p->prep_stream)
+            if (q) hipStreamDestroy(q);
         if (p->exec_stream) hipStreamDestroy(p->exec_stream);
         if (p->copy_stream) hipStreamDestroy(p->copy_stream);
         if (p->arena) hipFree(p->arena);
     };
-    hipError_t e = hipStreamCreate(&s->prep_stream);
-    if (e == hipSuccess) e = hipStreamCreate(&s->exec_stream);
+    hipError_t e = hipStreamCreate(&s->exec_stream);
+    for (int i = 0; i < kPrepThreads && e == hipSuccess; ++i) e = hipStreamCreate(&s->prep_stream[i]);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
     if (e == hipSuccess && budget) e = hipMalloc((void **)&s->arena, budget);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&s->done_ev[i], hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventCreate(&s->done_ev[i]);
+        if (e == hipSuccess) e = hipEventCreate(&s->begin_ev[i]);
+    }
     if (e != hipSuccess) {
         cleanup(s.get());
         return fail(ctx, e == hipErrorOutOfMemory ? TGP_ENOMEM : TGP_EHIP, "server setup: %s",
@@ -551,26 +575,31 @@ tgp_status tgp_server_create(tgp_ctx ctx, size_t cache_budget_bytes, int32_t max
     }
     s->arena_bytes = budget;
     s->cache.reset(new SubtreeCache(budget / (kUnitFloats * 4)));
-    tgp_status st = tgp_ctx_create(s->device, s->prep_stream, &s->prep);
-    if (st == TGP_OK) st = tgp_ctx_create(s->device, s->exec_stream, &s->exec);
+    tgp_status st = tgp_ctx_create(s->device, s->exec_stream, &s->exec);
+    for (int i = 0; i < kPrepThreads && st == TGP_OK; ++i)
+        st = tgp_ctx_create(s->device, s->prep_stream[i], &s->prep[i]);
     for (int i = 0; i < 2 && st == TGP_OK; ++i) st = tgp_batch_create(s->exec, 1, &s->batch[i]);
     if (st != TGP_OK) {
         cleanup(s.get());
         return fail(ctx, st, "server setup: %s", tgp_last_error(nullptr));
     }
-    for (tgp_ctx c : {s->prep, s->exec}) {
+    std::vector<tgp_ctx> all(s->prep, s->prep + kPrepThreads);
+    all.push_back(s->exec);
+    for (tgp_ctx c : all) {
         c->reorder = ctx->reorder;
         c->cache_access_cost = ctx->cache_access_cost;
         c->force_K = ctx->force_K;
         c->tile_cap = ctx->tile_cap;
         c->batch_persistent = ctx->batch_persistent;
     }
-    s->prep->plan_upload = false;
-    s->prep->cache_budget = budget;
+    for (tgp_ctx c : s->prep) {
+        c->plan_upload = false;
+        c->cache_budget = budget;
+    }
     s->K = s->exec->force_K && interp_variant_exists(s->exec->force_K, interp_max_stack()) ? s->exec->force_K : 4;
     s->stats.bytes_capacity = (int64_t)budget;
     tgp_server raw = s.release();
-    raw->prep_thr = std::thread(prep_loop, raw);
+    for (int i = 0; i < kPrepThreads; ++i) raw->prep_thr[i] = std::thread(prep_loop, raw, i);
     raw->exec_thr = std::thread(exec_loop, raw);
     *out = raw;
     return TGP_OK;
@@ -584,7 +613,7 @@ void tgp_server_destroy(tgp_server s) {
     }
     s->cv_prep.notify_all();
     s->cv_done.notify_all();
-    s->prep_thr.join();
+    for (auto &t : s->prep_thr) t.join();
     {
         std::lock_guard<std::mutex> lk(s->m);
         s->stop_exec = true;
@@ -593,10 +622,11 @@ void tgp_server_destroy(tgp_server s) {
     s->exec_thr.join();
     hipSetDevice(s->device);
     for (auto &b : s->batch) tgp_batch_destroy(b);
-    tgp_ctx_destroy(s->prep);
+    for (tgp_ctx c : s->prep) tgp_ctx_destroy(c);
     tgp_ctx_destroy(s->exec);
     for (auto &e : s->done_ev) hipEventDestroy(e);
-    hipStreamDestroy(s->prep_stream);
+    for (auto &e : s->begin_ev) hipEventDestroy(e);
+    for (hipStream_t q : s->prep_stream) hipStreamDestroy(q);
     hipStreamDestroy(s->exec_stream);
     hipStreamDestroy(s->copy_stream);
     if (s->pin_out) hipHostFree(s->pin_out);
@@ -609,6 +639,14 @@ tgp_status tgp_server_set_slab_work(tgp_server s, double node_evals) {
     if (!s || !(node_evals >= 1.0)) return srv_fail(s, TGP_EINVAL, "bad slab work");
     std::lock_guard<std::mutex> lk(s->m);
     s->slab_work = node_evals;
+    return TGP_OK;
+}
+
+tgp_status tgp_server_set_launch(tgp_server s, int32_t persistent, int32_t tiles_per_item) {
+    if (!s || tiles_per_item < 0) return srv_fail(s, TGP_EINVAL, "bad launch shape");
+    std::lock_guard<std::mutex> lk(s->m);
+    if (persistent >= 0) s->persistent = persistent != 0;
+    s->tiles = tiles_per_item;
     return TGP_OK;
 }
 
@@ -705,6 +743,7 @@ tgp_status tgp_server_ticket_info(tgp_server s, int64_t ticket, tgp_ticket_info 
     t.start_ms = r.t_start;
     t.done_ms = r.t_done;
     t.latency_ms = r.finished ? r.t_done - r.t_submit : 0.0;
+    t.prep_ms = r.prep_ms;
     t.dag_nodes = r.dag_nodes;
     t.credited_node_evals = r.dag_nodes * (r.dom ? r.dom->cases : 0);
     t.cache_hits = r.hits;

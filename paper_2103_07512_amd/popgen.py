@@ -562,6 +562,46 @@ def workload_c4(seed: int = 10, n_pops: int = 64):
     return out
 
 
+@dataclass
+class RunSpec:
+    """One GP run of the serving workload: its domain, first population,
+    target, and the seeds of its breeding and of its think times."""
+    run: int
+    shape: tuple
+    size: int
+    pop_seed: int
+    target: TargetSpec
+    breed_seed: int
+    think_seed: int
+    max_depth: int = 12
+
+    def first_population(self) -> Population:
+        return ramped_half_and_half(self.size, 2, 6, self.pop_seed, F18, len(self.shape))
+
+
+def workload_c5(seed: int = 11, n_runs: int = 16):
+    """Concurrent GP runs sending one population per generation.
+
+    Run r: grid side 512, 1024, 2048 or 4096 (n_runs / 4 runs each, in that
+    order), population size round(exp(U[ln 200, ln 2000])) fixed for the run,
+    generation 0 by ramped half-and-half depths 2-6 over the 18-operator set,
+    later generations bred from the returned fitness (tournament of 3,
+    crossover 0.8 / mutation 0.1 / copy 0.1, depth <= 12), target a full
+    depth-4 tree, RMSE.
+    """
+    rng = Rng(seed)
+    sides = (512, 1024, 2048, 4096)
+    per = max(1, n_runs // len(sides))
+    out = []
+    for r in range(n_runs):
+        side = sides[min(r // per, len(sides) - 1)]
+        size = int(round(math.exp(math.log(200) + rng.uniform() * (math.log(2000) - math.log(200)))))
+        base = seed * 1000 + 4 * r
+        out.append(RunSpec(r, (side, side), size, base, TargetSpec(4, base + 1, F18, 2, 1), base + 2,
+                           base + 3))
+    return out
+
+
 # The first generation of neutral breeding (seed 4 on the seed-3 start) at
 # which the 500-tree population shares 30-60% of its internal nodes; chosen
 # once and checked by a CPU test.

@@ -103,7 +103,8 @@ class TicketInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("slabs", ctypes.c_int32),
                 ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
                 ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
-                ("latency_ms", ctypes.c_double), ("dag_nodes", ctypes.c_int64),
+                ("latency_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
+                ("dag_nodes", ctypes.c_int64),
                 ("credited_node_evals", ctypes.c_int64), ("cache_hits", ctypes.c_int32),
                 ("cache_new", ctypes.c_int32)]
 
@@ -115,7 +116,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "completed", "failed", "steps", "slabs", "cache_hits", "cache_new",
         "evictions", "entries", "bytes_in_use", "bytes_peak", "bytes_capacity",
-        "credited_node_evals")] + [("max_active_seen", ctypes.c_int32), ("pad", ctypes.c_int32)]
+        "credited_node_evals")] + [("max_active_seen", ctypes.c_int32), ("pad", ctypes.c_int32),
+                                   ("step_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_ if n != "pad"}
@@ -152,6 +154,7 @@ SIGNATURES = [
     ("tgp_server_create", I32, [P, ctypes.c_size_t, I32, PP]),
     ("tgp_server_destroy", None, [P]),
     ("tgp_server_set_slab_work", I32, [P, ctypes.c_double]),
+    ("tgp_server_set_launch", I32, [P, I32, I32]),
     ("tgp_server_submit", I32, [P, I64, ctypes.POINTER(_Population), P, P, I32, P,
                                 ctypes.POINTER(I64)]),
     ("tgp_server_wait", I32, [P, I64, I64]),
@@ -427,6 +430,9 @@ class Server:
 
     def set_slab_work(self, node_evals: float):
         self._check(lib().tgp_server_set_slab_work(self.h, float(node_evals)))
+
+    def set_launch(self, persistent: int = -1, tiles_per_item: int = 0):
+        self._check(lib().tgp_server_set_launch(self.h, persistent, tiles_per_item))
 
     def submit(self, run_id: int, pop, domain: Domain, target, loss: int = RMSE, out=None):
         """Queue pop (popgen.Population or (tokens, offsets, n_ind, n_ch)); returns the ticket.
