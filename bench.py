@@ -178,6 +178,32 @@ def bench_c4(args):
     print(json.dumps(line), flush=True)
 
 
+def kernel_source_hash():
+    """Hash of the sources that make up the fused interpreter kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_interp.hip", "interp_gen.inc", "ops_device.h", "tgp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2103_07512_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per fitness launch from the committed counter summary, when
+    it was taken on the kernel as it is now (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_interp_c3_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("TRAFFIC "):
+                rec = json.loads(ln[len("TRAFFIC "):])
+    if not rec or rec.get("kernel_source") != kernel_source_hash():
+        return None
+    return {"bytes_per_launch": rec["bytes_per_launch"], "source": "profiles/k_interp_c3_hbm_traffic.md"}
+
+
 def serve_c5(generations, loads, with_plain, warm_generations=2, log=None, configure=None):
     """The serving workload: 16 GP runs, one request per generation each.
 
@@ -359,6 +385,11 @@ def main():
     ap.add_argument("--generations", type=int, default=20, help="serving workload: generations per run")
     ap.add_argument("--loads", default="0.5,0.7,0.9", help="serving workload: offered loads")
     ap.add_argument("--no-plain", action="store_true", help="serving workload: skip the plain pass")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="default workload: skip the short serving run that gives p50/p99 latency")
+    ap.add_argument("--latency-generations", type=int, default=6)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build evaluates a population on a single MI355X "
@@ -452,6 +483,27 @@ def main():
             "finite_fitness": int(np.isfinite(fit).sum()),
         },
     }
+    if args.calibrate_copy:
+        # A copy of known size for scaling the FETCH_SIZE / WRITE_SIZE counters.
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    traffic = recorded_traffic()
+    if traffic is not None:
+        line["roofline"]["traffic"] = traffic["bytes_per_launch"]
+        line["roofline"]["traffic_source"] = traffic["source"]
+    if not args.no_latency:
+        res = serve_c5(args.latency_generations, [0.7], False)
+        lo = res["loaded"][0]
+        line["latency"] = {
+            "workload": WORKLOADS["c5"] + f"; {args.latency_generations} generations per run, "
+                        f"the first 2 not counted",
+            "offered_load": 0.7, "p50_ms": lo["p50_ms"], "p99_ms": lo["p99_ms"],
+            "requests": lo["requests"], "served_node_evals_per_s_at_capacity":
+                res["capacity"]["node_evals_per_s"],
+            "same_as_closed_loop": lo["same_as_closed_loop"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pop, dspec, stats["dag_nodes"])
     print(json.dumps(line), flush=True)

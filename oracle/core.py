@@ -16,27 +16,30 @@ NONFINITE_STABLE = 2   # every FP32 variant gives the same non-finite class
 
 _TOKEN = np.dtype([("op", "u1"), ("var", "u1"), ("pad", "<u2"), ("value", "<f4")])
 _lib = None
+# A test that plants a mistake in a copy of oracle.c points this at the
+# mutant's library (the pins must then fail).
+_OVERRIDE = os.environ.get("TGP_ORACLE_LIBRARY")
 
 
 def library_path() -> str:
-    return _LIB
+    return _OVERRIDE or _LIB
 
 
-def build() -> str:
-    """Compile oracle.c with gcc (plain -O2, no fast-math, OpenMP)."""
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    """Compile oracle.c (or a copy of it) with gcc (plain -O2, no fast-math, OpenMP)."""
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-Wall", _SRC, "-o", _LIB + ".tmp", "-lm"]
+           "-shared", "-Wall", src, "-o", out + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not _OVERRIDE and not os.path.exists(_LIB):
             build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(library_path())
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         lib.orc_eval.argtypes = [P, P, i64, ctypes.c_int, P, P, P, P, i64, P, P, P, P, ctypes.c_int]

@@ -1,0 +1,62 @@
+"""The oracle's pins must catch plausible mistakes: each test plants one
+mistake (a swapped operand, a dropped term, a wrong sign or protection) in a
+copy of oracle.c, builds it on the CPU, and runs the pin suite
+(tests/test_oracle.py) against it in a fresh process; the suite must fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import core
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "oracle.c")
+
+MUTANTS = [
+    ("sub operands swapped", "case OV_SUB: return a - b;", "case OV_SUB: return b - a;"),
+    ("div protection gives 1", "return b == 0.0 ? 0.0 : a / b;", "return b == 0.0 ? 1.0 : a / b;"),
+    ("sin and cos swapped", "case OV_SIN: sincospi64(a, &s, &co); return s;",
+     "case OV_SIN: sincospi64(a, &s, &co); return co;"),
+    ("pi prescale dropped", "double st = sin(M_PI * t), ct = cos(M_PI * t);",
+     "double st = sin(t), ct = cos(t);"),
+    ("log protection value", "return a < 0.0 ? -1.0 : log(a);", "return a < 0.0 ? 0.0 : log(a);"),
+    ("pow(0, 0) = 1", "return (a == 0.0 && b == 0.0) ? 0.0 : pow(a, b);",
+     "return (a == 0.0 && b == 0.0) ? 1.0 : pow(a, b);"),
+    ("mod truncated", "if (r != 0.0 && ((r < 0.0) != (y < 0.0)))", "if (0)"),
+    ("clip bounds swapped", "case OV_CLIP: return fmax(fmin(a, c), b);",
+     "case OV_CLIP: return fmax(fmin(a, b), c);"),
+    ("mdist not halved", "case OV_MDIST: return (a + b) / 2.0;", "case OV_MDIST: return (a + b);"),
+    ("sstepp term dropped", "return a * a * a * (a * (6.0 * a - 15.0) + 10.0);",
+     "return a * a * a * (a * (6.0 * a - 15.0));"),
+    ("sign flipped", "return (double)((a > 0.0) - (a < 0.0));", "return (double)((a < 0.0) - (a > 0.0));"),
+    ("sqrt protection", "return a < 0.0 ? 0.0 : sqrt(a);", "return a < 0.0 ? sqrt(-a) : sqrt(a);"),
+    ("grid endpoint", "lo + (hi - lo) * (double)i / (double)(n - 1)", "lo + (hi - lo) * (double)i / (double)n"),
+    ("rmse without the root", "(loss == 0 ? sqrt(s / N) : s / N)", "(loss == 0 ? s / N : s / N)"),
+]
+
+
+def _run_pins(tmp_path, text):
+    src = tmp_path / "oracle_copy.c"
+    src.write_text(text)
+    lib = core.build(str(src), str(tmp_path / "liboracle_copy.so"))
+    env = dict(os.environ, TGP_ORACLE_LIBRARY=lib)
+    return subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                           os.path.join(HERE, "test_oracle.py")], env=env, capture_output=True,
+                          text=True, timeout=600)
+
+
+def test_unmodified_copy_passes(tmp_path):
+    """Control: the same procedure on an unmodified copy passes every pin."""
+    with open(SRC) as f:
+        r = _run_pins(tmp_path, f.read())
+    assert r.returncode == 0, r.stdout[-3000:]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    with open(SRC) as f:
+        text = f.read()
+    assert text.count(old) == 1, f"mutation site not unique or missing: {old!r}"
+    r = _run_pins(tmp_path, text.replace(old, new))
+    assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"
