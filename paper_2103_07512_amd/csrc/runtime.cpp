@@ -24,6 +24,7 @@
 #include <cmath>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -589,6 +590,41 @@ struct Planner {
     }
 };
 
+// Programs of many nodes emitted by a few host threads (emission only reads
+// the planner's decisions); each node's code stays contiguous, in order.
+struct Emitted {
+    uint32_t off, len;
+    int64_t reads;
+    double valu;
+};
+
+void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<uint2> &code,
+              std::vector<Emitted> &out) {
+    const size_t n = nodes.size();
+    out.assign(n, Emitted{0, 0, 0, 0.0});
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = n < 512 ? 1 : (int)std::min<unsigned>(8, hw);
+    std::vector<std::vector<uint2>> local(T);
+    auto work = [&](int t) {
+        const size_t b = n * t / T, e = n * (t + 1) / T;
+        for (size_t i = b; i < e; ++i) {
+            Emitted &m = out[i];
+            m.off = (uint32_t)local[t].size();
+            pl.emit(nodes[i], local[t], m.reads, &m.valu);
+            m.len = (uint32_t)(local[t].size() - m.off);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+    for (int t = 0; t < T; ++t) {
+        const uint32_t base = (uint32_t)code.size();
+        code.insert(code.end(), local[t].begin(), local[t].end());
+        for (size_t i = n * t / T; i < n * (t + 1) / T; ++i) out[i].off += base;
+    }
+}
+
 }  // namespace
 
 static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases);
@@ -665,14 +701,16 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     std::vector<std::vector<ProgDesc>> by_level(max_level + 1);
     int64_t cache_reads_fill = 0;
     double valu_fill = 0;
-    for (int32_t n : cached_nodes) {
-        if (pl.pre[n]) continue;
-        ProgDesc pd{};
-        pd.code_off = (uint32_t)code.size();
-        pl.emit(n, code, cache_reads_fill, &valu_fill);
-        pd.len = (uint32_t)(code.size() - pd.code_off);
-        pd.dest = pl.slot[n];
-        pd.chan = 0;
+    std::vector<int32_t> fill_nodes;
+    for (int32_t n : cached_nodes)
+        if (!pl.pre[n]) fill_nodes.push_back(n);
+    std::vector<Emitted> em;
+    emit_all(pl, fill_nodes, code, em);
+    for (size_t i = 0; i < fill_nodes.size(); ++i) {
+        const int32_t n = fill_nodes[i];
+        ProgDesc pd{em[i].off, em[i].len, pl.slot[n], 0};
+        cache_reads_fill += em[i].reads;
+        valu_fill += em[i].valu;
         by_level[pl.level[n]].push_back(pd);
     }
     auto longest_first = [](std::vector<ProgDesc> &v) {
@@ -689,14 +727,13 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     double exec_roots = 0;
     std::vector<int64_t> reads_of(U, 0);
     std::vector<double> valu_of(U, 0.0);
-    for (int32_t n : store_list) {
-        root_code[n] = (uint32_t)code.size();
-        int64_t cr = 0;
-        double v = 0;
-        pl.emit(n, code, cr, &v);
-        reads_of[n] = cr;
-        valu_of[n] = v;
-        root_len[n] = (uint32_t)(code.size() - root_code[n]);
+    emit_all(pl, store_list, code, em);
+    for (size_t i = 0; i < store_list.size(); ++i) {
+        const int32_t n = store_list[i];
+        root_code[n] = em[i].off;
+        root_len[n] = em[i].len;
+        reads_of[n] = em[i].reads;
+        valu_of[n] = em[i].valu;
     }
     double valu_roots = 0;
     for (size_t p = 0; p < reduce_list.size(); ++p) {
