@@ -448,6 +448,25 @@ def main():
     work = ctx.last_work()
     fit = out.cpu().numpy()
 
+    # Evaluation only (DAG and plan kept from the last step) and end to end
+    # (host tokens in, host fitness out, PCIe copies included).
+    dag = tgp.Dag(ctx, tok_dev, off_dev, pop.n_individuals, pop.n_channels)
+    tgp.fitness(ctx, dag, dom, target_dev, loss, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        tgp.fitness(ctx, dag, dom, target_dev, loss, out)
+    torch.cuda.synchronize()
+    eval_only_ms = (time.perf_counter() - t1) / args.steps * 1e3
+    dag.close()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        d2 = tgp.Dag(ctx, pop.tokens, pop.offsets, pop.n_individuals, pop.n_channels)
+        tgp.fitness(ctx, d2, dom, target_dev, loss, out)
+        host_fit = out.cpu().numpy()
+        d2.close()
+    end_to_end_ms = (time.perf_counter() - t1) / args.steps * 1e3
+
     ms = wall / args.steps * 1e3
     credited = stats["dag_nodes"] * dom.cases
     value = credited / (ms / 1e3)
@@ -480,6 +499,9 @@ def main():
             "launch": {k: times[-1][k] for k in ("interp_items", "cases_per_lane", "tiles_per_item")},
             "work": work,
             "executed_node_evals_per_s": work["executed_node_evals"] / (ms / 1e3),
+            "eval_only_ms": eval_only_ms,
+            "end_to_end_host_ms": end_to_end_ms,
+            "end_to_end_host_node_evals_per_s": stats["dag_nodes"] * dom.cases / (end_to_end_ms / 1e3),
             "finite_fitness": int(np.isfinite(fit).sum()),
         },
     }
