@@ -81,7 +81,14 @@ enum tgp_opcode {
     TGP_SSTEPP = 25,/* [1] x^3 (x (6x - 15) + 10) */
     TGP_LEN = 26,   /* [2] sqrt(x^2 + y^2) without intermediate overflow */
     TGP_LERP = 27,  /* [3] x + (y - x) frac(z) */
-    TGP_NUM_OPS = 28
+    /* The bitwise operators of Table 1 (listed there under Logic), appended
+     * here.  Each operand is first converted to a 32-bit integer: NaN gives
+     * 0, other values are truncated toward zero and saturated to
+     * [-2^31, 2^31 - 1]; the integer result is rounded to FP32. */
+    TGP_OR = 28,    /* [2] int(x) | int(y) */
+    TGP_XOR = 29,   /* [2] int(x) ^ int(y) */
+    TGP_AND = 30,   /* [2] int(x) & int(y) */
+    TGP_NUM_OPS = 31
 };
 
 /* One tree node.  Trees are postfix (children before parent, left to right).

@@ -41,6 +41,9 @@
  *   frac(x) = x - floor(x); if(x, y, z) = x != 0 ? y : z (NaN counts true);
  *   tan(x) = sin(pi x) / cos(pi x) with IEEE division;
  *   len(x, y) = the exact sqrt(x^2 + y^2) (hypot);
+ *   or/xor/and act on 32-bit integers made from the operands by truncation
+ *   toward zero with saturation (NaN gives 0), as Table 1's footnote asks
+ *   for a conversion to integers;
  *   coordinate k along an axis of n points is the FP32 rounding of
  *   lo + (hi - lo) * k / (n - 1) computed in FP64 (lo when n == 1),
  *   axes row-major with the last axis fastest; axis 0 is x, 1 is y, 2 is z.
@@ -70,6 +73,7 @@ enum {
     OV_SQRT, OV_SIGN, OV_ABS, OV_CLIP,
     OV_MOD, OV_FRAC, OV_IF,
     OV_STEP, OV_SSTEP, OV_SSTEPP, OV_LEN, OV_LERP,
+    OV_OR, OV_XOR, OV_AND,
     OV_COUNT
 };
 
@@ -82,6 +86,7 @@ static const int orc_arity[OV_COUNT] = {
     1, 1, 1, 3,
     2, 1, 3,
     1, 1, 1, 2, 3,
+    2, 2, 2,
 };
 
 #define ORC_MAX_DIM 3
@@ -186,6 +191,19 @@ static double floor_mod(double x, double y)
     return r;
 }
 
+/* The integer a bitwise operator works on: NaN gives 0, other values are
+ * truncated toward zero and saturated to the 32-bit range. */
+static int32_t to_i32(double x)
+{
+    if (isnan(x))
+        return 0;
+    if (x >= 2147483648.0)
+        return INT32_MAX;
+    if (x <= -2147483649.0)
+        return INT32_MIN;
+    return (int32_t)trunc(x);
+}
+
 static int is_integral(double v)
 {
     return isfinite(v) && floor(v) == v;
@@ -254,6 +272,13 @@ static double apply(int op, double a, double b, double c, double *br)
     case OV_LERP:
         *br = isfinite(c) ? floor(c) : -1.0;
         return a + (b - a) * (c - floor(c));
+    case OV_OR:
+    case OV_XOR:
+    case OV_AND: {
+        const int32_t ia = to_i32(a), ib = to_i32(b);
+        *br = (double)ia * 4294967296.0 + (double)(uint32_t)ib;
+        return (double)(op == OV_OR ? (ia | ib) : (op == OV_XOR ? (ia ^ ib) : (ia & ib)));
+    }
     }
     return NAN;
 }
@@ -467,6 +492,14 @@ static void evb(const onode *n, int32_t i, const double *xyz, double *v, double 
         err = contrib(1.0 - fz, ea) + contrib(fz, eb) + contrib(b - a, ec) + U_LIB * av;
         break;
     }
+    case OV_OR:
+    case OV_XOR:
+    case OV_AND:
+        /* truncation jumps at every non-zero integer */
+        if (ea != 0.0 && fabs(rint(a)) >= 1.0 && dist_to_int(a) <= MARGIN * ea) *ok = 0;
+        if (eb != 0.0 && fabs(rint(b)) >= 1.0 && dist_to_int(b) <= MARGIN * eb) *ok = 0;
+        err = U_CR * av;
+        break;
     }
     if (!isfinite(val))
         err = 0.0;   /* an exact special value; its class is checked instead */

@@ -42,6 +42,7 @@ FUNCS = [
     ("sqrt", 16, 1), ("sign", 17, 1), ("abs", 18, 1), ("clip", 19, 3),
     ("mod", 20, 2), ("frac", 21, 1), ("if", 22, 3),
     ("step", 23, 1), ("sstep", 24, 1), ("sstepp", 25, 1), ("len", 26, 2), ("lerp", 27, 3),
+    ("or", 28, 2), ("xor", 29, 2), ("and", 30, 2),
 ]
 FN_BASE = 8
 REV_BASE = 40
@@ -51,6 +52,10 @@ TERNARY = ("clip", "if", "lerp")
 PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
 # Operators compiled once, out of line.
 CALLED = {"sin", "cos", "tan", "exp", "log", "pow", "mod", "sstep", "sstepp", "len", "lerp"}
+# The bitwise operators share one opcode (that of "or"); the instruction's
+# bits 8-9 say which (0 or, 1 xor, 2 and).  They are compiled only into the
+# interpreters instantiated with BIT = true.
+BITWISE = ("or", "xor", "and")
 DEPTHS = [8]
 ARGS = "abc"
 
@@ -80,7 +85,7 @@ def body_for_depth(D):
     e = L.append
     e(f"// Stack of {D} register slots.  Returns when the program's I_END is reached")
     e(f"// at depth 1 (res = the program's value); a malformed program gives NaN.")
-    e("template <int K>")
+    e("template <int K, bool BIT>")
     e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
     e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
     e("        const int32_t (&cidx)[K], FV<K> &res)")
@@ -115,6 +120,8 @@ def body_for_depth(D):
             e("    case I_END: res = s0; return;")
         variants = []
         for name, op, ar in FUNCS:
+            if name in BITWISE[1:]:
+                continue
             variants.append((FN_BASE + op, name, ar, tuple(range(ar))))
             if name in REVERSIBLE:
                 variants.append((REV_BASE + op, name, ar, (1, 0)))
@@ -129,7 +136,19 @@ def body_for_depth(D):
             dst = S - ar
             # child i was evaluated order.index(i)-th, so it sits in slot dst + that position
             src = [f"s{dst + order.index(i)}" for i in range(ar)]
-            if name in CALLED:
+            if name == BITWISE[0]:
+                # only in the interpreters built with BIT (the others are
+                # never given programs that use these operators)
+                e(f"    case {c}:")
+                e("        if constexpr (BIT) {")
+                e("            const uint32_t kind = (ins.x >> 8) & 3u;")
+                e("#pragma unroll")
+                e(f"            for (int k = 0; k < K; ++k) s{dst}.v[k] = f_bitop({src[0]}.v[k], {src[1]}.v[k], kind);")
+                e(f"            goto L{dst + 1};")
+                e("        } else {")
+                e("            goto BAD;")
+                e("        }")
+            elif name in CALLED:
                 e(f"    case {c}: s{dst} = vcall_{name}<K>({', '.join(src)}); goto L{dst + 1};")
             else:
                 e(f"    case {c}:")

@@ -27,8 +27,7 @@
 
 namespace tgp {
 
-__constant__ int8_t c_arity[TGP_NUM_OPS] = {
-    0, 0, 2, 2, 2, 2, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 1, 1, 1, 3, 2, 1, 3, 1, 1, 1, 2, 3};
+__constant__ int8_t c_arity[TGP_NUM_OPS] = {TGP_ARITY_LIST};
 
 struct BuildStatus {
     unsigned long long first_error;  // (tree << 4) | code, min over trees; ~0 = none

@@ -60,16 +60,16 @@ __device__ __forceinline__ void kahan_merge(float &s, float &c, float s2, float 
     s = t;
 }
 
-template <int K, int D>
+template <int K, int D, bool BIT>
 __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const FV<K> &yv,
                                          const FV<K> &zv, const float *cache, int64_t cache_stride,
                                          const int32_t (&cidx)[K], FV<K> &res) {
     static_assert(D == 8, "compiled stack size: 8");
-    run_prog_d8<K>(ip, xv, yv, zv, cache, cache_stride, cidx, res);
+    run_prog_d8<K, BIT>(ip, xv, yv, zv, cache, cache_stride, cidx, res);
 }
 
 // One work item: program `code` over tiles_per_stripe tiles of one stripe.
-template <int K, int D, int MODE>
+template <int K, int D, int MODE, bool BIT>
 __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, int32_t dest, int32_t chan,
                                          uint32_t stripe, int lane) {
     const int32_t n = a.n_cases;
@@ -111,7 +111,7 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
             }
         }
         FV<K> res;
-        run_prog<K, D>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, res);
+        run_prog<K, D, BIT>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, res);
         if constexpr (MODE == MODE_STORE) {
             float *row = a.out + (size_t)dest * (size_t)a.out_stride;
 #pragma unroll
@@ -138,13 +138,13 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
     }
 }
 
-template <int K, int D, int MODE>
+template <int K, int D, int MODE, bool BIT>
 __global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
     const uint32_t item = blockIdx.x;
     const uint32_t p = item / (uint32_t)a.job.n_stripes;
     const uint32_t stripe = item - p * (uint32_t)a.job.n_stripes;
     const ProgDesc pd = a.progs[p];
-    run_item<K, D, MODE>(a.job, a.job.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
+    run_item<K, D, MODE, BIT>(a.job, a.job.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
 }
 
 // Batched interpreter, two launch forms over the work items of group g
@@ -187,7 +187,7 @@ __device__ __forceinline__ uint32_t find_pair(const uint32_t *__restrict__ item_
     return lo;
 }
 
-template <int K, int D, int MODE>
+template <int K, int D, int MODE, bool BIT>
 __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
                                               const PairDesc *__restrict__ pairs,
                                               const uint32_t *__restrict__ item_first,
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
                 const PairDesc pd = load_const(pairs + lo);
                 const JobDesc jd = load_const(jobs + pd.job);
                 const uint32_t stripe = item - load_const_u32(item_first + lo);
-                run_item<K, D, MODE>(jd, jd.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
+                run_item<K, D, MODE, BIT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
             }
         }
     }
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
 
 // Direct form: one wave per item (grid = the group's item count, or more);
 // the hardware dispatcher hands out the waves in item order.
-template <int K, int D, int MODE>
+template <int K, int D, int MODE, bool BIT>
 __global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__ jobs,
                                                      const PairDesc *__restrict__ pairs,
                                                      const uint32_t *__restrict__ item_first,
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__
     const uint32_t lo = find_pair(item_first, gd.pair_begin, gd.pair_end, item);
     const PairDesc pd = load_const(pairs + lo);
     const JobDesc jd = load_const(jobs + pd.job);
-    run_item<K, D, MODE>(jd, jd.code + pd.code_off, pd.dest, pd.chan, item - load_const_u32(item_first + lo),
+    run_item<K, D, MODE, BIT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, item - load_const_u32(item_first + lo),
                          threadIdx.x);
 }
 
@@ -313,43 +313,44 @@ __global__ __launch_bounds__(256) void k_finalize_batch(const FinJob *jobs, cons
 }
 
 // ------------------------------------------------------------- launchers
-template <int K, int D>
+template <int K, int D, bool BIT>
 static hipError_t launch_kd(bool store, const InterpArgs &a, hipStream_t s) {
     const uint32_t items = (uint32_t)a.n_progs * (uint32_t)a.job.n_stripes;
     if (items == 0) return hipSuccess;
     if (store)
-        hipLaunchKernelGGL((k_interp<K, D, MODE_STORE>), dim3(items), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_interp<K, D, MODE_STORE, BIT>), dim3(items), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_interp<K, D, MODE_REDUCE>), dim3(items), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_interp<K, D, MODE_REDUCE, BIT>), dim3(items), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
-template <int K, int D>
+template <int K, int D, bool BIT>
 static const void *batch_fn(bool store, bool persistent) {
     if (persistent)
-        return store ? (const void *)k_batch<K, D, MODE_STORE> : (const void *)k_batch<K, D, MODE_REDUCE>;
-    return store ? (const void *)k_batch_direct<K, D, MODE_STORE>
-                 : (const void *)k_batch_direct<K, D, MODE_REDUCE>;
+        return store ? (const void *)k_batch<K, D, MODE_STORE, BIT> : (const void *)k_batch<K, D, MODE_REDUCE, BIT>;
+    return store ? (const void *)k_batch_direct<K, D, MODE_STORE, BIT>
+                 : (const void *)k_batch_direct<K, D, MODE_REDUCE, BIT>;
 }
 
-template <int K, int D>
+template <int K, int D, bool BIT>
 static int grid_bd(bool store) {
     int per_cu = 0, dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (store)
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_STORE>, 64, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_STORE, BIT>, 64, 0);
     else
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_REDUCE>, 64, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_REDUCE, BIT>, 64, 0);
     return std::max(1, per_cu) * std::max(1, cus);
 }
 
+// Instantiated interpreters: (cases per lane, stack slots, bitwise operators).
 #ifndef TGP_VARIANTS
-#define TGP_VARIANTS(X) X(4, 8) X(2, 8)
+#define TGP_VARIANTS(X) X(4, 8, false) X(2, 8, false) X(4, 8, true)
 #endif
 
-bool interp_variant_exists(int K, int D) {
-#define X(k, d) if (K == k && D == d) return true;
+bool interp_variant_exists(int K, int D, bool bit) {
+#define X(k, d, b) if (K == k && D == d && bit == b) return true;
     TGP_VARIANTS(X)
 #undef X
     return false;
@@ -357,22 +358,22 @@ bool interp_variant_exists(int K, int D) {
 
 int interp_max_stack() { return 8; }
 
-hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s) {
-#define X(k, d) if (K == k && D == d) return launch_kd<k, d>(store, a, s);
+hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s, bool bit) {
+#define X(k, d, b) if (K == k && D == d && bit == b) return launch_kd<k, d, b>(store, a, s);
     TGP_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-const void *batch_kernel(int K, int D, bool store, bool persistent) {
-#define X(k, d) if (K == k && D == d) return batch_fn<k, d>(store, persistent);
+const void *batch_kernel(int K, int D, bool store, bool persistent, bool bit) {
+#define X(k, d, b) if (K == k && D == d && bit == b) return batch_fn<k, d, b>(store, persistent);
     TGP_VARIANTS(X)
 #undef X
     return nullptr;
 }
 
-int batch_grid(int K, int D, bool store) {
-#define X(k, d) if (K == k && D == d) return grid_bd<k, d>(store);
+int batch_grid(int K, int D, bool store, bool bit) {
+#define X(k, d, b) if (K == k && D == d && bit == b) return grid_bd<k, d, b>(store);
     TGP_VARIANTS(X)
 #undef X
     return 0;

@@ -66,5 +66,19 @@ __device__ __forceinline__ float f_lerp(float a, float b, float c) {
     double x = a, y = b, z = c;
     return (float)(x + (y - x) * (z - floor(z)));
 }
+// Bitwise operators: each operand becomes a 32-bit integer (NaN -> 0,
+// truncation toward zero, saturation to the int32 range), the integer result
+// is rounded to FP32; kind 0: or, 1: xor, 2: and.
+__device__ __forceinline__ int32_t to_i32(float a) {
+    if (!(a == a)) return 0;
+    if (a >= 2147483648.0f) return 2147483647;
+    if (a <= -2147483648.0f) return -2147483647 - 1;
+    return (int32_t)a;
+}
+__device__ __forceinline__ float f_bitop(float a, float b, uint32_t kind) {
+    const int32_t x = to_i32(a), y = to_i32(b);
+    const int32_t r = kind == 0 ? (x | y) : (kind == 1 ? (x ^ y) : (x & y));
+    return (float)r;
+}
 
 }  // namespace tgp

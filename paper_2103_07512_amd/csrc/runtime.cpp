@@ -90,7 +90,8 @@ const double kOpCost[TGP_NUM_OPS] = {
     3,  3,  3,  1,   // min max mdist neg
     11, 4,  1,  6,   // sqrt sign abs clip
     40, 2,  3,       // mod frac if
-    2,  9,  12, 16, 14  // step sstep sstepp len lerp
+    2,  9,  12, 16, 14, // step sstep sstepp len lerp
+    7,  7,  7           // or xor and
 };
 // Writing a cache row once and reading it back, in VALU-slot equivalents per
 // case: 4 bytes of HBM traffic at 8 TB/s against 256 CUs x 64 lanes x 2.4 GHz
@@ -575,6 +576,8 @@ struct Planner {
                 } else if (o == TGP_CONST) {
                     ins.x = I_CONST;
                     memcpy(&ins.y, &d.value[n], 4);
+                } else if (o == TGP_OR || o == TGP_XOR || o == TGP_AND) {
+                    ins.x = (kFnBase + TGP_OR) | ((uint32_t)(o - TGP_OR) << 8);
                 } else if (perm[n] == 0 || (kArity[o] == 2 && is_commutative(o))) {
                     ins.x = kFnBase + o;
                 } else if (kArity[o] == 2) {
@@ -763,6 +766,12 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.valu_roots_per_case = valu_roots;
     P.cache_reads_per_case = cache_reads_fill + cache_reads_roots;
     P.instructions = (int64_t)code.size();
+    P.bitwise = false;
+    for (const uint2 &ins : code)
+        if ((ins.x & 0xffu) == kFnBase + TGP_OR) {
+            P.bitwise = true;
+            break;
+        }
     P.n_slots = (int32_t)cached_nodes.size();
     P.n_spills = pl.spills;
     P.n_fill = (int32_t)fill.size();
@@ -832,7 +841,8 @@ void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *s
     *stripes = (int32_t)((n_tiles + tps - 1) / tps);
 }
 
-int choose_K(tgp_ctx ctx, int64_t cases) {
+int choose_K(tgp_ctx ctx, int64_t cases, bool bitwise) {
+    if (bitwise) return 4;  // the one interpreter built with the bitwise operators
     if (ctx->force_K) return ctx->force_K;
     return cases >= 64 * 4 * 4 ? 4 : 2;
 }
@@ -877,7 +887,7 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
         a.n_progs = e - b;
         choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
         a.job.out = cache;
-        HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
+        HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.bitwise));
     }
     record(ctx, 1);
     return TGP_OK;
@@ -923,7 +933,7 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     st = build_plan(ctx, d, dom->cases);
     if (st != TGP_OK) return st;
     const Plan &P = d->plan;
-    const int K = choose_K(ctx, dom->cases);
+    const int K = choose_K(ctx, dom->cases, P.bitwise);
     float *cache = nullptr;
     st = run_fill(ctx, d, dom, K, &cache);
     if (st != TGP_OK) return st;
@@ -936,7 +946,7 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.job.n_stripes));
     a.job.partial = (float2 *)ctx->partial.p;
     record(ctx, 2);
-    HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream));
+    HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream, P.bitwise));
     record(ctx, 3);
     record(ctx, 4);
     HCHK(ctx, launch_finalize(a.job.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.job.n_stripes,
@@ -958,7 +968,7 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     st = build_plan(ctx, d, dom->cases);
     if (st != TGP_OK) return st;
     const Plan &P = d->plan;
-    const int K = choose_K(ctx, dom->cases);
+    const int K = choose_K(ctx, dom->cases, P.bitwise);
     float *cache = nullptr;
     st = run_fill(ctx, d, dom, K, &cache);
     if (st != TGP_OK) return st;
@@ -969,7 +979,7 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
     a.job.out = out_dev;
     record(ctx, 2);
-    HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream));
+    HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.bitwise));
     record(ctx, 3);
     record(ctx, 4);
     record(ctx, 5);

@@ -596,7 +596,11 @@ tgp_status tgp_server_create(tgp_ctx ctx, size_t cache_budget_bytes, int32_t max
         c->plan_upload = false;
         c->cache_budget = budget;
     }
-    s->K = s->exec->force_K && interp_variant_exists(s->exec->force_K, interp_max_stack()) ? s->exec->force_K : 4;
+    // One case split for every step, whatever the requests in it: four cases
+    // per lane (the split, and so the summation order, of a request must not
+    // depend on its neighbours).
+    s->K = 4;
+    s->exec->force_K = 4;
     s->stats.bytes_capacity = (int64_t)budget;
     tgp_server raw = s.release();
     for (int i = 0; i < kPrepThreads; ++i) raw->prep_thr[i] = std::thread(prep_loop, raw, i);

@@ -12,22 +12,28 @@
 
 namespace tgp {
 
-// Arity of each public opcode (Table 1).
-constexpr int kArity[TGP_NUM_OPS] = {
-    0, 0,        // var const
-    2, 2, 2, 2,  // add sub mult div
-    1, 1, 1,     // sin cos tan
-    1, 1, 2,     // exp log pow
-    2, 2, 2, 1,  // min max mdist neg
-    1, 1, 1, 3,  // sqrt sign abs clip
-    2, 1, 3,     // mod frac if
-    1, 1, 1, 2, 3  // step sstep sstepp len lerp
-};
+// Arity of each public opcode (Table 1), shared by the host tables and the
+// device constant table of the DAG builder.
+#define TGP_ARITY_LIST                                                 \
+    0, 0,                         /* var const */                      \
+        2, 2, 2, 2,               /* add sub mult div */               \
+        1, 1, 1,                  /* sin cos tan */                    \
+        1, 1, 2,                  /* exp log pow */                    \
+        2, 2, 2, 1,               /* min max mdist neg */              \
+        1, 1, 1, 3,               /* sqrt sign abs clip */             \
+        2, 1, 3,                  /* mod frac if */                    \
+        1, 1, 1, 2, 3,            /* step sstep sstepp len lerp */     \
+        2, 2, 2                   /* or xor and */
+
+constexpr int kArityList[] = {TGP_ARITY_LIST};
+static_assert(sizeof(kArityList) / sizeof(int) == TGP_NUM_OPS, "one arity per opcode");
+constexpr int kArity[TGP_NUM_OPS] = {TGP_ARITY_LIST};
 
 // Interpreter instruction codes.  An instruction is a uint2: .x = code, .y =
 // the FP32 bits of a constant (I_CONST) or the cache row (I_CACHE: the row
 // starts cache_stride floats times .y past the job's cache base).  Function
-// opcodes are the public opcode plus kFnBase.
+// opcodes are the public opcode plus kFnBase; the three bitwise operators
+// share the code of TGP_OR, with 0 / 1 / 2 (or / xor / and) in bits 8-9.
 // Operators whose children were evaluated out of left-to-right order (to
 // bound the stack, Sethi-Ullman order) use the permuted forms: kRevBase + op
 // for a reversed non-commutative binary operator, kPermBase + 6 t + p for
@@ -44,7 +50,7 @@ constexpr uint8_t kPerms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2
 
 inline bool is_commutative(int op) {
     return op == TGP_ADD || op == TGP_MULT || op == TGP_MIN || op == TGP_MAX || op == TGP_MDIST ||
-           op == TGP_LEN;
+           op == TGP_LEN || op == TGP_OR || op == TGP_XOR || op == TGP_AND;
 }
 inline int ternary_index(int op) {
     return op == TGP_CLIP ? 0 : (op == TGP_IF ? 1 : (op == TGP_LERP ? 2 : -1));
@@ -129,19 +135,20 @@ struct Variant {
     int D;
 };
 
-hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s);
+// bit: the interpreter that also knows the bitwise operators (only K = 4).
+hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s, bool bit);
 // Batched interpreter kernels (for graph nodes): the persistent form takes
 // (jobs, pairs, item_first, groups, g, counters[groups x batch_parts()]),
 // the direct form (jobs, pairs, item_first, groups, g) with one wave per item.
-const void *batch_kernel(int K, int D, bool store, bool persistent);
-int batch_grid(int K, int D, bool store);  // resident waves of the persistent form
+const void *batch_kernel(int K, int D, bool store, bool persistent, bool bit);
+int batch_grid(int K, int D, bool store, bool bit);  // resident waves of the persistent form
 uint32_t batch_parts();
 const void *reset_kernel();           // (uint32_t *counters, int32_t n)
 const void *finalize_batch_kernel();  // (const FinJob *, const int32_t *n_jobs, const uint32_t *n_ind)
 hipError_t launch_reset(uint32_t *counters, int32_t n, hipStream_t s);
 hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
                                  int32_t grid, hipStream_t s);
-bool interp_variant_exists(int K, int D);
+bool interp_variant_exists(int K, int D, bool bit = false);
 int interp_max_stack();   // largest D compiled
 
 // Finalize: per individual, FP64 sum of its channels' partial rows.

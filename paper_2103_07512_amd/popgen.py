@@ -42,6 +42,7 @@ OPS = [
     ("sqrt", 1), ("sign", 1), ("abs", 1), ("clip", 3),
     ("mod", 2), ("frac", 1), ("if", 3),
     ("step", 1), ("sstep", 1), ("sstepp", 1), ("len", 2), ("lerp", 3),
+    ("or", 2), ("xor", 2), ("and", 2),      # bitwise (Table 1, Logic), appended
 ]
 OP_CODE = {name: i for i, (name, _) in enumerate(OPS)}
 OP_CODE["mul"] = OP_CODE["mult"]           # the configs spell it "mul"

@@ -93,6 +93,9 @@ TABLE1 = [
     ("min(pow(-0.5, 0.5), 0.5)", 0.5), ("max(0.5, pow(-0.5, 0.5))", 0.5), ("step(0.0)", 1.0),
     ("sstepp(0.5)", 0.5), ("len(0.75, 1.0)", 1.25), ("lerp(0.0, 1.0, -0.75)", 0.25),
     ("mdist(0.5, -0.25)", 0.125), ("exp(0.0)", 1.0), ("tan(0.25)", 1.0),
+    ("or(3.7, 1.2)", 3.0), ("xor(-2.5, 1.0)", -1.0), ("and(-1.0, 5.9)", 5.0),
+    ("or(pow(-0.5, 0.5), 6.0)", 6.0), ("and(exp(100.0), 1.0)", 1.0),
+    ("or(neg(exp(100.0)), 0.0)", -2147483648.0), ("xor(0.9, -0.9)", 0.0),
 ]
 
 
@@ -168,7 +171,7 @@ def test_parity_extended_ops(env):
     funcs = tuple(n for n, a in pg.OPS if a > 0)
     pop = pg.ramped_half_and_half(80, 1, 6, 61, funcs, 2)
     tgt = pg.TargetSpec(3, 62, pg.F6, 2, 1)
-    _full_parity(env, pop, (33, 65), tgt, what="all 26 operators")
+    _full_parity(env, pop, (33, 65), tgt, what=f"all {len(funcs)} operators")
 
 
 def test_dag_bit_exact(env):

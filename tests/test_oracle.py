@@ -84,6 +84,10 @@ def test_golden_5x5(path):
     ("mdist(0.5, -0.25)", 0.125), ("step(-0.1)", -1.0), ("step(0.0)", 1.0),
     ("sstep(0.5)", 0.5), ("sstepp(0.5)", 0.5), ("len(0.75, 1.0)", 1.25),
     ("lerp(0.0, 1.0, 0.25)", 0.25), ("lerp(0.0, 1.0, 1.25)", 0.25), ("lerp(0.0, 1.0, -0.75)", 0.25),
+    # bitwise on truncated integers: 3 | 1, -2 ^ 1, -1 & 5, NaN -> 0, saturation
+    ("or(3.7, 1.2)", 3.0), ("xor(-2.5, 1.0)", -1.0), ("and(-1.0, 5.9)", 5.0),
+    ("or(pow(-0.5, 0.5), 6.0)", 6.0), ("and(exp(100.0), 1.0)", 1.0),
+    ("or(neg(exp(100.0)), 0.0)", -2147483648.0), ("xor(0.9, -0.9)", 0.0),
 ])
 def test_table1_points(text, want):
     got = ev1(text)
@@ -219,7 +223,8 @@ def _np_eval(text, X, Y):
     def sinpi(a):
         with np.errstate(all="ignore"):
             r = np.sin(np.pi * np.asarray(a, float))
-        return np.where(np.asarray(a) == np.round(np.asarray(a)), 0.0, r)
+        a = np.asarray(a, float)
+        return np.where(np.isfinite(a) & (a == np.round(a)), 0.0, r)
 
     def cospi(a):
         with np.errstate(all="ignore"):
@@ -268,7 +273,21 @@ def _np_eval(text, X, Y):
         lerp=lambda a, b, c: a + (b - a) * frac(c), x=X, y=Y, inf=np.inf, nan=np.nan,
         np=np)
     env["if"] = lambda a, b, c: np.where(a != 0, b, c)
-    code = text.replace("if(", "env['if'](")
+
+    def to_int(a):
+        a = np.asarray(a, dtype=np.float64)
+        with np.errstate(all="ignore"):
+            t = np.where(np.isnan(a), 0.0, np.clip(np.trunc(a), -2.0 ** 31, 2.0 ** 31 - 1))
+        return t.astype(np.int64)
+
+    env["or"] = lambda a, b: (to_int(a) | to_int(b)).astype(float)
+    env["xor"] = lambda a, b: (to_int(a) ^ to_int(b)).astype(float)
+    env["and"] = lambda a, b: (to_int(a) & to_int(b)).astype(float)
+    code = text.replace("if(", "env['if'](").replace("xor(", "env['xor'](")
+    code = code.replace("and(", "env['and'](").replace(" or(", " env['or'](")
+    if code.startswith("or("):
+        code = "env['or'](" + code[3:]
+    code = code.replace("(or(", "(env['or'](")
     env["env"] = env
     with np.errstate(all="ignore"):
         return np.broadcast_to(eval(code, {"__builtins__": {}}, env), X.shape).astype(float)
@@ -301,7 +320,7 @@ def _compare(got, want, text):
 def test_brute_force_depth1():
     """Every tree of depth <= 1 over the operators and 7 terminals, on the 4x4 grid."""
     trees = _all_depth1()
-    assert len(trees) == 7 + 13 * 7 + 10 * 49 + 3 * 343
+    assert len(trees) == 7 + 13 * 7 + 13 * 49 + 3 * 343
     c = oracle.coords(4).astype(float)
     X, Y = np.meshgrid(c, c, indexing="ij")
     toks = [pg.parse(t) for t in trees]

@@ -33,6 +33,8 @@ MUTANTS = [
     ("sqrt protection", "return a < 0.0 ? 0.0 : sqrt(a);", "return a < 0.0 ? sqrt(-a) : sqrt(a);"),
     ("grid endpoint", "lo + (hi - lo) * (double)i / (double)(n - 1)", "lo + (hi - lo) * (double)i / (double)n"),
     ("rmse without the root", "(loss == 0 ? sqrt(s / N) : s / N)", "(loss == 0 ? s / N : s / N)"),
+    ("xor computed as or", "(ia ^ ib)", "(ia | ib)"),
+    ("integers rounded, not truncated", "return (int32_t)trunc(x);", "return (int32_t)rint(x);"),
 ]
 
 
