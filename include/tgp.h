@@ -88,7 +88,15 @@ enum tgp_opcode {
     TGP_OR = 28,    /* [2] int(x) | int(y) */
     TGP_XOR = 29,   /* [2] int(x) ^ int(y) */
     TGP_AND = 30,   /* [2] int(x) & int(y) */
-    TGP_NUM_OPS = 31
+    /* [3] warp(v, t0, t1): the image transform of Table 1 and Sec. 3.2, read
+     * as a gather: the value at a case is v at the grid point whose positions
+     * along axes 0 and 1 are given by t0 and t1 (domain units; nearest point,
+     * halves rounded up, clamped to the axis, NaN giving the first point); a
+     * third axis keeps the case's own point and a 1-D domain ignores t1.  v
+     * is materialised over the whole domain first (it is always a cached
+     * subtree). */
+    TGP_WARP = 31,
+    TGP_NUM_OPS = 32
 };
 
 /* One tree node.  Trees are postfix (children before parent, left to right).

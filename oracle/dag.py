@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 
 # Arities by opcode, in Table 1 order (kept here independently of any other module).
-_ARITY = [0, 0, 2, 2, 2, 2, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 1, 1, 1, 3, 2, 1, 3, 1, 1, 1, 2, 3, 2, 2, 2]
+_ARITY = [0, 0, 2, 2, 2, 2, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 1, 1, 1, 3, 2, 1, 3, 1, 1, 1, 2, 3, 2, 2, 2, 3]
 
 
 def tree_stack_depth(ops) -> int:

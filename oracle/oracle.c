@@ -41,6 +41,9 @@
  *   frac(x) = x - floor(x); if(x, y, z) = x != 0 ? y : z (NaN counts true);
  *   tan(x) = sin(pi x) / cos(pi x) with IEEE division;
  *   len(x, y) = the exact sqrt(x^2 + y^2) (hypot);
+ *   warp(v, t0, t1) is a gather: v at the grid point whose axis-0 and axis-1
+ *   positions t0, t1 name (nearest point, halves rounded up, clamped, NaN
+ *   giving the first point; a third axis keeps its own point);
  *   or/xor/and act on 32-bit integers made from the operands by truncation
  *   toward zero with saturation (NaN gives 0), as Table 1's footnote asks
  *   for a conversion to integers;
@@ -74,6 +77,7 @@ enum {
     OV_MOD, OV_FRAC, OV_IF,
     OV_STEP, OV_SSTEP, OV_SSTEPP, OV_LEN, OV_LERP,
     OV_OR, OV_XOR, OV_AND,
+    OV_WARP,
     OV_COUNT
 };
 
@@ -87,6 +91,7 @@ static const int orc_arity[OV_COUNT] = {
     2, 1, 3,
     1, 1, 1, 2, 3,
     2, 2, 2,
+    3,
 };
 
 #define ORC_MAX_DIM 3
@@ -289,6 +294,7 @@ typedef struct {
     int ndim;
     int64_t shape[ORC_MAX_DIM];
     int64_t stride[ORC_MAX_DIM];
+    double lo[ORC_MAX_DIM], hi[ORC_MAX_DIM];
     float *coord[ORC_MAX_DIM];
 } odomain;
 
@@ -307,6 +313,8 @@ static int make_domain(int ndim, const int64_t *shape, const double *lo, const d
         st *= shape[k];
     }
     for (int k = 0; k < ndim; k++) {
+        d->lo[k] = lo[k];
+        d->hi[k] = hi[k];
         d->coord[k] = (float *)malloc(sizeof(float) * (size_t)shape[k]);
         for (int64_t i = 0; i < shape[k]; i++) {
             double v = shape[k] == 1 ? lo[k] : lo[k] + (hi[k] - lo[k]) * (double)i / (double)(shape[k] - 1);
@@ -330,9 +338,41 @@ static void case_coords(const odomain *d, int64_t c, double *xyz)
     }
 }
 
+/* ---------------------------------------------------------------- warp */
+
+/* warp(v, t0, t1) (Sec. 3.2, Table 1) read as a gather: the value at a case is
+ * v at the grid point that t0 and t1 name along axes 0 and 1, each the
+ * nearest point of its axis (position u = (t - lo)(n - 1)/(hi - lo) rounded
+ * half up, clamped to the axis, NaN giving point 0); a third axis keeps the
+ * case's own point, and a 1-D domain ignores t1.  Index of axis k: */
+static int64_t warp_axis(const odomain *d, int k, double t)
+{
+    const int64_t n = d->shape[k];
+    if (n == 1)
+        return 0;
+    const double u = (t - d->lo[k]) * ((double)(n - 1) / (d->hi[k] - d->lo[k])) + 0.5;
+    const double w = fmin(fmax(u, 0.0), (double)(n - 1)); /* fmax(NaN, 0) = 0 */
+    return (int64_t)floor(w);
+}
+
+/* Coordinates of the point warp reads, from the current case's coordinates. */
+static void warp_coords(const odomain *d, double t0, double t1, const double *xyz, double *out)
+{
+    out[0] = d->coord[0][warp_axis(d, 0, t0)];
+    if (d->ndim > 1)
+        out[1] = d->coord[1][warp_axis(d, 1, t1)];
+    if (d->ndim > 2)
+        out[2] = xyz[2];
+}
+
+/* Is the rounding of axis k's position clear of its steps by MARGIN bounds,
+ * given the bound e of t?  The steps are at the integers 1 .. n - 1 of
+ * u = position + 1/2; the FP32 evaluation of u adds up to 3 ulp of u. */
+static int warp_axis_clear(const odomain *d, int k, double t, double e);
+
 /* ------------------------------------------------------- the tree walkers */
 
-static double ev64(const onode *n, int32_t i, const double *xyz)
+static double ev64(const odomain *d, const onode *n, int32_t i, const double *xyz)
 {
     const onode *p = &n[i];
     if (p->op == OV_VAR)
@@ -341,11 +381,16 @@ static double ev64(const onode *n, int32_t i, const double *xyz)
         return (double)p->value;
     double a = 0.0, b = 0.0, c = 0.0, br;
     int ar = orc_arity[p->op];
-    a = ev64(n, p->kid[0], xyz);
+    if (p->op == OV_WARP) {
+        double at[3];
+        warp_coords(d, ev64(d, n, p->kid[1], xyz), ev64(d, n, p->kid[2], xyz), xyz, at);
+        return ev64(d, n, p->kid[0], at);
+    }
+    a = ev64(d, n, p->kid[0], xyz);
     if (ar > 1)
-        b = ev64(n, p->kid[1], xyz);
+        b = ev64(d, n, p->kid[1], xyz);
     if (ar > 2)
-        c = ev64(n, p->kid[2], xyz);
+        c = ev64(d, n, p->kid[2], xyz);
     return apply(p->op, a, b, c, &br);
 }
 
@@ -380,7 +425,21 @@ static double dist_to_int(double x)
 
 /* One node in O64 (v), O32r (r) and the running bound (e); *ok is cleared
  * when a discontinuity is too close or O32r falls on another side. */
-static void evb(const onode *n, int32_t i, const double *xyz, double *v, double *r, double *e, int *ok)
+static int warp_axis_clear(const odomain *d, int k, double t, double e)
+{
+    const int64_t n = d->shape[k];
+    if (n == 1 || !isfinite(t))
+        return 1;
+    const double scale = (double)(n - 1) / (d->hi[k] - d->lo[k]);
+    const double u = (t - d->lo[k]) * scale + 0.5;
+    const double eu = fabs(scale) * e + 3.0 * U_CR * (fabs(u) + 1.0);
+    if (u < -MARGIN * eu || u > (double)(n - 1) + MARGIN * eu)
+        return 1; /* clamped */
+    return dist_to_int(u) > MARGIN * eu;
+}
+
+static void evb(const odomain *d, const onode *n, int32_t i, const double *xyz, double *v, double *r,
+                double *e, int *ok)
 {
     const onode *p = &n[i];
     if (p->op == OV_VAR) {
@@ -395,8 +454,23 @@ static void evb(const onode *n, int32_t i, const double *xyz, double *v, double 
     }
     double kv[3] = {0, 0, 0}, kr[3] = {0, 0, 0}, ke[3] = {0, 0, 0};
     int ar = orc_arity[p->op];
+    if (p->op == OV_WARP) {
+        /* the coordinates first; then v at the point they name (O64's point;
+         * O32r must name the same one) */
+        for (int j = 1; j < 3; j++)
+            evb(d, n, p->kid[j], xyz, &kv[j], &kr[j], &ke[j], ok);
+        for (int k = 0; k < d->ndim && k < 2; k++) {
+            if (warp_axis(d, k, kv[1 + k]) != warp_axis(d, k, kr[1 + k]) ||
+                !warp_axis_clear(d, k, kv[1 + k], ke[1 + k]))
+                *ok = 0;
+        }
+        double at[3];
+        warp_coords(d, kv[1], kv[2], xyz, at);
+        evb(d, n, p->kid[0], at, v, r, e, ok);
+        return;
+    }
     for (int j = 0; j < ar; j++)
-        evb(n, p->kid[j], xyz, &kv[j], &kr[j], &ke[j], ok);
+        evb(d, n, p->kid[j], xyz, &kv[j], &kr[j], &ke[j], ok);
     double br0, br1;
     const double a = kv[0], b = kv[1], c = kv[2];
     const double ea = ke[0], eb = ke[1], ec = ke[2];
@@ -571,12 +645,12 @@ int orc_eval(const orc_token *tokens, const int64_t *offsets, int64_t n_roots,
                 case_coords(&d, c, xyz);
                 const otree *t = &trees[r];
                 if (!four) {
-                    v64[q] = ev64(t->n, t->count - 1, xyz);
+                    v64[q] = ev64(&d, t->n, t->count - 1, xyz);
                     continue;
                 }
                 double v, r32, e;
                 int ok = 1;
-                evb(t->n, t->count - 1, xyz, &v, &r32, &e, &ok);
+                evb(&d, t->n, t->count - 1, xyz, &v, &r32, &e, &ok);
                 v64[q] = v;
                 if (v32r)
                     v32r[q] = r32;

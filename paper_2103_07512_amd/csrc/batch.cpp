@@ -84,7 +84,7 @@ struct tgp_batch_s {
     tgp_ctx ctx = nullptr;
     bool use_graph = true;
     bool persistent = true;  // persistent kernels, or one wave per work item
-    bool bit = false;        // interpreter with the bitwise operators
+    bool ext = false;        // interpreter with the bitwise operators and warp
     int K = 4;
     int levels_cap = 4;  // fill levels the graph has launches for
     int grid_store = 0, grid_reduce = 0;
@@ -152,7 +152,7 @@ static hipKernelNodeParams launch_params(tgp_batch b, int i, void **args) {
         const bool store = i <= L;
         const int g = i - 1;
         b->group_index[g] = g;
-        p.func = const_cast<void *>(batch_kernel(b->K, interp_max_stack(), store, b->persistent, b->bit));
+        p.func = const_cast<void *>(batch_kernel(b->K, interp_max_stack(), store, b->persistent, b->ext));
         if (b->persistent) {
             p.gridDim = dim3(store ? b->grid_store : b->grid_reduce);
         } else {
@@ -318,13 +318,13 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
         HCHK(ctx, hipEventSynchronize(b->staged_ev));
         b->staged = false;
     }
-    bool bit = false;
-    for (int32_t j = 0; j < n_jobs; ++j) bit = bit || jobs[j].plan->bitwise;
+    bool ext = false;
+    for (int32_t j = 0; j < n_jobs; ++j) ext = ext || jobs[j].plan->ext;
     int K = ctx->force_K ? ctx->force_K : 4;
-    if (!interp_variant_exists(K, interp_max_stack(), bit)) K = 4;
-    if (K != b->K || bit != b->bit) {
+    if (!interp_variant_exists(K, interp_max_stack(), ext)) K = 4;
+    if (K != b->K || ext != b->ext) {
         b->K = K;
-        b->bit = bit;
+        b->ext = ext;
         b->stale = true;
     }
     const bool persistent = ctx->batch_persistent != 0;
@@ -496,7 +496,7 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
     if (e == hipSuccess) e = hipEventRecord(b->staged_ev, ctx->stream);
     if (e != hipSuccess) return fail(ctx, TGP_EHIP, "batch upload: %s", hipGetErrorString(e));
     b->staged = true;
-    const int gs = batch_grid(K, interp_max_stack(), true, bit), gr = batch_grid(K, interp_max_stack(), false, bit);
+    const int gs = batch_grid(K, interp_max_stack(), true, ext), gr = batch_grid(K, interp_max_stack(), false, ext);
     if (gs != b->grid_store || gr != b->grid_reduce) {
         b->grid_store = gs;
         b->grid_reduce = gr;

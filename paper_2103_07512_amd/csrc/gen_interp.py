@@ -53,8 +53,8 @@ PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
 # Operators compiled once, out of line.
 CALLED = {"sin", "cos", "tan", "exp", "log", "pow", "mod", "sstep", "sstepp", "len", "lerp"}
 # The bitwise operators share one opcode (that of "or"); the instruction's
-# bits 8-9 say which (0 or, 1 xor, 2 and).  They are compiled only into the
-# interpreters instantiated with BIT = true.
+# bits 8-9 say which (0 or, 1 xor, 2 and).  They and warp (I_WARP) are
+# compiled only into the interpreters instantiated with EXT = true.
 BITWISE = ("or", "xor", "and")
 DEPTHS = [8]
 ARGS = "abc"
@@ -85,10 +85,10 @@ def body_for_depth(D):
     e = L.append
     e(f"// Stack of {D} register slots.  Returns when the program's I_END is reached")
     e(f"// at depth 1 (res = the program's value); a malformed program gives NaN.")
-    e("template <int K, bool BIT>")
+    e("template <int K, bool EXT>")
     e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
     e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
-    e("        const int32_t (&cidx)[K], FV<K> &res)")
+    e("        const int32_t (&cidx)[K], const WarpGeom &wg, FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
     e("    // The next instruction is fetched one dispatch ahead so that the scalar")
@@ -118,6 +118,16 @@ def body_for_depth(D):
             e("    }")
         if S == 1:
             e("    case I_END: res = s0; return;")
+        if S >= 2:
+            e("    case I_WARP:")
+            e("        if constexpr (EXT) {")
+            e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+            e("#pragma unroll")
+            e(f"            for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row[warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], cidx[k])];")
+            e(f"            goto L{S - 1};")
+            e("        } else {")
+            e("            goto BAD;")
+            e("        }")
         variants = []
         for name, op, ar in FUNCS:
             if name in BITWISE[1:]:
@@ -137,10 +147,10 @@ def body_for_depth(D):
             # child i was evaluated order.index(i)-th, so it sits in slot dst + that position
             src = [f"s{dst + order.index(i)}" for i in range(ar)]
             if name == BITWISE[0]:
-                # only in the interpreters built with BIT (the others are
+                # only in the interpreters built with EXT (the others are
                 # never given programs that use these operators)
                 e(f"    case {c}:")
-                e("        if constexpr (BIT) {")
+                e("        if constexpr (EXT) {")
                 e("            const uint32_t kind = (ins.x >> 8) & 3u;")
                 e("#pragma unroll")
                 e(f"            for (int k = 0; k < K; ++k) s{dst}.v[k] = f_bitop({src[0]}.v[k], {src[1]}.v[k], kind);")

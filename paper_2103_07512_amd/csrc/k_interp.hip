@@ -34,6 +34,26 @@ struct FV {
     float v[K];
 };
 
+// What warp needs to know of the domain: the position scale of axes 0 and
+// 1, their sizes and strides, and the number of axes.
+struct WarpGeom {
+    float lo0, lo1, sc0, sc1;
+    int32_t n0, n1;
+    uint32_t st0, st1;
+    int32_t ndim;
+};
+
+// The case warp reads for a case c: the points named by t0 and t1 along
+// axes 0 and 1, the case's own point along a third axis.
+__device__ __forceinline__ int32_t warp_case(const WarpGeom &g, float t0, float t1, int32_t c) {
+    uint32_t r = (uint32_t)warp_point(t0, g.lo0, g.sc0, g.n0) * g.st0;
+    if (g.ndim > 1) {
+        r += (uint32_t)warp_point(t1, g.lo1, g.sc1, g.n1) * g.st1;
+        if (g.ndim > 2) r += (uint32_t)c % g.st1;
+    }
+    return (int32_t)r;
+}
+
 #include "interp_gen.inc"
 
 enum { MODE_REDUCE = 0, MODE_STORE = 1 };
@@ -60,16 +80,16 @@ __device__ __forceinline__ void kahan_merge(float &s, float &c, float s2, float 
     s = t;
 }
 
-template <int K, int D, bool BIT>
+template <int K, int D, bool EXT>
 __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const FV<K> &yv,
                                          const FV<K> &zv, const float *cache, int64_t cache_stride,
-                                         const int32_t (&cidx)[K], FV<K> &res) {
+                                         const int32_t (&cidx)[K], const WarpGeom &wg, FV<K> &res) {
     static_assert(D == 8, "compiled stack size: 8");
-    run_prog_d8<K, BIT>(ip, xv, yv, zv, cache, cache_stride, cidx, res);
+    run_prog_d8<K, EXT>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, res);
 }
 
 // One work item: program `code` over tiles_per_stripe tiles of one stripe.
-template <int K, int D, int MODE, bool BIT>
+template <int K, int D, int MODE, bool EXT>
 __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, int32_t dest, int32_t chan,
                                          uint32_t stripe, int lane) {
     const int32_t n = a.n_cases;
@@ -111,7 +131,12 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
             }
         }
         FV<K> res;
-        run_prog<K, D, BIT>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, res);
+        WarpGeom wg{};
+        if constexpr (EXT) {
+            wg = WarpGeom{a.warp_lo[0], a.warp_lo[1], a.warp_scale[0], a.warp_scale[1], a.shape[0], a.shape[1],
+                          (uint32_t)a.stride[0], (uint32_t)a.stride[1], a.ndim};
+        }
+        run_prog<K, D, EXT>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, wg, res);
         if constexpr (MODE == MODE_STORE) {
             float *row = a.out + (size_t)dest * (size_t)a.out_stride;
 #pragma unroll
@@ -138,13 +163,13 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
     }
 }
 
-template <int K, int D, int MODE, bool BIT>
+template <int K, int D, int MODE, bool EXT>
 __global__ __launch_bounds__(64) void k_interp(const InterpArgs a) {
     const uint32_t item = blockIdx.x;
     const uint32_t p = item / (uint32_t)a.job.n_stripes;
     const uint32_t stripe = item - p * (uint32_t)a.job.n_stripes;
     const ProgDesc pd = a.progs[p];
-    run_item<K, D, MODE, BIT>(a.job, a.job.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
+    run_item<K, D, MODE, EXT>(a.job, a.job.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
 }
 
 // Batched interpreter, two launch forms over the work items of group g
@@ -187,7 +212,7 @@ __device__ __forceinline__ uint32_t find_pair(const uint32_t *__restrict__ item_
     return lo;
 }
 
-template <int K, int D, int MODE, bool BIT>
+template <int K, int D, int MODE, bool EXT>
 __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
                                               const PairDesc *__restrict__ pairs,
                                               const uint32_t *__restrict__ item_first,
@@ -212,7 +237,7 @@ __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
                 const PairDesc pd = load_const(pairs + lo);
                 const JobDesc jd = load_const(jobs + pd.job);
                 const uint32_t stripe = item - load_const_u32(item_first + lo);
-                run_item<K, D, MODE, BIT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
+                run_item<K, D, MODE, EXT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
             }
         }
     }
@@ -220,7 +245,7 @@ __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
 
 // Direct form: one wave per item (grid = the group's item count, or more);
 // the hardware dispatcher hands out the waves in item order.
-template <int K, int D, int MODE, bool BIT>
+template <int K, int D, int MODE, bool EXT>
 __global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__ jobs,
                                                      const PairDesc *__restrict__ pairs,
                                                      const uint32_t *__restrict__ item_first,
@@ -231,7 +256,7 @@ __global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__
     const uint32_t lo = find_pair(item_first, gd.pair_begin, gd.pair_end, item);
     const PairDesc pd = load_const(pairs + lo);
     const JobDesc jd = load_const(jobs + pd.job);
-    run_item<K, D, MODE, BIT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, item - load_const_u32(item_first + lo),
+    run_item<K, D, MODE, EXT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, item - load_const_u32(item_first + lo),
                          threadIdx.x);
 }
 
@@ -313,38 +338,39 @@ __global__ __launch_bounds__(256) void k_finalize_batch(const FinJob *jobs, cons
 }
 
 // ------------------------------------------------------------- launchers
-template <int K, int D, bool BIT>
+template <int K, int D, bool EXT>
 static hipError_t launch_kd(bool store, const InterpArgs &a, hipStream_t s) {
     const uint32_t items = (uint32_t)a.n_progs * (uint32_t)a.job.n_stripes;
     if (items == 0) return hipSuccess;
     if (store)
-        hipLaunchKernelGGL((k_interp<K, D, MODE_STORE, BIT>), dim3(items), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_interp<K, D, MODE_STORE, EXT>), dim3(items), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_interp<K, D, MODE_REDUCE, BIT>), dim3(items), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_interp<K, D, MODE_REDUCE, EXT>), dim3(items), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
-template <int K, int D, bool BIT>
+template <int K, int D, bool EXT>
 static const void *batch_fn(bool store, bool persistent) {
     if (persistent)
-        return store ? (const void *)k_batch<K, D, MODE_STORE, BIT> : (const void *)k_batch<K, D, MODE_REDUCE, BIT>;
-    return store ? (const void *)k_batch_direct<K, D, MODE_STORE, BIT>
-                 : (const void *)k_batch_direct<K, D, MODE_REDUCE, BIT>;
+        return store ? (const void *)k_batch<K, D, MODE_STORE, EXT> : (const void *)k_batch<K, D, MODE_REDUCE, EXT>;
+    return store ? (const void *)k_batch_direct<K, D, MODE_STORE, EXT>
+                 : (const void *)k_batch_direct<K, D, MODE_REDUCE, EXT>;
 }
 
-template <int K, int D, bool BIT>
+template <int K, int D, bool EXT>
 static int grid_bd(bool store) {
     int per_cu = 0, dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (store)
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_STORE, BIT>, 64, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_STORE, EXT>, 64, 0);
     else
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_REDUCE, BIT>, 64, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<K, D, MODE_REDUCE, EXT>, 64, 0);
     return std::max(1, per_cu) * std::max(1, cus);
 }
 
-// Instantiated interpreters: (cases per lane, stack slots, bitwise operators).
+// Instantiated interpreters: (cases per lane, stack slots, bitwise operators
+// and warp).
 #ifndef TGP_VARIANTS
 #define TGP_VARIANTS(X) X(4, 8, false) X(2, 8, false) X(4, 8, true)
 #endif

@@ -66,6 +66,14 @@ __device__ __forceinline__ float f_lerp(float a, float b, float c) {
     double x = a, y = b, z = c;
     return (float)(x + (y - x) * (z - floor(z)));
 }
+// warp: the nearest point of an axis of n points to position (t - lo) *
+// scale, halves rounded up, clamped to the axis; NaN gives point 0 (fmaxf
+// returns its other operand).
+__device__ __forceinline__ int32_t warp_point(float t, float lo, float scale, int32_t n) {
+    const float u = (t - lo) * scale + 0.5f;
+    return (int32_t)floorf(fminf(fmaxf(u, 0.0f), (float)(n - 1)));
+}
+
 // Bitwise operators: each operand becomes a 32-bit integer (NaN -> 0,
 // truncation toward zero, saturation to the int32 range), the integer result
 // is rounded to FP32; kind 0: or, 1: xor, 2: and.

@@ -91,7 +91,8 @@ const double kOpCost[TGP_NUM_OPS] = {
     11, 4,  1,  6,   // sqrt sign abs clip
     40, 2,  3,       // mod frac if
     2,  9,  12, 16, 14, // step sstep sstepp len lerp
-    7,  7,  7           // or xor and
+    7,  7,  7,          // or xor and
+    24                  // warp (two axis points, a gathered read)
 };
 // Writing a cache row once and reading it back, in VALU-slot equivalents per
 // case: 4 bytes of HBM traffic at 8 TB/s against 256 CUs x 64 lanes x 2.4 GHz
@@ -456,6 +457,14 @@ struct Planner {
         if (!d.precached.empty() && access_cost >= 0)
             for (int64_t n = 0; n < U; ++n)
                 if (d.precached[n] && arity(n) > 0 && cost[n] > access_cost) cached[n] = pre[n] = 1;
+        // The value a warp gathers from is read at other cases than the one
+        // being evaluated, so it is always materialised (a cached row).
+        size_t used = 0;
+        for (int64_t n = 0; n < U; ++n)
+            if (op(n) == TGP_WARP && !cached[d.kid[3 * n]]) {
+                cached[d.kid[3 * n]] = 1;
+                ++used;
+            }
         // Bottom-up: bound the register stack of every program.  Children are
         // evaluated in decreasing order of the stack they need (Sethi-Ullman);
         // a node whose children still cannot be evaluated within D slots gets
@@ -463,10 +472,23 @@ struct Planner {
         std::vector<int32_t> need(U, 1);
         perm.assign(U, 0);
         auto ref_need = [&](int32_t c) { return cached[c] ? 1 : need[c]; };
-        size_t used = 0;
         for (int64_t n = 0; n < U; ++n) {
             const int a = arity(n);
             if (a == 0) continue;
+            if (op(n) == TGP_WARP) {  // t0 then t1 on the stack, in that order
+                for (;;) {
+                    const int32_t c1 = d.kid[3 * n + 1], c2 = d.kid[3 * n + 2];
+                    const int r1 = ref_need(c1), r2 = ref_need(c2);
+                    const int v = std::max(r1, 1 + r2);
+                    if (v <= D) {
+                        need[n] = v;
+                        break;
+                    }
+                    cached[r1 >= r2 ? c1 : c2] = 1;
+                    ++used;
+                }
+                continue;
+            }
             for (;;) {
                 int r[3] = {0, 0, 0};
                 for (int j = 0; j < a; ++j) r[j] = ref_need(d.kid[3 * n + j]);
@@ -555,8 +577,9 @@ struct Planner {
             auto &top = st.back();
             const int32_t n = top.first;
             const bool leafish = arity(n) == 0 || (n != root && cached[n]);
-            if (!leafish && top.second < arity(n)) {
-                const int32_t c = d.kid[3 * n + kPerms[perm[n]][top.second]];
+            const bool warp = op(n) == TGP_WARP;  // stack children t0, t1 only
+            if (!leafish && top.second < (warp ? 2 : arity(n))) {
+                const int32_t c = warp ? d.kid[3 * n + 1 + top.second] : d.kid[3 * n + kPerms[perm[n]][top.second]];
                 ++top.second;
                 st.push_back({c, 0});
                 continue;
@@ -578,6 +601,10 @@ struct Planner {
                     memcpy(&ins.y, &d.value[n], 4);
                 } else if (o == TGP_OR || o == TGP_XOR || o == TGP_AND) {
                     ins.x = (kFnBase + TGP_OR) | ((uint32_t)(o - TGP_OR) << 8);
+                } else if (o == TGP_WARP) {
+                    ins.x = I_WARP;
+                    ins.y = (uint32_t)slot[d.kid[3 * n]];
+                    ++cache_reads;
                 } else if (perm[n] == 0 || (kArity[o] == 2 && is_commutative(o))) {
                     ins.x = kFnBase + o;
                 } else if (kArity[o] == 2) {
@@ -766,12 +793,12 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.valu_roots_per_case = valu_roots;
     P.cache_reads_per_case = cache_reads_fill + cache_reads_roots;
     P.instructions = (int64_t)code.size();
-    P.bitwise = false;
-    for (const uint2 &ins : code)
-        if ((ins.x & 0xffu) == kFnBase + TGP_OR) {
-            P.bitwise = true;
-            break;
-        }
+    P.ext = P.warp = false;
+    for (const uint2 &ins : code) {
+        const uint32_t c = ins.x & 0xffu;
+        if (c == kFnBase + TGP_OR) P.ext = true;
+        if (c == I_WARP) P.ext = P.warp = true;
+    }
     P.n_slots = (int32_t)cached_nodes.size();
     P.n_spills = pl.spills;
     P.n_fill = (int32_t)fill.size();
@@ -841,8 +868,8 @@ void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *s
     *stripes = (int32_t)((n_tiles + tps - 1) / tps);
 }
 
-int choose_K(tgp_ctx ctx, int64_t cases, bool bitwise) {
-    if (bitwise) return 4;  // the one interpreter built with the bitwise operators
+int choose_K(tgp_ctx ctx, int64_t cases, bool ext) {
+    if (ext) return 4;  // the one interpreter built with the bitwise operators and warp
     if (ctx->force_K) return ctx->force_K;
     return cases >= 64 * 4 * 4 ? 4 : 2;
 }
@@ -860,6 +887,10 @@ void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache)
     j.cache = cache;
     j.case_base = 0;
     j.cache_stride = j.out_stride = j.target_stride = dom->cases;
+    for (int k = 0; k < 2; ++k) {
+        j.warp_lo[k] = (float)dom->lo[k];
+        j.warp_scale[k] = dom->shape[k] > 1 ? (float)((double)(dom->shape[k] - 1) / (dom->hi[k] - dom->lo[k])) : 0.0f;
+    }
 }
 
 static void fill_args(InterpArgs &a, tgp_domain dom, const Plan &P, const float *cache) {
@@ -887,7 +918,7 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
         a.n_progs = e - b;
         choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
         a.job.out = cache;
-        HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.bitwise));
+        HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.ext));
     }
     record(ctx, 1);
     return TGP_OK;
@@ -933,7 +964,7 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     st = build_plan(ctx, d, dom->cases);
     if (st != TGP_OK) return st;
     const Plan &P = d->plan;
-    const int K = choose_K(ctx, dom->cases, P.bitwise);
+    const int K = choose_K(ctx, dom->cases, P.ext);
     float *cache = nullptr;
     st = run_fill(ctx, d, dom, K, &cache);
     if (st != TGP_OK) return st;
@@ -946,7 +977,7 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.job.n_stripes));
     a.job.partial = (float2 *)ctx->partial.p;
     record(ctx, 2);
-    HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream, P.bitwise));
+    HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream, P.ext));
     record(ctx, 3);
     record(ctx, 4);
     HCHK(ctx, launch_finalize(a.job.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.job.n_stripes,
@@ -968,7 +999,7 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     st = build_plan(ctx, d, dom->cases);
     if (st != TGP_OK) return st;
     const Plan &P = d->plan;
-    const int K = choose_K(ctx, dom->cases, P.bitwise);
+    const int K = choose_K(ctx, dom->cases, P.ext);
     float *cache = nullptr;
     st = run_fill(ctx, d, dom, K, &cache);
     if (st != TGP_OK) return st;
@@ -979,7 +1010,7 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
     a.job.out = out_dev;
     record(ctx, 2);
-    HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.bitwise));
+    HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.ext));
     record(ctx, 3);
     record(ctx, 4);
     record(ctx, 5);

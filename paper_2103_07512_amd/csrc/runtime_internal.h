@@ -86,7 +86,8 @@ struct Plan {
     std::vector<int32_t> ind_rows_host;
     std::vector<int32_t> slot_node;     // DAG node held by each cache slot
     std::vector<uint8_t> slot_pre;      // slot already resident (no fill program)
-    bool bitwise = false;               // uses the bitwise operators
+    bool ext = false;                   // uses the bitwise operators or warp
+    bool warp = false;                  // uses warp
     int64_t instructions = 0;
     double exec_per_case = 0;           // instructions run per case, fitness form
     double valu_dag_per_case = 0;       // cost-model slots of each DAG node once
@@ -177,7 +178,7 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
 // --------------------------------------------------------------- shared helpers
 extern const double kOpCost[TGP_NUM_OPS];
 tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases);
-int choose_K(tgp_ctx ctx, int64_t cases, bool bitwise);
+int choose_K(tgp_ctx ctx, int64_t cases, bool ext);
 void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
                   int32_t *tiles_per);
 void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache);

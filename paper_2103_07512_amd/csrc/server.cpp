@@ -324,7 +324,9 @@ void prepare(tgp_server s, tgp_ctx pc, const ReqP &rp) {
     const double per_case = std::max<double>(1.0, (double)U);
     int64_t slab = (int64_t)(s->slab_work / per_case);
     slab = std::max<int64_t>(kSlabQuantum, slab / kSlabQuantum * kSlabQuantum);
-    if (slab >= cases) slab = cases;
+    // warp reads its source at any case, so the source must be complete
+    // before any warp runs: such a request is evaluated in one slab
+    if (slab >= cases || P.warp) slab = cases;
     r.slab = slab;
     r.n_slabs = (int32_t)((cases + slab - 1) / slab);
     const int64_t tiles = (slab + 64 * s->K - 1) / (64 * s->K);

@@ -23,7 +23,8 @@ namespace tgp {
         1, 1, 1, 3,               /* sqrt sign abs clip */             \
         2, 1, 3,                  /* mod frac if */                    \
         1, 1, 1, 2, 3,            /* step sstep sstepp len lerp */     \
-        2, 2, 2                   /* or xor and */
+        2, 2, 2,                  /* or xor and */                     \
+        3                         /* warp */
 
 constexpr int kArityList[] = {TGP_ARITY_LIST};
 static_assert(sizeof(kArityList) / sizeof(int) == TGP_NUM_OPS, "one arity per opcode");
@@ -41,6 +42,7 @@ constexpr int kArity[TGP_NUM_OPS] = {TGP_ARITY_LIST};
 // order kPerms[p].
 enum : uint32_t {
     I_X = 0, I_Y = 1, I_Z = 2, I_CONST = 3, I_CACHE = 4, I_END = 5,
+    I_WARP = 6,  // pops t0, t1; pushes cache row .y at the point they name
     kFnBase = 8,
     kRevBase = 40,
     kPermBase = 72,
@@ -86,6 +88,7 @@ struct JobDesc {
     const float *target;         // REDUCE: channel chan at target + chan * target_stride
     float2 *partial;             // REDUCE: [dest][n_stripes] (sum, compensation)
     int64_t cache_stride, out_stride, target_stride;
+    float warp_lo[2], warp_scale[2]; // warp: axis k position of t is (t - lo) * scale
 };
 
 // Launch arguments of the plain (one program set, one domain) interpreter:
@@ -135,7 +138,8 @@ struct Variant {
     int D;
 };
 
-// bit: the interpreter that also knows the bitwise operators (only K = 4).
+// ext: the interpreter that also knows the bitwise operators and warp (only
+// K = 4).
 hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s, bool bit);
 // Batched interpreter kernels (for graph nodes): the persistent form takes
 // (jobs, pairs, item_first, groups, g, counters[groups x batch_parts()]),

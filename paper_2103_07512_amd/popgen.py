@@ -43,6 +43,7 @@ OPS = [
     ("mod", 2), ("frac", 1), ("if", 3),
     ("step", 1), ("sstep", 1), ("sstepp", 1), ("len", 2), ("lerp", 3),
     ("or", 2), ("xor", 2), ("and", 2),      # bitwise (Table 1, Logic), appended
+    ("warp", 3),                            # image transform (Table 1), appended
 ]
 OP_CODE = {name: i for i, (name, _) in enumerate(OPS)}
 OP_CODE["mul"] = OP_CODE["mult"]           # the configs spell it "mul"

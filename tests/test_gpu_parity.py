@@ -174,6 +174,17 @@ def test_parity_extended_ops(env):
     _full_parity(env, pop, (33, 65), tgt, what=f"all {len(funcs)} operators")
 
 
+def test_parity_warp(env):
+    """warp gathers from a materialised subtree: 2-D ragged, 3-D and 1-D grids."""
+    funcs = pg.F6 + ("warp", "warp")  # warp drawn a quarter of the time
+    for i, shape in enumerate([(37, 53), (9, 10, 11), (17,)]):
+        pop = pg.ramped_half_and_half(60, 2, 6, 71 + i, funcs, len(shape))
+        tgt = pg.TargetSpec(3, 75 + i, pg.F6, len(shape), 1)
+        n_warp = int((pop.tokens["op"] == pg.OP_CODE["warp"]).sum())
+        assert n_warp > 20
+        _full_parity(env, pop, shape, tgt, what=f"warp {shape} ({n_warp} warp nodes)")
+
+
 def test_dag_bit_exact(env):
     tgp, ctx, torch = env
     for name, pop in (("C1", pg.workload_c1()[0]), ("C2", pg.workload_c2(side=8)[0]),

@@ -52,7 +52,8 @@ def mixed_work(env, seed):
     out = []
     specs = [(40, 2, 6, (64, 64), 1, 0), (120, 2, 8, (256, 256), 1, 0), (30, 3, 7, (20, 30, 40), 1, 0),
              (60, 2, 9, (512, 512), 1, 0), (25, 2, 6, (128, 96), 3, 1), (200, 2, 10, (32, 32), 1, 0)]
-    funcs = [pg.F18] * 5 + [pg.F18 + ("or", "xor", "and")]  # the last one uses the bitwise interpreter
+    # the last one uses the interpreter with the bitwise operators and warp
+    funcs = [pg.F18] * 5 + [pg.F18 + ("or", "xor", "and", "warp")]
     for i, (n, dmin, dmax, shape, ch, loss) in enumerate(specs):
         pop = pg.ramped_half_and_half(n, dmin, dmax, seed * 10 + i, funcs[i], len(shape), n_channels=ch)
         spec = pg.TargetSpec(4, seed * 10 + 5 + i, pg.F18, len(shape), ch)

@@ -280,6 +280,16 @@ def _np_eval(text, X, Y):
             t = np.where(np.isnan(a), 0.0, np.clip(np.trunc(a), -2.0 ** 31, 2.0 ** 31 - 1))
         return t.astype(np.int64)
 
+    def warp(a, b, c):
+        A, B, C = (np.broadcast_to(np.asarray(v, float), X.shape) for v in (a, b, c))
+
+        def idx(t, n):
+            with np.errstate(all="ignore"):
+                u = (t + 1.0) * (n - 1) / 2.0 + 0.5
+            return np.floor(np.where(np.isnan(u), 0.0, np.clip(u, 0, n - 1))).astype(int)
+        return A[idx(B, X.shape[0]), idx(C, X.shape[1])]
+
+    env["warp"] = warp
     env["or"] = lambda a, b: (to_int(a) | to_int(b)).astype(float)
     env["xor"] = lambda a, b: (to_int(a) ^ to_int(b)).astype(float)
     env["and"] = lambda a, b: (to_int(a) & to_int(b)).astype(float)
@@ -320,7 +330,7 @@ def _compare(got, want, text):
 def test_brute_force_depth1():
     """Every tree of depth <= 1 over the operators and 7 terminals, on the 4x4 grid."""
     trees = _all_depth1()
-    assert len(trees) == 7 + 13 * 7 + 13 * 49 + 3 * 343
+    assert len(trees) == 7 + 13 * 7 + 13 * 49 + 4 * 343
     c = oracle.coords(4).astype(float)
     X, Y = np.meshgrid(c, c, indexing="ij")
     toks = [pg.parse(t) for t in trees]
@@ -346,6 +356,29 @@ def test_brute_force_depth2_sample():
     got = oracle.evaluate(pop.tokens, pop.offsets, (4, 4))
     for i, t in enumerate(trees):
         _compare(got[i], _np_eval(t, X, Y).ravel(), t)
+
+
+# ----------------------------------------------------------------- warp
+def test_warp_gather_rules():
+    """warp read as a gather at the nearest grid point (Sec. 3.2, Table 1)."""
+    g = ev("add(x, mult(y, 3.0))").reshape(5, 5)
+    # identity: each case reads its own point
+    assert np.array_equal(ev("warp(add(x, mult(y, 3.0)), x, y)").reshape(5, 5), g)
+    # transpose: t0 = y, t1 = x
+    assert np.array_equal(ev("warp(add(x, mult(y, 3.0)), y, x)").reshape(5, 5), g.T)
+    # halves round up: position (0.25 + 1) * 2 = 2.5 -> point 3; -0.25 -> 1.5 -> point 2
+    assert np.all(ev("warp(x, 0.25, y)") == 0.5) and np.all(ev("warp(x, -0.25, y)") == 0.0)
+    # clamping to the axis and NaN -> first point
+    assert np.all(ev("warp(add(x, y), 7.0, -7.0)") == 1.0 + -1.0)
+    assert np.all(ev("warp(x, pow(-0.5, 0.5), y)") == -1.0)
+    # a 1-D domain ignores t1; a 3-D domain keeps the case's own z point
+    assert np.array_equal(ev("warp(x, neg(x), 0.0)", (7,)), -ev("x", (7,)))
+    z = ev("z", (3, 3, 3))
+    assert np.array_equal(ev("warp(z, 1.0, -1.0)", (3, 3, 3)), z)
+    assert np.all(ev("warp(add(x, y), 1.0, -1.0)", (3, 3, 3)) == 0.0)
+    # a one-point axis always reads its point; t1 = 0 names the middle of axis 1
+    assert np.array_equal(ev("warp(y, 0.3, y)", (1, 5)), ev("y", (1, 5)))
+    assert np.all(ev("warp(y, 0.3, 0.0)", (1, 5)) == 0.0)
 
 
 # ----------------------------------------------------------------- fitness

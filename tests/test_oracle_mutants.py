@@ -35,6 +35,9 @@ MUTANTS = [
     ("rmse without the root", "(loss == 0 ? sqrt(s / N) : s / N)", "(loss == 0 ? s / N : s / N)"),
     ("xor computed as or", "(ia ^ ib)", "(ia | ib)"),
     ("integers rounded, not truncated", "return (int32_t)trunc(x);", "return (int32_t)rint(x);"),
+    ("warp axes swapped", "warp_coords(d, ev64(d, n, p->kid[1], xyz), ev64(d, n, p->kid[2], xyz), xyz, at);",
+     "warp_coords(d, ev64(d, n, p->kid[2], xyz), ev64(d, n, p->kid[1], xyz), xyz, at);"),
+    ("warp rounds halves down", "(d->hi[k] - d->lo[k])) + 0.5;", "(d->hi[k] - d->lo[k])) + 0.4999;"),
 ]
 
 
