@@ -115,8 +115,9 @@ def test_served_against_oracle(env):
     srv = tgp.Server(ctx, 1 << 28, 4)
     srv.set_slab_work(float(1 << 16))  # several slabs even on the small grids
     cases = []
-    for i, shape in enumerate([(64, 64), (33, 47), (9, 10, 11)]):
-        pop = pg.ramped_half_and_half(30, 2, 7, 300 + i, pg.F18, len(shape))
+    for i, shape in enumerate([(64, 64), (33, 47), (9, 10, 11), (40, 24)]):
+        funcs = pg.F18 if i < 3 else pg.F18 + ("warp", "or", "xor", "and")
+        pop = pg.ramped_half_and_half(30, 2, 7, 300 + i, funcs, len(shape))
         w = Work(env, pop, shape, pg.TargetSpec(3, 310 + i, pg.F18, len(shape), 1))
         cases.append((w, srv.submit(i, pop, w.dom, w.target, 0)))
     for w, t in cases:
