@@ -382,6 +382,7 @@ def main():
     ap.add_argument("--tiles-per-item", type=int, default=0)
     ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--cache-access-cost", type=float, default=20.0)
+    ap.add_argument("--lds-stack", action="store_true", help="operand stack in LDS instead of registers")
     ap.add_argument("--generations", type=int, default=20, help="serving workload: generations per run")
     ap.add_argument("--loads", default="0.5,0.7,0.9", help="serving workload: offered loads")
     ap.add_argument("--no-plain", action="store_true", help="serving workload: skip the plain pass")
@@ -412,6 +413,7 @@ def main():
     ctx = tgp.Context(0)
     ctx.set_tuning(args.cases_per_lane, args.tiles_per_item)
     ctx.set_plan(not args.no_reorder, args.cache_access_cost)
+    ctx.set_stack(args.lds_stack)
     dom = tgp.Domain(ctx, dspec.shape)
 
     def render(tree):

@@ -180,6 +180,14 @@ tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles
  * subtrees needed to bound the stack.  Values never depend on either. */
 tgp_status tgp_ctx_set_plan(tgp_ctx ctx, int32_t reorder_children, double cache_access_cost);
 
+/* Where the interpreter keeps a program's operand stack: lds = 0 (default)
+ * in 8 register slots per case, with a dispatch block per stack depth and
+ * four cases per lane; lds != 0 in 16 LDS slots per case (the top of the
+ * stack in registers, one dispatch loop, two cases per lane), which needs
+ * fewer subtrees spilled to cache rows for deep programs.  Values never
+ * depend on it; the autotuner chooses between the two. */
+tgp_status tgp_ctx_set_stack(tgp_ctx ctx, int32_t lds);
+
 /* Test hook: keep only the low `bits` bits of the DAG builder's 64-bit key
  * hash (0 = all bits), forcing collisions so that the full-key comparison is
  * exercised.  Process-wide; the DAG produced must not change. */
@@ -315,9 +323,10 @@ typedef struct {
 } tgp_batch_stats;
 tgp_status tgp_batch_stats_get(tgp_batch batch, tgp_batch_stats *out);
 
-/* Autotuner: times cases-per-lane K in {2, 4} x the cap on tiles per work
- * item in {4, 16} x the batched launch form (persistent waves drawing items
- * from partitioned atomic counters, or one wave per item) on the given jobs
+/* Autotuner: times the stack form and cases per lane (registers with K in
+ * {2, 4}, or LDS with K = 2) x the cap on tiles per work item in {4, 16} x
+ * the batched launch form (persistent waves drawing items from partitioned
+ * atomic counters, or one wave per item) on the given jobs
  * (a warm-up and a timed batched run each) and installs the fastest in ctx.
  * With cache_path != NULL the choice is appended to that file (one JSON
  * object per line, keyed by the workload's size class) and reused without
@@ -325,6 +334,7 @@ tgp_status tgp_batch_stats_get(tgp_batch batch, tgp_batch_stats *out);
 typedef struct {
     int32_t cases_per_lane, tiles_cap, persistent;
     int32_t candidates, from_cache;
+    int32_t stack_lds;       /* chosen stack form (tgp_ctx_set_stack) */
     double best_ms;
 } tgp_tune_result;
 tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const char *cache_path,

@@ -85,6 +85,7 @@ struct tgp_batch_s {
     bool use_graph = true;
     bool persistent = true;  // persistent kernels, or one wave per work item
     bool ext = false;        // interpreter with the bitwise operators and warp
+    int D = 8;               // stack slots: 8 registers or the LDS form
     int K = 4;
     int levels_cap = 4;  // fill levels the graph has launches for
     int grid_store = 0, grid_reduce = 0;
@@ -152,7 +153,7 @@ static hipKernelNodeParams launch_params(tgp_batch b, int i, void **args) {
         const bool store = i <= L;
         const int g = i - 1;
         b->group_index[g] = g;
-        p.func = const_cast<void *>(batch_kernel(b->K, interp_max_stack(), store, b->persistent, b->ext));
+        p.func = const_cast<void *>(batch_kernel(b->K, b->D, store, b->persistent, b->ext));
         if (b->persistent) {
             p.gridDim = dim3(store ? b->grid_store : b->grid_reduce);
         } else {
@@ -319,12 +320,18 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
         b->staged = false;
     }
     bool ext = false;
-    for (int32_t j = 0; j < n_jobs; ++j) ext = ext || jobs[j].plan->ext;
+    const int D = ctx_stack_slots(ctx);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        ext = ext || jobs[j].plan->ext;
+        if (jobs[j].plan->D != D) return fail(ctx, TGP_EINVAL, "job %d was planned for another stack form", j);
+    }
     int K = ctx->force_K ? ctx->force_K : 4;
-    if (!interp_variant_exists(K, interp_max_stack(), ext)) K = 4;
-    if (K != b->K || ext != b->ext) {
+    if (ctx->stack_lds) K = 2;
+    if (!interp_variant_exists(K, D, ext)) K = 4;
+    if (K != b->K || ext != b->ext || D != b->D) {
         b->K = K;
         b->ext = ext;
+        b->D = D;
         b->stale = true;
     }
     const bool persistent = ctx->batch_persistent != 0;
@@ -496,7 +503,7 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
     if (e == hipSuccess) e = hipEventRecord(b->staged_ev, ctx->stream);
     if (e != hipSuccess) return fail(ctx, TGP_EHIP, "batch upload: %s", hipGetErrorString(e));
     b->staged = true;
-    const int gs = batch_grid(K, interp_max_stack(), true, ext), gr = batch_grid(K, interp_max_stack(), false, ext);
+    const int gs = batch_grid(K, D, true, ext), gr = batch_grid(K, D, false, ext);
     if (gs != b->grid_store || gr != b->grid_reduce) {
         b->grid_store = gs;
         b->grid_reduce = gr;
@@ -557,9 +564,11 @@ tgp_status tgp_fitness_batch(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs) {
 
 // ------------------------------------------------------------------ autotune
 //
-// Candidates: cases per lane K in {2, 4} x the cap on tiles per work item in
-// {4, 16} x the launch form (persistent waves or one wave per work item).  Each is timed (HIP events, after one warm-up run) on the
-// caller's own jobs; the fastest is installed in the context and, with a
+// Candidates: the stack form with its cases per lane (registers with K in
+// {4, 2}, LDS with K = 2) x the cap on tiles per work item in {4, 16} x the
+// launch form (persistent waves or one wave per work item).  Each is timed
+// (HIP events, after one warm-up run) on the caller's own jobs; the fastest
+// is installed in the context and, with a
 // cache path, recorded under a key made of the job count and the log2 sizes
 // of the batch's cases and instructions, so a later call with a workload of
 // the same class reuses it without timing.
@@ -575,24 +584,26 @@ static std::string tune_key(int32_t n_jobs, const tgp_job *jobs) {
     return buf;
 }
 
-static bool lookup(const char *path, const std::string &key, int *K, int *cap, int *pers) {
+static bool lookup(const char *path, const std::string &key, int *K, int *cap, int *pers, int *lds) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
     std::string line;
+    bool found = false;
     while (std::getline(f, line)) {
-        // one JSON object per line: {"key": "...", "K": k, "tiles_cap": t, "ms": m}
+        // one JSON object per line: {"key": "...", "K": k, "tiles_cap": t, "persistent": p, "lds": l, "ms": m}
         const std::string tag = "\"key\": \"" + key + "\"";
         if (line.find(tag) == std::string::npos) continue;
         const size_t a = line.find("\"K\": "), c = line.find("\"tiles_cap\": "),
-                     q = line.find("\"persistent\": ");
+                     q = line.find("\"persistent\": "), l = line.find("\"lds\": ");
         if (a == std::string::npos || c == std::string::npos || q == std::string::npos) continue;
         *K = atoi(line.c_str() + a + 5);
         *cap = atoi(line.c_str() + c + 13);
         *pers = atoi(line.c_str() + q + 14);
-        return true;
+        *lds = l == std::string::npos ? 0 : atoi(line.c_str() + l + 7);
+        found = true;  // the last record of the key wins
     }
-    return false;
+    return found;
 }
 
 tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const char *cache_path,
@@ -600,15 +611,18 @@ tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const 
     if (!ctx || n_jobs <= 0 || !jobs) return fail(ctx, TGP_EINVAL, "bad arguments");
     const std::string key = tune_key(n_jobs, jobs);
     tgp_tune_result r{};
-    int K = 0, cap = 0, pers = 1;
-    if (lookup(cache_path, key, &K, &cap, &pers) && interp_variant_exists(K, interp_max_stack())) {
+    int K = 0, cap = 0, pers = 1, lds = 0;
+    if (lookup(cache_path, key, &K, &cap, &pers, &lds) &&
+        interp_variant_exists(K, lds ? interp_lds_stack() : interp_max_stack(), lds != 0)) {
         ctx->force_K = K;
         ctx->tile_cap = cap;
         ctx->force_tiles = 0;
         ctx->batch_persistent = pers;
+        ctx->stack_lds = lds;
         r.cases_per_lane = K;
         r.tiles_cap = cap;
         r.persistent = pers;
+        r.stack_lds = lds;
         r.from_cache = 1;
         if (out) *out = r;
         return TGP_OK;
@@ -619,21 +633,24 @@ tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const 
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    const int Ks[2] = {4, 2};
+    // (stack form, cases per lane): registers with K = 4 or 2, LDS with K = 2
+    const int forms[3][2] = {{0, 4}, {0, 2}, {1, 2}};
     const int caps[2] = {4, 16};
     double best = 1e300;
-    int bestK = 4, bestCap = 16, bestP = 1, tried = 0;
+    int bestK = 4, bestCap = 16, bestP = 1, bestL = 0, tried = 0;
     const int oldK = ctx->force_K, oldCap = ctx->tile_cap, oldT = ctx->force_tiles,
-              oldP = ctx->batch_persistent;
-    for (int kk : Ks) {
-        if (!interp_variant_exists(kk, interp_max_stack())) continue;
+              oldP = ctx->batch_persistent, oldL = ctx->stack_lds;
+    for (const auto &f : forms) {
+        const int lf = f[0], kk = f[1];
+        if (!interp_variant_exists(kk, lf ? interp_lds_stack() : interp_max_stack(), lf != 0)) continue;
         for (int cp = 0; cp < 4; ++cp) {
             const int c = caps[cp % 2], pf = cp / 2 == 0 ? 1 : 0;
             ctx->force_K = kk;
             ctx->tile_cap = c;
             ctx->force_tiles = 0;
             ctx->batch_persistent = pf;
-            st = tgp_batch_run(b, n_jobs, jobs);  // warm-up
+            ctx->stack_lds = lf;
+            st = tgp_batch_run(b, n_jobs, jobs);  // warm-up (and planning for this stack form)
             if (st != TGP_OK) break;
             hipEventRecord(e0, ctx->stream);
             st = tgp_batch_run(b, n_jobs, jobs);
@@ -648,6 +665,7 @@ tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const 
                 bestK = kk;
                 bestCap = c;
                 bestP = pf;
+                bestL = lf;
             }
         }
         if (st != TGP_OK) break;
@@ -660,22 +678,25 @@ tgp_status tgp_autotune(tgp_ctx ctx, int32_t n_jobs, const tgp_job *jobs, const 
         ctx->tile_cap = oldCap;
         ctx->force_tiles = oldT;
         ctx->batch_persistent = oldP;
+        ctx->stack_lds = oldL;
         return st;
     }
     ctx->force_K = bestK;
     ctx->tile_cap = bestCap;
     ctx->force_tiles = 0;
     ctx->batch_persistent = bestP;
+    ctx->stack_lds = bestL;
     r.cases_per_lane = bestK;
     r.tiles_cap = bestCap;
     r.persistent = bestP;
+    r.stack_lds = bestL;
     r.best_ms = best;
     r.candidates = tried;
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
         if (f) {
             f << "{\"key\": \"" << key << "\", \"K\": " << bestK << ", \"tiles_cap\": " << bestCap
-              << ", \"persistent\": " << bestP << ", \"ms\": " << best << "}\n";
+              << ", \"persistent\": " << bestP << ", \"lds\": " << bestL << ", \"ms\": " << best << "}\n";
         }
     }
     if (out) *out = r;

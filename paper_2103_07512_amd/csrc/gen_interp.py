@@ -176,6 +176,111 @@ def body_for_depth(D):
     return "\n".join(L)
 
 
+def body_lds():
+    """The interpreter with its operand stack in LDS.
+
+    The top of the stack stays in registers (t); the values below it live in
+    this wave's LDS rows, slot s of case k of lane l at sl[(s * K + k) * 64 +
+    l] (consecutive lanes in consecutive banks).  A push stores t and moves
+    the new value into t; the first push stores an unused value into slot 0,
+    so a program of stack depth n uses slots 0 .. n - 1.  One dispatch loop
+    serves every depth: the slot index is a run-time scalar, which LDS
+    addressing allows and registers do not.
+    """
+    L = []
+    e = L.append
+    e("// Operand stack in LDS (top of stack in registers); see gen_interp.py.")
+    e("template <int K>")
+    e("__device__ __forceinline__ void lds_put(float *sl, uint32_t s, int lane, const FV<K> &v) {")
+    e("#pragma unroll")
+    e("    for (int k = 0; k < K; ++k) sl[(s * K + k) * 64 + lane] = v.v[k];")
+    e("}")
+    e("template <int K>")
+    e("__device__ __forceinline__ FV<K> lds_get(const float *sl, uint32_t s, int lane) {")
+    e("    FV<K> v;")
+    e("#pragma unroll")
+    e("    for (int k = 0; k < K; ++k) v.v[k] = sl[(s * K + k) * 64 + lane];")
+    e("    return v;")
+    e("}")
+    e("template <int K>")
+    e("__device__ __forceinline__ void run_prog_lds(const uint2 *__restrict__ ip, const FV<K> &xv,")
+    e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
+    e("        const int32_t (&cidx)[K], const WarpGeom &wg, float *sl, int lane, FV<K> &res)")
+    e("{")
+    e("    FV<K> t;")
+    e("#pragma unroll")
+    e("    for (int k = 0; k < K; ++k) t.v[k] = 0.0f;")
+    e("    uint32_t sp = 0;  // values stored in LDS")
+    e("    for (;;) {")
+    e("        const uint2 ins = *ip;")
+    e("        ++ip;")
+    e("        switch (ins.x & 0xffu) {")
+    for name, reg in (("I_X", "xv"), ("I_Y", "yv"), ("I_Z", "zv")):
+        e(f"        case {name}: lds_put<K>(sl, sp++, lane, t); t = {reg}; break;")
+    e("        case I_CONST: {")
+    e("            lds_put<K>(sl, sp++, lane, t);")
+    e("            const float c = __uint_as_float(ins.y);")
+    e("#pragma unroll")
+    e("            for (int k = 0; k < K; ++k) t.v[k] = c;")
+    e("            break;")
+    e("        }")
+    e("        case I_CACHE: {")
+    e("            lds_put<K>(sl, sp++, lane, t);")
+    e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+    e("#pragma unroll")
+    e("            for (int k = 0; k < K; ++k) t.v[k] = row[cidx[k]];")
+    e("            break;")
+    e("        }")
+    e("        case I_END: res = t; return;")
+    e("        case I_WARP: {")
+    e("            const FV<K> t0 = lds_get<K>(sl, --sp, lane);")
+    e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+    e("#pragma unroll")
+    e("            for (int k = 0; k < K; ++k) t.v[k] = row[warp_case(wg, t0.v[k], t.v[k], cidx[k])];")
+    e("            break;")
+    e("        }")
+    for name, op, ar in FUNCS:
+        if name in BITWISE[1:]:
+            continue
+        variants = [(FN_BASE + op, tuple(range(ar)))]
+        if name in REVERSIBLE:
+            variants.append((REV_BASE + op, (1, 0)))
+        if name in TERNARY:
+            t = TERNARY.index(name)
+            variants += [(PERM_BASE + 6 * t + p, order) for p, order in enumerate(PERMS) if p]
+        for c, order in variants:
+            e(f"        case {c}: {{")
+            # stack values in evaluation order: the deepest first, t last;
+            # child order[i] is the i-th value
+            names = [f"u{i}" for i in range(ar)]
+            for i in range(ar - 1):
+                e(f"            const FV<K> {names[i]} = lds_get<K>(sl, sp - {ar - 1 - i}, lane);")
+            if ar > 1:
+                e(f"            sp -= {ar - 1};")
+            e(f"            const FV<K> {names[ar - 1]} = t;")
+            args = [names[order.index(i)] for i in range(ar)]
+            if name == BITWISE[0]:
+                e("            const uint32_t kind = (ins.x >> 8) & 3u;")
+                e("#pragma unroll")
+                e(f"            for (int k = 0; k < K; ++k) t.v[k] = f_bitop({args[0]}.v[k], {args[1]}.v[k], kind);")
+            elif name in CALLED:
+                e(f"            t = vcall_{name}<K>({', '.join(args)});")
+            else:
+                e("#pragma unroll")
+                e(f"            for (int k = 0; k < K; ++k) t.v[k] = f_{name}({', '.join(a + '.v[k]' for a in args)});")
+            e("            break;")
+            e("        }")
+    e("        default:")
+    e("#pragma unroll")
+    e("            for (int k = 0; k < K; ++k) res.v[k] = __builtin_nanf(\"\");")
+    e("            return;")
+    e("        }")
+    e("    }")
+    e("}")
+    e("")
+    return "\n".join(L)
+
+
 def generate():
     out = ["// interp_gen.inc -- GENERATED by gen_interp.py; do not edit.",
            "// Stack-depth-specialised postfix interpreters, one per stack size.",
@@ -184,6 +289,7 @@ def generate():
            called_functions()]
     for D in DEPTHS:
         out.append(body_for_depth(D))
+    out.append(body_lds())
     return "\n".join(out) + "\n"
 
 

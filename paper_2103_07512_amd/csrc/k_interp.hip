@@ -80,12 +80,27 @@ __device__ __forceinline__ void kahan_merge(float &s, float &c, float s2, float 
     s = t;
 }
 
+// Stack forms: D = 8 register slots (depth-specialised dispatch), or
+// D = kLdsSlots slots in LDS (one dispatch loop, top of stack in registers).
+constexpr int kLdsSlots = 16;
+
 template <int K, int D, bool EXT>
 __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const FV<K> &yv,
                                          const FV<K> &zv, const float *cache, int64_t cache_stride,
-                                         const int32_t (&cidx)[K], const WarpGeom &wg, FV<K> &res) {
-    static_assert(D == 8, "compiled stack size: 8");
-    run_prog_d8<K, EXT>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, res);
+                                         const int32_t (&cidx)[K], const WarpGeom &wg, float *sl,
+                                         int lane, FV<K> &res) {
+    static_assert(D == 8 || D == kLdsSlots, "compiled stack forms: 8 registers, 16 LDS slots");
+    if constexpr (D == kLdsSlots)
+        run_prog_lds<K>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, sl, lane, res);
+    else
+        run_prog_d8<K, EXT>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, res);
+}
+
+// This wave's LDS stack rows (one wave per workgroup).
+template <int K, int D>
+__device__ __forceinline__ float *lds_stack() {
+    __shared__ float rows[D == kLdsSlots ? kLdsSlots * K * 64 : 1];
+    return rows;
 }
 
 // One work item: program `code` over tiles_per_stripe tiles of one stripe.
@@ -132,11 +147,11 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
         }
         FV<K> res;
         WarpGeom wg{};
-        if constexpr (EXT) {
+        if constexpr (EXT || D == kLdsSlots) {
             wg = WarpGeom{a.warp_lo[0], a.warp_lo[1], a.warp_scale[0], a.warp_scale[1], a.shape[0], a.shape[1],
                           (uint32_t)a.stride[0], (uint32_t)a.stride[1], a.ndim};
         }
-        run_prog<K, D, EXT>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, wg, res);
+        run_prog<K, D, EXT>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, wg, lds_stack<K, D>(), lane, res);
         if constexpr (MODE == MODE_STORE) {
             float *row = a.out + (size_t)dest * (size_t)a.out_stride;
 #pragma unroll
@@ -370,12 +385,13 @@ static int grid_bd(bool store) {
 }
 
 // Instantiated interpreters: (cases per lane, stack slots, bitwise operators
-// and warp).
+// and warp).  The LDS-stack form knows every operator.
 #ifndef TGP_VARIANTS
-#define TGP_VARIANTS(X) X(4, 8, false) X(2, 8, false) X(4, 8, true)
+#define TGP_VARIANTS(X) X(4, 8, false) X(2, 8, false) X(4, 8, true) X(2, 16, true)
 #endif
 
 bool interp_variant_exists(int K, int D, bool bit) {
+    if (D == kLdsSlots) bit = true;
 #define X(k, d, b) if (K == k && D == d && bit == b) return true;
     TGP_VARIANTS(X)
 #undef X
@@ -383,8 +399,10 @@ bool interp_variant_exists(int K, int D, bool bit) {
 }
 
 int interp_max_stack() { return 8; }
+int interp_lds_stack() { return kLdsSlots; }
 
 hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStream_t s, bool bit) {
+    if (D == kLdsSlots) bit = true;
 #define X(k, d, b) if (K == k && D == d && bit == b) return launch_kd<k, d, b>(store, a, s);
     TGP_VARIANTS(X)
 #undef X
@@ -392,6 +410,7 @@ hipError_t launch_interp(int K, int D, bool store, const InterpArgs &a, hipStrea
 }
 
 const void *batch_kernel(int K, int D, bool store, bool persistent, bool bit) {
+    if (D == kLdsSlots) bit = true;
 #define X(k, d, b) if (K == k && D == d && bit == b) return batch_fn<k, d, b>(store, persistent);
     TGP_VARIANTS(X)
 #undef X
@@ -399,6 +418,7 @@ const void *batch_kernel(int K, int D, bool store, bool persistent, bool bit) {
 }
 
 int batch_grid(int K, int D, bool store, bool bit) {
+    if (D == kLdsSlots) bit = true;
 #define X(k, d, b) if (K == k && D == d && bit == b) return grid_bd<k, d, b>(store);
     TGP_VARIANTS(X)
 #undef X

@@ -200,6 +200,12 @@ tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles
     return TGP_OK;
 }
 
+tgp_status tgp_ctx_set_stack(tgp_ctx ctx, int32_t lds) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    ctx->stack_lds = lds != 0;
+    return TGP_OK;
+}
+
 tgp_status tgp_ctx_set_plan(tgp_ctx ctx, int32_t reorder_children, double cache_access_cost) {
     if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
     ctx->reorder = reorder_children != 0;
@@ -659,9 +665,14 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
 
 static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases);
 
+int ctx_stack_slots(tgp_ctx ctx) { return ctx->stack_lds ? interp_lds_stack() : interp_max_stack(); }
+
 tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     const double t0 = now_ms();
-    tgp_status st = d->plan.cases == cases ? TGP_OK : build_plan_impl(ctx, d, cases);
+    const Plan &P = d->plan;
+    const bool same = P.cases == cases && P.D == ctx_stack_slots(ctx) && P.reorder == (ctx->reorder != 0) &&
+                      P.access_cost == ctx->cache_access_cost;
+    tgp_status st = same ? TGP_OK : build_plan_impl(ctx, d, cases);
     ctx->times.plan_ms = now_ms() - t0;
     return st;
 }
@@ -702,7 +713,10 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
             P.dup_src[r] = store_of[n];
         }
     }
-    const int D = interp_max_stack();
+    const int D = ctx_stack_slots(ctx);
+    P.D = D;
+    P.reorder = ctx->reorder != 0;
+    P.access_cost = ctx->cache_access_cost;
     size_t budget_slots = (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
     Planner pl(*d, D, budget_slots);
     pl.reorder = ctx->reorder != 0;
@@ -869,7 +883,8 @@ void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *s
 }
 
 int choose_K(tgp_ctx ctx, int64_t cases, bool ext) {
-    if (ext) return 4;  // the one interpreter built with the bitwise operators and warp
+    if (ctx->stack_lds) return 2;  // the LDS-stack interpreter
+    if (ext) return 4;  // the register-stack interpreter built with the bitwise operators and warp
     if (ctx->force_K) return ctx->force_K;
     return cases >= 64 * 4 * 4 ? 4 : 2;
 }
@@ -918,7 +933,7 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
         a.n_progs = e - b;
         choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
         a.job.out = cache;
-        HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.ext));
+        HCHK(ctx, launch_interp(K, P.D, true, a, ctx->stream, P.ext));
     }
     record(ctx, 1);
     return TGP_OK;
@@ -977,7 +992,7 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     HCHK(ctx, ensure(ctx->partial, sizeof(float2) * (size_t)a.n_progs * (size_t)a.job.n_stripes));
     a.job.partial = (float2 *)ctx->partial.p;
     record(ctx, 2);
-    HCHK(ctx, launch_interp(K, interp_max_stack(), false, a, ctx->stream, P.ext));
+    HCHK(ctx, launch_interp(K, P.D, false, a, ctx->stream, P.ext));
     record(ctx, 3);
     record(ctx, 4);
     HCHK(ctx, launch_finalize(a.job.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.job.n_stripes,
@@ -1010,7 +1025,7 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
     a.job.out = out_dev;
     record(ctx, 2);
-    HCHK(ctx, launch_interp(K, interp_max_stack(), true, a, ctx->stream, P.ext));
+    HCHK(ctx, launch_interp(K, P.D, true, a, ctx->stream, P.ext));
     record(ctx, 3);
     record(ctx, 4);
     record(ctx, 5);

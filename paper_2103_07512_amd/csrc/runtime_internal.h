@@ -31,6 +31,7 @@ struct tgp_ctx_s {
     tgp_batch batch = nullptr;  // kept by tgp_fitness_batch
     int reorder = 1;                     // Sethi-Ullman child order
     bool plan_upload = true;             // plans also kept on the device
+    int stack_lds = 0;                   // operand stack in LDS (1) or registers (0)
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
     DevicePool pool;             // DAG, plan and population blocks
@@ -68,6 +69,9 @@ struct tgp_domain_s {
 // A compiled evaluation plan of one DAG for one case count.
 struct Plan {
     int64_t cases = -1;
+    int D = 0;                          // stack slots the programs were planned for
+    bool reorder = true;
+    double access_cost = 0;
     int32_t n_slots = 0;
     int64_t n_spills = 0;               // cached only to bound the register stack
     std::vector<int32_t> level_first;   // fill programs of level l: [level_first[l], level_first[l+1])
@@ -179,6 +183,7 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
 extern const double kOpCost[TGP_NUM_OPS];
 tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases);
 int choose_K(tgp_ctx ctx, int64_t cases, bool ext);
+int ctx_stack_slots(tgp_ctx ctx);
 void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,
                   int32_t *tiles_per);
 void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache);

@@ -153,7 +153,8 @@ hipError_t launch_reset(uint32_t *counters, int32_t n, hipStream_t s);
 hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
                                  int32_t grid, hipStream_t s);
 bool interp_variant_exists(int K, int D, bool bit = false);
-int interp_max_stack();   // largest D compiled
+int interp_max_stack();   // register stack slots
+int interp_lds_stack();   // LDS stack slots (the other stack form, K = 2)
 
 // Finalize: per individual, FP64 sum of its channels' partial rows.
 hipError_t launch_finalize(const float2 *partial, const int32_t *ind_rows, int32_t n_ind,

@@ -87,7 +87,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("cases_per_lane", ctypes.c_int32), ("tiles_cap", ctypes.c_int32),
                 ("persistent", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("best_ms", ctypes.c_double)]
+                ("stack_lds", ctypes.c_int32), ("best_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -131,6 +131,7 @@ SIGNATURES = [
     ("tgp_ctx_set_cache_budget", I32, [P, ctypes.c_size_t]),
     ("tgp_ctx_set_tuning", I32, [P, I32, I32]),
     ("tgp_ctx_set_plan", I32, [P, I32, ctypes.c_double]),
+    ("tgp_ctx_set_stack", I32, [P, I32]),
     ("tgp_debug_set_hash_bits", I32, [I32]),
     ("tgp_domain_create", I32, [P, I32, P, P, P, PP]),
     ("tgp_domain_destroy", None, [P]),
@@ -224,6 +225,10 @@ class Context:
 
     def set_plan(self, reorder_children: bool = True, cache_access_cost: float = 20.0):
         _check(lib().tgp_ctx_set_plan(self.h, 1 if reorder_children else 0, cache_access_cost), self.h)
+
+    def set_stack(self, lds: bool = False):
+        """Operand stack in LDS (True) or in registers (False, the default)."""
+        _check(lib().tgp_ctx_set_stack(self.h, 1 if lds else 0), self.h)
 
     def set_batch_form(self, persistent: bool = True):
         _check(lib().tgp_ctx_set_batch_form(self.h, 1 if persistent else 0), self.h)

@@ -140,6 +140,24 @@ def test_fitness_batch_against_oracle(env):
             assert abs(g[i] - f64[i]) <= max(1e-6 * f64[i], 2 * ef[i]), (i, g[i], f64[i])
 
 
+def test_batch_lds_stack(env):
+    """Batched steps with the LDS stack agree with the register form."""
+    tgp, ctx, torch = env
+    jobs = make_jobs(env, small_c4(17, 6))
+    want = plain(env, jobs)
+    try:
+        ctx.set_stack(True)
+        b = tgp.Batch(ctx, use_graph=True)
+        b.run(jobs)
+        torch.cuda.synchronize()
+        st = b.stats()
+        assert st["cases_per_lane"] == 2
+        for (dag, _, _, _, out), w in zip(jobs, want):
+            same(out.cpu().numpy(), w, 1e-6)
+    finally:
+        ctx.set_stack(False)
+
+
 def test_autotune_and_cache(env, tmp_path):
     tgp, ctx, torch = env
     jobs = make_jobs(env, small_c4(13, 5))
@@ -148,14 +166,16 @@ def test_autotune_and_cache(env, tmp_path):
     r1 = tgp.autotune(ctx, jobs, path)
     say(r1)
     assert r1["cases_per_lane"] in (2, 4) and r1["tiles_cap"] in (4, 8, 16, 32)
-    assert r1["from_cache"] == 0 and r1["candidates"] == 8
+    assert r1["from_cache"] == 0 and r1["candidates"] == 12 and r1["stack_lds"] in (0, 1)
     r2 = tgp.autotune(ctx, jobs, path)
-    assert r2["from_cache"] == 1 and (r2["cases_per_lane"], r2["tiles_cap"]) == (r1["cases_per_lane"], r1["tiles_cap"])
+    assert r2["from_cache"] == 1 and (r2["cases_per_lane"], r2["tiles_cap"], r2["stack_lds"]) == \
+        (r1["cases_per_lane"], r1["tiles_cap"], r1["stack_lds"])
     assert os.path.getsize(path) > 0
     # results under the tuned shape still match the plain path within the fitness tolerance
     tgp.fitness_batch(ctx, jobs)
     torch.cuda.synchronize()
     ctx.set_tuning(0, 0)
+    ctx.set_stack(False)
     want = plain(env, jobs)
     for (dag, _, _, _, out), w in zip(jobs, want):
         same(out.cpu().numpy(), w, 1e-6)

@@ -254,6 +254,39 @@ def test_tuning_does_not_change_values(env):
         assert np.array_equal(outs[0].view(np.uint32), o.view(np.uint32))
 
 
+def test_lds_stack_form(env):
+    """The LDS-stack interpreter: per-case values bitwise equal to the register
+    form's (same operators, same order), parity with the oracle, and deep
+    programs that the register form must spill run without spills."""
+    tgp, ctx, torch = env
+    funcs = tuple(n for n, a in pg.OPS if a > 0)
+    pop = pg.ramped_half_and_half(60, 2, 9, 91, funcs, 2)
+    shape = (41, 37)
+    regs, dag_r, _ = gpu_eval(env, pop, shape)
+    try:
+        ctx.set_stack(True)
+        say("LDS stack: all operators")
+        lds, dag_l, dom = gpu_eval(env, pop, shape)
+        assert np.array_equal(regs.view(np.uint32), lds.view(np.uint32))
+        _full_parity(env, pop, shape, pg.TargetSpec(3, 92, pg.F6, 2, 1), what="LDS stack")
+
+        # complete binary trees of depth 9 and 12 need a stack of 10 and 13
+        def full(d, v):
+            return v if d == 0 else f"sub({full(d - 1, v)}, mult({full(d - 1, v)}, 0.5))"
+        deep = pg.population_from_texts([full(9, "x"), full(12, "y")])
+        got, dag, dom = gpu_eval(env, deep, (16, 16))
+        w = ctx.last_work()
+        say("LDS stack, deep programs:", w["stack_spills"], "spills")
+        assert w["stack_spills"] == 0
+        v64, v32, st, eb = oracle.evaluate(deep.tokens, deep.offsets, (16, 16), bound=True)
+        _parity.check_cases(got, v64, v32, st, "LDS deep")
+    finally:
+        ctx.set_stack(False)
+    got_r, _, _ = gpu_eval(env, deep, (16, 16))
+    assert ctx.last_work()["stack_spills"] > 0
+    assert np.array_equal(got.view(np.uint32), got_r.view(np.uint32))
+
+
 def test_determinism_and_duplicates(env):
     tgp, ctx, torch = env
     pop = pg.ramped_half_and_half(30, 2, 8, 91, pg.F18, 2)
