@@ -188,6 +188,12 @@ tgp_status tgp_ctx_set_plan(tgp_ctx ctx, int32_t reorder_children, double cache_
  * depend on it; the autotuner chooses between the two. */
 tgp_status tgp_ctx_set_stack(tgp_ctx ctx, int32_t lds);
 
+/* Constant folding (default on): a subtree with no variable has the same
+ * value at every case, so it is evaluated once, on the device with the
+ * interpreter's own FP32 operators, and its programs use the value as a
+ * constant.  Values are bitwise the same either way. */
+tgp_status tgp_ctx_set_folding(tgp_ctx ctx, int32_t on);
+
 /* Test hook: keep only the low `bits` bits of the DAG builder's 64-bit key
  * hash (0 = all bits), forcing collisions so that the full-key comparison is
  * exercised.  Process-wide; the DAG produced must not change. */
@@ -259,6 +265,7 @@ typedef struct {
     double executed_valu_roots;  /* root-program launch, cost model x cases */
     int64_t cache_bytes_read;    /* HBM bytes of cache loads (algorithmic) */
     int64_t cache_bytes_written; /* HBM bytes of cache stores (algorithmic) */
+    int64_t folded_nodes;        /* constant subtrees evaluated once and used as constants */
 } tgp_work_stats;
 tgp_status tgp_last_work(tgp_ctx ctx, tgp_work_stats *out);
 

@@ -200,6 +200,12 @@ tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles
     return TGP_OK;
 }
 
+tgp_status tgp_ctx_set_folding(tgp_ctx ctx, int32_t on) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    ctx->fold = on != 0;
+    return TGP_OK;
+}
+
 tgp_status tgp_ctx_set_stack(tgp_ctx ctx, int32_t lds) {
     if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
     ctx->stack_lds = lds != 0;
@@ -443,7 +449,10 @@ struct Planner {
 
     Planner(const tgp_dag_s &dag, int stack, size_t slots) : d(dag), D(stack), budget_slots(slots) {}
 
-    int op(int64_t n) const { return d.op[n] & 0xff; }
+    std::vector<uint8_t> folded;  // constant subtrees replaced by their value
+    std::vector<float> fold_val;
+    // A folded node is a constant leaf for the planner.
+    int op(int64_t n) const { return !folded.empty() && folded[n] ? TGP_CONST : (d.op[n] & 0xff); }
     int arity(int64_t n) const { return kArity[op(n)]; }
 
     // Decide the cached nodes; returns TGP_OK or an error.
@@ -604,7 +613,7 @@ struct Planner {
                     ins.x = v == 0 ? I_X : (v == 1 ? I_Y : I_Z);
                 } else if (o == TGP_CONST) {
                     ins.x = I_CONST;
-                    memcpy(&ins.y, &d.value[n], 4);
+                    memcpy(&ins.y, !folded.empty() && folded[n] ? &fold_val[n] : &d.value[n], 4);
                 } else if (o == TGP_OR || o == TGP_XOR || o == TGP_AND) {
                     ins.x = (kFnBase + TGP_OR) | ((uint32_t)(o - TGP_OR) << 8);
                 } else if (o == TGP_WARP) {
@@ -665,13 +674,78 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
 
 static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases);
 
+// Constant subtrees (no variable below) that some non-constant node or a
+// root uses are evaluated once on the device, height by height; folded[n]
+// marks them and fold_val[n] holds their FP32 value.
+static tgp_status fold_constants(tgp_ctx ctx, tgp_dag d, std::vector<uint8_t> &folded,
+                                 std::vector<float> &fold_val) {
+    const int64_t U = d->stats.dag_nodes;
+    std::vector<uint8_t> novar(U, 0), use(U, 0);
+    int32_t max_h = 0;
+    for (int64_t n = 0; n < U; ++n) {  // children have smaller ids
+        const int o = d->op[n] & 0xff;
+        bool nv = o != TGP_VAR;
+        for (int j = 0; j < kArity[o]; ++j) nv = nv && novar[d->kid[3 * n + j]];
+        novar[n] = nv;
+        if (nv) max_h = std::max(max_h, d->height[n]);
+    }
+    int64_t n_use = 0;
+    auto mark = [&](int32_t c) {
+        if (novar[c] && kArity[d->op[c] & 0xff] > 0 && !use[c]) {
+            use[c] = 1;
+            ++n_use;
+        }
+    };
+    for (int64_t n = 0; n < U; ++n)
+        if (!novar[n])
+            for (int j = 0; j < kArity[d->op[n] & 0xff]; ++j) mark(d->kid[3 * n + j]);
+    for (int32_t r : d->roots) mark(r);
+    if (n_use == 0) return TGP_OK;
+    // every variable-free node, by height (children before parents)
+    std::vector<int32_t> first(max_h + 2, 0), list;
+    for (int64_t n = 0; n < U; ++n)
+        if (novar[n]) ++first[d->height[n] + 1];
+    for (int h = 0; h <= max_h; ++h) first[h + 1] += first[h];
+    list.resize(first[max_h + 1]);
+    {
+        std::vector<int32_t> at(first.begin(), first.end() - 1);
+        for (int64_t n = 0; n < U; ++n)
+            if (novar[n]) list[at[d->height[n]]++] = (int32_t)n;
+    }
+    int32_t *list_dev = nullptr;
+    float *val_dev = nullptr;
+    void *stage = nullptr;
+    hipError_t e = ctx->pool.alloc((void **)&list_dev, sizeof(int32_t) * list.size());
+    if (e == hipSuccess) e = ctx->pool.alloc((void **)&val_dev, sizeof(float) * U);
+    if (e == hipSuccess) e = ctx_pinned(ctx, sizeof(int32_t) * list.size(), &stage);
+    if (e == hipSuccess) {
+        memcpy(stage, list.data(), sizeof(int32_t) * list.size());
+        e = hipMemcpyAsync(list_dev, stage, sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, ctx->stream);
+    }
+    if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
+    for (int h = 0; h <= max_h && e == hipSuccess; ++h)
+        e = launch_fold_level(d->dev.node_op, d->dev.node_value, d->dev.node_kid, list_dev + first[h],
+                              first[h + 1] - first[h], val_dev, ctx->stream);
+    fold_val.assign(U, 0.0f);
+    if (e == hipSuccess) e = ctx_pinned(ctx, sizeof(float) * U, &stage);
+    if (e == hipSuccess) e = hipMemcpyAsync(stage, val_dev, sizeof(float) * U, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) memcpy(fold_val.data(), stage, sizeof(float) * U);
+    hipStreamSynchronize(ctx->stream);
+    ctx->pool.release(list_dev);
+    ctx->pool.release(val_dev);
+    if (e != hipSuccess) return fail(ctx, TGP_EHIP, "constant folding: %s", hipGetErrorString(e));
+    folded.swap(use);
+    return TGP_OK;
+}
+
 int ctx_stack_slots(tgp_ctx ctx) { return ctx->stack_lds ? interp_lds_stack() : interp_max_stack(); }
 
 tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     const double t0 = now_ms();
     const Plan &P = d->plan;
     const bool same = P.cases == cases && P.D == ctx_stack_slots(ctx) && P.reorder == (ctx->reorder != 0) &&
-                      P.access_cost == ctx->cache_access_cost;
+                      P.access_cost == ctx->cache_access_cost && P.fold == ctx->fold;
     tgp_status st = same ? TGP_OK : build_plan_impl(ctx, d, cases);
     ctx->times.plan_ms = now_ms() - t0;
     return st;
@@ -717,8 +791,15 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.D = D;
     P.reorder = ctx->reorder != 0;
     P.access_cost = ctx->cache_access_cost;
+    P.fold = ctx->fold;
     size_t budget_slots = (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
     Planner pl(*d, D, budget_slots);
+    if (ctx->fold) {
+        tgp_status fs = fold_constants(ctx, d, pl.folded, pl.fold_val);
+        if (fs != TGP_OK) return fs;
+    }
+    P.n_folded = 0;
+    for (uint8_t f : pl.folded) P.n_folded += f;
     pl.reorder = ctx->reorder != 0;
     pl.access_cost = ctx->cache_access_cost;
     std::string why;
@@ -964,6 +1045,7 @@ static void record_work(tgp_ctx ctx, tgp_dag d, tgp_domain dom, bool fitness) {
     w.executed_valu_roots = P.valu_roots_per_case * cases;
     w.cache_bytes_written = (int64_t)P.n_slots * dom->cases * 4;
     w.cache_bytes_read = P.cache_reads_per_case * dom->cases * 4;
+    w.folded_nodes = P.n_folded;
 }
 
 extern "C" {

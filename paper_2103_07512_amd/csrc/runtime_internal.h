@@ -32,6 +32,7 @@ struct tgp_ctx_s {
     int reorder = 1;                     // Sethi-Ullman child order
     bool plan_upload = true;             // plans also kept on the device
     int stack_lds = 0;                   // operand stack in LDS (1) or registers (0)
+    int fold = 1;                        // constant folding
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
     DevicePool pool;             // DAG, plan and population blocks
@@ -72,6 +73,8 @@ struct Plan {
     int D = 0;                          // stack slots the programs were planned for
     bool reorder = true;
     double access_cost = 0;
+    int fold = -1;
+    int64_t n_folded = 0;               // constant subtrees folded
     int32_t n_slots = 0;
     int64_t n_spills = 0;               // cached only to bound the register stack
     std::vector<int32_t> level_first;   // fill programs of level l: [level_first[l], level_first[l+1])

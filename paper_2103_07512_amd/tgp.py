@@ -51,7 +51,7 @@ class WorkStats(ctypes.Structure):
                 ("programs", ctypes.c_int64), ("instructions", ctypes.c_int64),
                 ("algorithmic_valu", ctypes.c_double), ("executed_valu_fill", ctypes.c_double),
                 ("executed_valu_roots", ctypes.c_double), ("cache_bytes_read", ctypes.c_int64),
-                ("cache_bytes_written", ctypes.c_int64)]
+                ("cache_bytes_written", ctypes.c_int64), ("folded_nodes", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -132,6 +132,7 @@ SIGNATURES = [
     ("tgp_ctx_set_tuning", I32, [P, I32, I32]),
     ("tgp_ctx_set_plan", I32, [P, I32, ctypes.c_double]),
     ("tgp_ctx_set_stack", I32, [P, I32]),
+    ("tgp_ctx_set_folding", I32, [P, I32]),
     ("tgp_debug_set_hash_bits", I32, [I32]),
     ("tgp_domain_create", I32, [P, I32, P, P, P, PP]),
     ("tgp_domain_destroy", None, [P]),
@@ -225,6 +226,10 @@ class Context:
 
     def set_plan(self, reorder_children: bool = True, cache_access_cost: float = 20.0):
         _check(lib().tgp_ctx_set_plan(self.h, 1 if reorder_children else 0, cache_access_cost), self.h)
+
+    def set_folding(self, on: bool = True):
+        """Evaluate constant subtrees once and use their values as constants."""
+        _check(lib().tgp_ctx_set_folding(self.h, 1 if on else 0), self.h)
 
     def set_stack(self, lds: bool = False):
         """Operand stack in LDS (True) or in registers (False, the default)."""

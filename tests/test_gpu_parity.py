@@ -254,6 +254,42 @@ def test_tuning_does_not_change_values(env):
         assert np.array_equal(outs[0].view(np.uint32), o.view(np.uint32))
 
 
+def test_constant_folding_bitwise(env):
+    """Subtrees without variables, evaluated once and used as constants, give
+    bitwise the per-case values and fitness of evaluating them everywhere."""
+    tgp, ctx, torch = env
+    funcs = tuple(n for n, a in pg.OPS if a > 0)
+    pop = pg.ramped_half_and_half(120, 2, 8, 97, funcs, 2)
+    extra = pg.population_from_texts([
+        "add(0.5, sin(0.25))", "pow(-0.5, 0.5)", "mult(x, add(0.25, exp(0.5)))",
+        "warp(sub(0.3, 0.1), x, y)", "div(x, sub(0.5, 0.5))", "add(y, mod(0.7, neg(0.2)))"])
+    both = pg.Population.from_trees(pop.trees() + extra.trees())
+    shape = (33, 29)
+    target = finite_target(pg.TargetSpec(3, 98, pg.F6, 2, 1), shape)
+    res = {}
+    try:
+        for on in (False, True):
+            ctx.set_folding(on)
+            got, dag, dom = gpu_eval(env, both, shape)
+            w = ctx.last_work()
+            f = gpu_fit(env, both, dom, dag, target)
+            res[on] = (got, f, w)
+    finally:
+        ctx.set_folding(True)
+    say("folded subtrees:", res[True][2]["folded_nodes"], "executed",
+        res[False][2]["executed_node_evals"], "->", res[True][2]["executed_node_evals"])
+    assert res[False][2]["folded_nodes"] == 0 and res[True][2]["folded_nodes"] > 20
+    assert res[True][2]["executed_node_evals"] < res[False][2]["executed_node_evals"]
+    # bitwise, except that a NaN's sign and payload are not part of its value
+    a, b = res[False][0], res[True][0]
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    m = ~np.isnan(a)
+    assert np.array_equal(a[m].view(np.uint32), b[m].view(np.uint32))
+    assert np.array_equal(res[False][1].view(np.uint64), res[True][1].view(np.uint64))
+    v64, v32, st, eb = oracle.evaluate(both.tokens, both.offsets, shape, bound=True)
+    _parity.check_cases(res[True][0], v64, v32, st, "folded")
+
+
 def test_lds_stack_form(env):
     """The LDS-stack interpreter: per-case values bitwise equal to the register
     form's (same operators, same order), parity with the oracle, and deep
