@@ -497,7 +497,7 @@ def main():
                      "kernel_ms": interp_ms},
         "detail": {
             "phases_ms": {k: float(np.mean([t[k] for t in times]))
-                          for k in ("build_dag_ms", "plan_ms", "fill_ms", "interp_ms", "finalize_ms")},
+                          for k in ("build_dag_ms", "plan_ms", "plan_fold_ms", "plan_decide_ms", "plan_emit_ms", "fill_ms", "interp_ms", "finalize_ms")},
             "launch": {k: times[-1][k] for k in ("interp_items", "cases_per_lane", "tiles_per_item")},
             "work": work,
             "executed_node_evals_per_s": work["executed_node_evals"] / (ms / 1e3),

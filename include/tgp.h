@@ -282,6 +282,9 @@ typedef struct {
     int64_t interp_items; /* work items (waves) of the root-program launch */
     int32_t cases_per_lane;
     int32_t tiles_per_item;
+    /* parts of plan_ms: constant folding (with its device round trip), the
+     * caching and stack decisions, program emission, the rest */
+    double plan_fold_ms, plan_decide_ms, plan_emit_ms;
 } tgp_timing;
 tgp_status tgp_ctx_set_timing(tgp_ctx ctx, int32_t enable);
 tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out);

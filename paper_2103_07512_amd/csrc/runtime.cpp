@@ -794,10 +794,13 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.fold = ctx->fold;
     size_t budget_slots = (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
     Planner pl(*d, D, budget_slots);
+    const double tf0 = now_ms();
     if (ctx->fold) {
         tgp_status fs = fold_constants(ctx, d, pl.folded, pl.fold_val);
         if (fs != TGP_OK) return fs;
     }
+    const double tf1 = now_ms();
+    ctx->times.plan_fold_ms = tf1 - tf0;
     P.n_folded = 0;
     for (uint8_t f : pl.folded) P.n_folded += f;
     pl.reorder = ctx->reorder != 0;
@@ -805,6 +808,8 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     std::string why;
     tgp_status st = pl.decide(rootrefs, why);
     if (st != TGP_OK) return fail(ctx, st, "%s", why.c_str());
+    const double td1 = now_ms();
+    ctx->times.plan_decide_ms = td1 - tf1;
 
     // Emit code: fill programs by level, then one program per distinct root.
     std::vector<uint2> code;
@@ -873,6 +878,7 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
         ProgDesc pd{root_code[n], root_len[n], store_of[n], 0};
         store.push_back(pd);
     }
+    ctx->times.plan_emit_ms = now_ms() - td1;
     // reduce programs keep dest = their row; order them longest first
     longest_first(reduce);
     longest_first(store);
