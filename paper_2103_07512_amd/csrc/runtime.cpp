@@ -79,20 +79,22 @@ tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
 }
 
 // --------------------------------------------------------------- cost model
-// VALU issue slots per case of each operator in the fused interpreter on
-// gfx950 (counted from the compiled instruction sequences; terminals cost
-// the register move that places them on the stack).
+// VALU instructions per case of each operator as this library compiles it
+// for gfx950, measured by opcost_probe.hip (SQ_INSTS_VALU of a one-operator
+// kernel over random inputs in [-1, 1], less its loads, stores and
+// indexing); terminals cost the register move that places them on the
+// stack, warp is estimated (two axis points and a gathered read).
 const double kOpCost[TGP_NUM_OPS] = {
-    1,  1,           // var const
-    1,  1,  1, 11,   // add sub mult div
-    21, 21, 46,      // sin cos tan
-    13, 15, 60,      // exp log pow
-    3,  3,  3,  1,   // min max mdist neg
-    11, 4,  1,  6,   // sqrt sign abs clip
-    40, 2,  3,       // mod frac if
-    2,  9,  12, 16, 14, // step sstep sstepp len lerp
-    7,  7,  7,          // or xor and
-    24                  // warp (two axis points, a gathered read)
+    1,  1,              // var const
+    1,  1,  1, 13,      // add sub mult div
+    38, 35, 55,         // sin cos tan
+    14, 15, 169,        // exp log pow
+    3,  3,  3,  1,      // min max mdist neg
+    19, 4,  1,  5,      // sqrt sign abs clip
+    42, 2,  2,          // mod frac if
+    2,  6,  9, 27, 9,   // step sstep sstepp len lerp
+    16, 16, 16,         // or xor and
+    24                  // warp
 };
 // Writing a cache row once and reading it back, in VALU-slot equivalents per
 // case: 4 bytes of HBM traffic at 8 TB/s against 256 CUs x 64 lanes x 2.4 GHz
