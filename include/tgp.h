@@ -194,6 +194,15 @@ tgp_status tgp_ctx_set_stack(tgp_ctx ctx, int32_t lds);
  * constant.  Values are bitwise the same either way. */
 tgp_status tgp_ctx_set_folding(tgp_ctx ctx, int32_t on);
 
+/* Hash-consing identity of later tgp_build_dag calls: structural (0, the
+ * default: op, payload and children in order, Handley's DAG of Sec. 2), or
+ * also up to the operand order of the operators whose operands commute
+ * bitwise in this library (1: add, mult, mdist, len, or, xor, and; not min
+ * and max, whose result for +0 / -0 may follow the operand order).  A node
+ * keeps the child order of its first occurrence.  Values are the same
+ * either way; the DAG (and the credited node count) can only shrink. */
+tgp_status tgp_ctx_set_hashing(tgp_ctx ctx, int32_t commutative);
+
 /* Test hook: keep only the low `bits` bits of the DAG builder's 64-bit key
  * hash (0 = all bits), forcing collisions so that the full-key comparison is
  * exercised.  Process-wide; the DAG produced must not change. */

@@ -25,8 +25,19 @@ def tree_stack_depth(ops) -> int:
     return best
 
 
-def build_dag(tokens, offsets):
+# Operators whose two operands may be swapped without changing a bit of the
+# result in the library (IEEE addition and multiplication, the mean, the FP64
+# hypotenuse, the bitwise operators); min/max are not among them (which zero
+# of +0 / -0 comes out may follow the operand order).
+COMMUTATIVE = (2, 4, 14, 26, 28, 29, 30)
+
+
+def build_dag(tokens, offsets, commutative=False):
     """Canonicalise a population.
+
+    With commutative=True, a node of a COMMUTATIVE operator is identified by
+    the unordered pair of its children (its children stay in the order of
+    its first occurrence).
 
     Returns a dict with
       node_op, node_var (uint8), node_value (float32), children (int32 [U][3], -1 = none),
@@ -57,16 +68,18 @@ def build_dag(tokens, offsets):
                 del stack[len(stack) - a:]
                 h = 1 + max(hstack[len(hstack) - a:])
                 del hstack[len(hstack) - a:]
-                key = (op, 0, kids)
+                key = (op, 0, tuple(sorted(kids)) if commutative and op in COMMUTATIVE else kids)
+                first_kids = kids
             else:
                 payload = int(var[t]) if op == 0 else int(bits[t])
                 key = (op, payload, ())
+                first_kids = ()
                 h = 0
             nid = table.get(key)
             if nid is None:
                 nid = len(node_key)
                 table[key] = nid
-                node_key.append(key)
+                node_key.append((key[0], key[1], first_kids))
                 mult.append(0)
             mult[nid] += 1
             stack.append(nid)

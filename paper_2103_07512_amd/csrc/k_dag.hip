@@ -167,8 +167,15 @@ struct Key {
     uint32_t k0, k1, k2, k3;
 };
 
+// Operators whose operands commute bitwise in this library (see
+// tgp_ctx_set_hashing).
+__device__ __forceinline__ bool commutes(uint32_t op) {
+    return op == TGP_ADD || op == TGP_MULT || op == TGP_MDIST || op == TGP_LEN || op == TGP_OR ||
+           op == TGP_XOR || op == TGP_AND;
+}
+
 __device__ __forceinline__ Key key_of(int32_t t, const uint2 *tok, const int32_t *kid,
-                                      const int32_t *canon) {
+                                      const int32_t *canon, bool commute) {
     const uint2 w = tok[t];
     const uint32_t op = w.x & 0xffu;
     Key k{op, 0xffffffffu, 0xffffffffu, 0xffffffffu};
@@ -181,6 +188,11 @@ __device__ __forceinline__ Key key_of(int32_t t, const uint2 *tok, const int32_t
         k.k1 = (uint32_t)canon[kid[3 * t + 0]];
         if (a > 1) k.k2 = (uint32_t)canon[kid[3 * t + 1]];
         if (a > 2) k.k3 = (uint32_t)canon[kid[3 * t + 2]];
+        if (commute && commutes(op) && k.k1 > k.k2) {
+            const uint32_t x = k.k1;
+            k.k1 = k.k2;
+            k.k2 = x;
+        }
     }
     return k;
 }
@@ -206,11 +218,11 @@ __device__ __forceinline__ uint64_t key_hash(const Key &k, uint32_t hash_mask_bi
 // smallest token index with that key.
 __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
                               const int32_t *canon, int32_t *table, uint64_t mask,
-                              uint32_t hash_bits) {
+                              uint32_t hash_bits, bool commute) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t t = list[i];
-    const Key k = key_of(t, tok, kid, canon);
+    const Key k = key_of(t, tok, kid, canon, commute);
     uint64_t s = key_hash(k, hash_bits) & mask;
     for (;;) {
         int32_t e = table[s];
@@ -218,7 +230,7 @@ __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, 
             e = atomicCAS(&table[s], -1, t);
             if (e < 0) return;  // claimed an empty slot
         }
-        if (key_eq(key_of(e, tok, kid, canon), k)) {
+        if (key_eq(key_of(e, tok, kid, canon, commute), k)) {
             atomicMin(&table[s], t);
             return;
         }
@@ -230,11 +242,11 @@ __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, 
 // representative.
 __global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
                                int32_t *canon, const int32_t *table, uint64_t mask,
-                               uint32_t hash_bits) {
+                               uint32_t hash_bits, bool commute) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t t = list[i];
-    const Key k = key_of(t, tok, kid, canon);
+    const Key k = key_of(t, tok, kid, canon, commute);
     uint64_t s = key_hash(k, hash_bits) & mask;
     for (;;) {
         const int32_t e = table[s];
@@ -242,7 +254,7 @@ __global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok,
             canon[t] = t;
             return;
         }
-        if (key_eq(key_of(e, tok, kid, canon), k)) {
+        if (key_eq(key_of(e, tok, kid, canon, commute), k)) {
             canon[t] = e;
             return;
         }
@@ -369,7 +381,7 @@ uint32_t g_debug_hash_bits = 0;  // set by tests to force hash collisions
 
 DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
                                 int64_t T, DagDevice *dev, DevicePool &pool, hipStream_t s,
-                                char *err, size_t errlen) {
+                                char *err, size_t errlen, bool commute) {
     DagBuildResult res{};
     res.status = TGP_OK;
     res.bad_tree = -1;
@@ -450,9 +462,9 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
             if (!n) continue;
             const int32_t *lst = list + start[h];
             hipLaunchKernelGGL(k_hash_insert, grid_for(n), dim3(256), 0, s, lst, n, tok, kid, canon,
-                               table, (uint64_t)(cap - 1), g_debug_hash_bits);
+                               table, (uint64_t)(cap - 1), g_debug_hash_bits, commute);
             hipLaunchKernelGGL(k_hash_resolve, grid_for(n), dim3(256), 0, s, lst, n, tok, kid,
-                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits);
+                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits, commute);
         }
         DCHK(hipGetLastError());
         DCHK(pool.alloc((void **)&flag, sizeof(int32_t) * T));

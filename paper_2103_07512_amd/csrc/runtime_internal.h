@@ -33,6 +33,7 @@ struct tgp_ctx_s {
     bool plan_upload = true;             // plans also kept on the device
     int stack_lds = 0;                   // operand stack in LDS (1) or registers (0)
     int fold = 1;                        // constant folding
+    int commute = 0;                     // hash-consing up to operand order of commuting operators
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
     DevicePool pool;             // DAG, plan and population blocks

@@ -135,6 +135,7 @@ SIGNATURES = [
     ("tgp_ctx_set_plan", I32, [P, I32, ctypes.c_double]),
     ("tgp_ctx_set_stack", I32, [P, I32]),
     ("tgp_ctx_set_folding", I32, [P, I32]),
+    ("tgp_ctx_set_hashing", I32, [P, I32]),
     ("tgp_debug_set_hash_bits", I32, [I32]),
     ("tgp_domain_create", I32, [P, I32, P, P, P, PP]),
     ("tgp_domain_destroy", None, [P]),
@@ -228,6 +229,10 @@ class Context:
 
     def set_plan(self, reorder_children: bool = True, cache_access_cost: float = 20.0):
         _check(lib().tgp_ctx_set_plan(self.h, 1 if reorder_children else 0, cache_access_cost), self.h)
+
+    def set_hashing(self, commutative: bool = False):
+        """Hash-cons up to the operand order of commuting operators."""
+        _check(lib().tgp_ctx_set_hashing(self.h, 1 if commutative else 0), self.h)
 
     def set_folding(self, on: bool = True):
         """Evaluate constant subtrees once and use their values as constants."""

@@ -185,14 +185,14 @@ def test_parity_warp(env):
         _full_parity(env, pop, shape, tgt, what=f"warp {shape} ({n_warp} warp nodes)")
 
 
-def test_dag_bit_exact(env):
+def _dag_bit_exact(env, commutative):
     tgp, ctx, torch = env
     for name, pop in (("C1", pg.workload_c1()[0]), ("C2", pg.workload_c2(side=8)[0]),
                       ("F18 d2-12", pg.ramped_half_and_half(300, 2, 12, 71, pg.F18, 2))):
-        say("DAG", name, len(pop.tokens))
+        say("DAG", name, len(pop.tokens), "commutative" if commutative else "structural")
         dag = tgp.build_dag(ctx, pop)
         g = dag.export()
-        o = oracle.build_dag(pop.tokens, pop.offsets)
+        o = oracle.build_dag(pop.tokens, pop.offsets, commutative=commutative)
         assert g["dag_nodes"] == o["dag_nodes"]
         assert np.array_equal(g["nodes"]["op"], o["node_op"])
         assert np.array_equal(g["nodes"]["var"][o["node_op"] == 0], o["node_var"][o["node_op"] == 0])
@@ -204,6 +204,33 @@ def test_dag_bit_exact(env):
         for k in ("tree_nodes", "tree_internal", "dag_internal", "shared_internal", "max_stack",
                   "max_height"):
             assert g[k] == o[k], k
+
+
+def test_dag_bit_exact(env):
+    _dag_bit_exact(env, False)
+
+
+def test_dag_commutative_hashing(env):
+    """Hash-consing up to operand order: bit-exact against the oracle's DAG of
+    the same identity, fewer nodes, and the same per-case values and fitness."""
+    tgp, ctx, torch = env
+    pop = pg.workload_c2(side=8)[0]
+    shape = (40, 36)
+    target = finite_target(pg.TargetSpec(3, 99, pg.F6, 2, 1), shape)
+    got_s, dag_s, dom = gpu_eval(env, pop, shape)
+    f_s = gpu_fit(env, pop, dom, dag_s, target)
+    try:
+        ctx.set_hashing(True)
+        _dag_bit_exact(env, True)
+        got_c, dag_c, dom = gpu_eval(env, pop, shape)
+        f_c = gpu_fit(env, pop, dom, dag_c, target)
+    finally:
+        ctx.set_hashing(False)
+    assert dag_c.stats()["dag_nodes"] < dag_s.stats()["dag_nodes"]
+    assert np.array_equal(np.isnan(got_s), np.isnan(got_c))
+    m = ~np.isnan(got_s)
+    assert np.array_equal(got_s[m].view(np.uint32), got_c[m].view(np.uint32))
+    assert np.array_equal(f_s.view(np.uint64), f_c.view(np.uint64))
 
 
 def test_dag_forced_hash_collisions(env):

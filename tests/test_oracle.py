@@ -491,6 +491,29 @@ def test_dag_invariants():
         assert d3[k] == d[k]
 
 
+def test_dag_commutative_identity():
+    """Hash-consing up to the operand order of commuting operators: add and
+    mult pairs merge, sub and min pairs do not; a merged node keeps the child
+    order of its first occurrence."""
+    texts = ["add(x, y)", "add(y, x)", "sub(x, y)", "sub(y, x)", "min(x, y)", "min(y, x)",
+             "mult(add(x, y), 2.0)", "mult(2.0, add(y, x))"]
+    pop = pg.population_from_texts(texts)
+    s = oracle.build_dag(pop.tokens, pop.offsets)
+    c = oracle.build_dag(pop.tokens, pop.offsets, commutative=True)
+    assert s["dag_nodes"] == 3 + 8 and c["dag_nodes"] == 3 + 1 + 2 + 2 + 1
+    r = c["roots"].tolist()
+    assert r[0] == r[1] and r[2] != r[3] and r[4] != r[5] and r[6] == r[7]
+    assert c["children"][r[0]][:2].tolist() == [0, 1]          # add(x, y) as first met
+    assert c["children"][r[6]][:2].tolist() == [r[0], c["children"][r[6]][1]]
+    assert c["node_value"][c["children"][r[6]][1]] == 2.0
+    # same trees in every order: the commutative DAG is never larger
+    pop2, _, _ = pg.workload_c2(side=8)
+    a = oracle.build_dag(pop2.tokens, pop2.offsets)
+    b = oracle.build_dag(pop2.tokens, pop2.offsets, commutative=True)
+    assert b["dag_nodes"] <= a["dag_nodes"] and b["tree_nodes"] == a["tree_nodes"]
+    assert b["multiplicity"].sum() == len(pop2.tokens)
+
+
 def test_c2_sharing_in_range():
     pop, _, _ = pg.workload_c2(side=8)
     d = oracle.build_dag(pop.tokens, pop.offsets)
