@@ -280,6 +280,8 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
     HCHK(ctx, hipSetDevice(ctx->device));
     const double t0 = now_ms();
     std::vector<StepJob> sj(n_jobs);
+    std::vector<tgp_dag> dags(n_jobs);
+    std::vector<int64_t> cases(n_jobs);
     int64_t credited = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const tgp_job &J = jobs[j];
@@ -288,8 +290,14 @@ tgp_status tgp_batch_run(tgp_batch b, int32_t n_jobs, const tgp_job *jobs) {
         if (J.loss != TGP_RMSE && J.loss != TGP_MSE) return fail(ctx, TGP_EINVAL, "job %d: bad loss", j);
         if (J.dag->n_ind > 0 && (!J.target_dev || !J.out_dev))
             return fail(ctx, TGP_EINVAL, "job %d: NULL target or output", j);
-        st = build_plan(ctx, J.dag, J.domain->cases);
-        if (st != TGP_OK) return fail(ctx, st, "job %d: %s", j, ctx->err.c_str());
+        dags[j] = J.dag;
+        cases[j] = J.domain->cases;
+    }
+    // every job's plan at once: host threads, one device round trip
+    tgp_status pst = build_plans(ctx, n_jobs, dags.data(), cases.data());
+    if (pst != TGP_OK) return pst;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const tgp_job &J = jobs[j];
         StepJob &s = sj[j];
         s.plan = &J.dag->plan;
         s.domain = J.domain;

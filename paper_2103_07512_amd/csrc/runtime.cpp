@@ -20,8 +20,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -653,11 +655,11 @@ struct Emitted {
 };
 
 void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<uint2> &code,
-              std::vector<Emitted> &out) {
+              std::vector<Emitted> &out, int threads) {
     const size_t n = nodes.size();
     out.assign(n, Emitted{0, 0, 0, 0.0});
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int T = n < 512 ? 1 : (int)std::min<unsigned>(8, hw);
+    const int T = n < 512 ? 1 : (int)std::min<unsigned>((unsigned)std::max(threads, 1), hw);
     std::vector<std::vector<uint2>> local(T);
     auto work = [&](int t) {
         const size_t b = n * t / T, e = n * (t + 1) / T;
@@ -681,16 +683,66 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
 
 }  // namespace
 
-static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases);
+// ------------------------------------------------------------------ planning
+//
+// Planning one DAG runs in phases so that a batch of many DAGs can run each
+// phase for all of them at once: host preparation (program lists, the
+// variable-free subtrees), constant folding on the device (one round trip
+// for the whole batch), the caching and stack decisions with program
+// emission (host, one DAG per thread), and the upload of the programs (only
+// for the single-DAG calls; a batch packs the host copies itself).
+struct PlanJob {
+    tgp_dag d;
+    int64_t cases;
+    Planner pl;
+    std::vector<int32_t> rootrefs, ind_rows, store_of, store_list;
+    std::vector<std::pair<int32_t, int32_t>> reduce_list;  // (root node, channel)
+    // variable-free nodes by height (folding), this job's place in the batch
+    std::vector<int32_t> fold_first, fold_list;
+    size_t fold_list_at = 0, fold_val_at = 0;
+    double t_decide = 0, t_emit = 0;
+    tgp_status st = TGP_OK;
+    std::string err;
+    PlanJob(tgp_dag dag, int64_t n_cases, int D, size_t budget)
+        : d(dag), cases(n_cases), pl(*dag, D, budget) {}
+};
 
-// Constant subtrees (no variable below) that some non-constant node or a
-// root uses are evaluated once on the device, height by height; folded[n]
-// marks them and fold_val[n] holds their FP32 value.
-static tgp_status fold_constants(tgp_ctx ctx, tgp_dag d, std::vector<uint8_t> &folded,
-                                 std::vector<float> &fold_val) {
-    const int64_t U = d->stats.dag_nodes;
+static void plan_prepare(PlanJob &w, bool fold) {
+    tgp_dag d = w.d;
+    Plan &P = d->plan;
+    const int64_t U = d->stats.dag_nodes, R = d->stats.n_roots;
+    const int n_ch = d->n_ch;
+    // distinct programs
+    std::unordered_map<int64_t, int32_t> reduce_of;  // (root id, ch) -> program
+    w.rootrefs.assign(U, 0);
+    w.ind_rows.resize(R);
+    w.store_of.assign(U, -1);
+    P.store_rows.assign(R, -1);
+    P.dup_src.assign(R, -1);
+    for (int64_t r = 0; r < R; ++r) {
+        const int32_t n = d->roots[r];
+        const int ch = (int)(r % n_ch);
+        const int64_t key = (int64_t)n * n_ch + ch;
+        auto it = reduce_of.find(key);
+        if (it == reduce_of.end()) {
+            it = reduce_of.emplace(key, (int32_t)w.reduce_list.size()).first;
+            w.reduce_list.push_back({n, ch});
+            w.rootrefs[n] += 1;
+        }
+        w.ind_rows[r] = it->second;
+        if (w.store_of[n] < 0) {
+            w.store_of[n] = (int32_t)r;
+            w.store_list.push_back(n);
+            P.store_rows[r] = (int32_t)r;
+        } else {
+            P.dup_src[r] = w.store_of[n];
+        }
+    }
+    if (!fold) return;
+    // Constant subtrees (no variable below) that some non-constant node or a
+    // root uses are folded: marked in pl.folded, evaluated on the device.
     std::vector<uint8_t> novar(U, 0), use(U, 0);
-    int32_t max_h = 0;
+    int32_t max_h = -1;
     for (int64_t n = 0; n < U; ++n) {  // children have smaller ids
         const int o = d->op[n] & 0xff;
         bool nv = o != TGP_VAR;
@@ -709,118 +761,102 @@ static tgp_status fold_constants(tgp_ctx ctx, tgp_dag d, std::vector<uint8_t> &f
         if (!novar[n])
             for (int j = 0; j < kArity[d->op[n] & 0xff]; ++j) mark(d->kid[3 * n + j]);
     for (int32_t r : d->roots) mark(r);
-    if (n_use == 0) return TGP_OK;
+    if (n_use == 0) return;
     // every variable-free node, by height (children before parents)
-    std::vector<int32_t> first(max_h + 2, 0), list;
+    w.fold_first.assign(max_h + 2, 0);
     for (int64_t n = 0; n < U; ++n)
-        if (novar[n]) ++first[d->height[n] + 1];
-    for (int h = 0; h <= max_h; ++h) first[h + 1] += first[h];
-    list.resize(first[max_h + 1]);
-    {
-        std::vector<int32_t> at(first.begin(), first.end() - 1);
-        for (int64_t n = 0; n < U; ++n)
-            if (novar[n]) list[at[d->height[n]]++] = (int32_t)n;
-    }
-    int32_t *list_dev = nullptr;
-    float *val_dev = nullptr;
-    void *stage = nullptr;
-    hipError_t e = ctx->pool.alloc((void **)&list_dev, sizeof(int32_t) * list.size());
-    if (e == hipSuccess) e = ctx->pool.alloc((void **)&val_dev, sizeof(float) * U);
-    if (e == hipSuccess) e = ctx_pinned(ctx, sizeof(int32_t) * list.size(), &stage);
+        if (novar[n]) ++w.fold_first[d->height[n] + 1];
+    for (int h = 0; h <= max_h; ++h) w.fold_first[h + 1] += w.fold_first[h];
+    w.fold_list.resize(w.fold_first[max_h + 1]);
+    std::vector<int32_t> at(w.fold_first.begin(), w.fold_first.end() - 1);
+    for (int64_t n = 0; n < U; ++n)
+        if (novar[n]) w.fold_list[at[d->height[n]]++] = (int32_t)n;
+    w.pl.folded.swap(use);
+}
+
+// Folds the marked subtrees of every job: one upload of the node lists, one
+// launch per height over all jobs, one read-back of the values.
+static tgp_status fold_run(tgp_ctx ctx, const std::vector<PlanJob *> &jobs) {
+    std::vector<PlanJob *> fj;
+    size_t n_list = 0, n_val = 0;
+    int32_t max_h = -1;
+    for (PlanJob *w : jobs)
+        if (!w->fold_list.empty()) {
+            w->fold_list_at = n_list;
+            w->fold_val_at = n_val;
+            n_list += w->fold_list.size();
+            n_val += (size_t)w->d->stats.dag_nodes;
+            max_h = std::max(max_h, (int32_t)w->fold_first.size() - 2);
+            fj.push_back(w);
+        }
+    if (fj.empty()) return TGP_OK;
+    // the (job, node) lists of all jobs ordered by height, then job
+    std::vector<int32_t> hfirst(max_h + 2, 0);
+    for (PlanJob *w : fj)
+        for (size_t h = 0; h + 1 < w->fold_first.size(); ++h)
+            hfirst[h + 1] += w->fold_first[h + 1] - w->fold_first[h];
+    for (int h = 0; h <= max_h; ++h) hfirst[h + 1] += hfirst[h];
+    const size_t desc_bytes = sizeof(FoldDesc) * fj.size();
+    const size_t list_off = (desc_bytes + 255) & ~(size_t)255;
+    const size_t val_off = (list_off + sizeof(int2) * n_list + 255) & ~(size_t)255;
+    const size_t up_bytes = list_off + sizeof(int2) * n_list;
+    void *blk = nullptr, *stage = nullptr;
+    hipError_t e = ctx->pool.alloc(&blk, val_off + sizeof(float) * n_val);
+    if (e == hipSuccess) e = ctx_pinned(ctx, std::max(up_bytes, sizeof(float) * n_val), &stage);
     if (e == hipSuccess) {
-        memcpy(stage, list.data(), sizeof(int32_t) * list.size());
-        e = hipMemcpyAsync(list_dev, stage, sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, ctx->stream);
+        FoldDesc *desc = static_cast<FoldDesc *>(stage);
+        int2 *list = reinterpret_cast<int2 *>(static_cast<char *>(stage) + list_off);
+        float *val_dev = reinterpret_cast<float *>(static_cast<char *>(blk) + val_off);
+        std::vector<int32_t> at(hfirst.begin(), hfirst.end() - 1);
+        for (size_t j = 0; j < fj.size(); ++j) {
+            const PlanJob &w = *fj[j];
+            desc[j] = FoldDesc{w.d->dev.node_op, w.d->dev.node_value, w.d->dev.node_kid, val_dev + w.fold_val_at};
+            for (size_t h = 0; h + 1 < w.fold_first.size(); ++h)
+                for (int32_t q = w.fold_first[h]; q < w.fold_first[h + 1]; ++q)
+                    list[at[h]++] = int2{(int32_t)j, w.fold_list[q]};
+        }
+        e = hipMemcpyAsync(blk, stage, up_bytes, hipMemcpyHostToDevice, ctx->stream);
     }
     if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
+    const FoldDesc *desc_dev = static_cast<const FoldDesc *>(blk);
+    const int2 *list_dev = reinterpret_cast<const int2 *>(static_cast<char *>(blk) + list_off);
     for (int h = 0; h <= max_h && e == hipSuccess; ++h)
-        e = launch_fold_level(d->dev.node_op, d->dev.node_value, d->dev.node_kid, list_dev + first[h],
-                              first[h + 1] - first[h], val_dev, ctx->stream);
-    fold_val.assign(U, 0.0f);
-    if (e == hipSuccess) e = ctx_pinned(ctx, sizeof(float) * U, &stage);
-    if (e == hipSuccess) e = hipMemcpyAsync(stage, val_dev, sizeof(float) * U, hipMemcpyDeviceToHost, ctx->stream);
+        e = launch_fold_level(desc_dev, list_dev + hfirst[h], hfirst[h + 1] - hfirst[h], ctx->stream);
+    if (e == hipSuccess) e = ctx_pinned(ctx, sizeof(float) * n_val, &stage);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stage, static_cast<char *>(blk) + val_off, sizeof(float) * n_val,
+                           hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e == hipSuccess) memcpy(fold_val.data(), stage, sizeof(float) * U);
+    if (e == hipSuccess)
+        for (PlanJob *w : fj) {
+            const float *v = static_cast<const float *>(stage) + w->fold_val_at;
+            w->pl.fold_val.assign(v, v + w->d->stats.dag_nodes);
+        }
     hipStreamSynchronize(ctx->stream);
-    ctx->pool.release(list_dev);
-    ctx->pool.release(val_dev);
+    ctx->pool.release(blk);
     if (e != hipSuccess) return fail(ctx, TGP_EHIP, "constant folding: %s", hipGetErrorString(e));
-    folded.swap(use);
     return TGP_OK;
 }
 
-int ctx_stack_slots(tgp_ctx ctx) { return ctx->stack_lds ? interp_lds_stack() : interp_max_stack(); }
-
-tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
-    const double t0 = now_ms();
-    const Plan &P = d->plan;
-    const bool same = P.cases == cases && P.D == ctx_stack_slots(ctx) && P.reorder == (ctx->reorder != 0) &&
-                      P.access_cost == ctx->cache_access_cost && P.fold == ctx->fold;
-    tgp_status st = same ? TGP_OK : build_plan_impl(ctx, d, cases);
-    ctx->times.plan_ms = now_ms() - t0;
-    return st;
-}
-
-static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
+// Caching and stack decisions, then the programs: fill programs by level,
+// one program per distinct (root, channel) and one per distinct root.
+// Host only; emit_threads host threads emit the programs.
+static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double access_cost, int fold,
+                                   int emit_threads) {
+    tgp_dag d = w.d;
     Plan &P = d->plan;
-    if (P.blob) {
-        HCHK(ctx, hipStreamSynchronize(ctx->stream));
-        P.release(ctx->pool);
-    }
-    const int64_t U = d->stats.dag_nodes, R = d->stats.n_roots;
-    const int n_ch = d->n_ch;
-    // distinct programs
-    std::vector<int32_t> rootrefs(U, 0);
-    std::unordered_map<int64_t, int32_t> reduce_of;  // (root id, ch) -> program
-    std::vector<std::pair<int32_t, int32_t>> reduce_list;
-    std::vector<int32_t> ind_rows(R);
-    std::vector<int32_t> store_of(U, -1);
-    std::vector<int32_t> store_list;  // root node ids
-    P.store_rows.assign(R, -1);
-    P.dup_src.assign(R, -1);
-    for (int64_t r = 0; r < R; ++r) {
-        const int32_t n = d->roots[r];
-        const int ch = (int)(r % n_ch);
-        const int64_t key = (int64_t)n * n_ch + ch;
-        auto it = reduce_of.find(key);
-        if (it == reduce_of.end()) {
-            it = reduce_of.emplace(key, (int32_t)reduce_list.size()).first;
-            reduce_list.push_back({n, ch});
-            rootrefs[n] += 1;
-        }
-        ind_rows[r] = it->second;
-        if (store_of[n] < 0) {
-            store_of[n] = (int32_t)r;
-            store_list.push_back(n);
-            P.store_rows[r] = (int32_t)r;
-        } else {
-            P.dup_src[r] = store_of[n];
-        }
-    }
-    const int D = ctx_stack_slots(ctx);
-    P.D = D;
-    P.reorder = ctx->reorder != 0;
-    P.access_cost = ctx->cache_access_cost;
-    P.fold = ctx->fold;
-    size_t budget_slots = (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
-    Planner pl(*d, D, budget_slots);
-    const double tf0 = now_ms();
-    if (ctx->fold) {
-        tgp_status fs = fold_constants(ctx, d, pl.folded, pl.fold_val);
-        if (fs != TGP_OK) return fs;
-    }
-    const double tf1 = now_ms();
-    ctx->times.plan_fold_ms = tf1 - tf0;
+    Planner &pl = w.pl;
+    const int64_t U = d->stats.dag_nodes;
+    const double t0 = now_ms();
     P.n_folded = 0;
     for (uint8_t f : pl.folded) P.n_folded += f;
-    pl.reorder = ctx->reorder != 0;
-    pl.access_cost = ctx->cache_access_cost;
-    std::string why;
-    tgp_status st = pl.decide(rootrefs, why);
-    if (st != TGP_OK) return fail(ctx, st, "%s", why.c_str());
-    const double td1 = now_ms();
-    ctx->times.plan_decide_ms = td1 - tf1;
+    pl.reorder = reorder;
+    pl.access_cost = access_cost;
+    tgp_status st = pl.decide(w.rootrefs, w.err);
+    if (st != TGP_OK) return st;
+    const double t1 = now_ms();
+    w.t_decide = t1 - t0;
 
-    // Emit code: fill programs by level, then one program per distinct root.
     std::vector<uint2> code;
     std::vector<ProgDesc> fill, reduce, store;
     int32_t max_level = -1;
@@ -844,7 +880,7 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     for (int32_t n : cached_nodes)
         if (!pl.pre[n]) fill_nodes.push_back(n);
     std::vector<Emitted> em;
-    emit_all(pl, fill_nodes, code, em);
+    emit_all(pl, fill_nodes, code, em, emit_threads);
     for (size_t i = 0; i < fill_nodes.size(); ++i) {
         const int32_t n = fill_nodes[i];
         ProgDesc pd{em[i].off, em[i].len, pl.slot[n], 0};
@@ -866,28 +902,27 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     double exec_roots = 0;
     std::vector<int64_t> reads_of(U, 0);
     std::vector<double> valu_of(U, 0.0);
-    emit_all(pl, store_list, code, em);
-    for (size_t i = 0; i < store_list.size(); ++i) {
-        const int32_t n = store_list[i];
+    emit_all(pl, w.store_list, code, em, emit_threads);
+    for (size_t i = 0; i < w.store_list.size(); ++i) {
+        const int32_t n = w.store_list[i];
         root_code[n] = em[i].off;
         root_len[n] = em[i].len;
         reads_of[n] = em[i].reads;
         valu_of[n] = em[i].valu;
     }
     double valu_roots = 0;
-    for (size_t p = 0; p < reduce_list.size(); ++p) {
-        const int32_t n = reduce_list[p].first;
-        ProgDesc pd{root_code[n], root_len[n], (int32_t)p, reduce_list[p].second};
+    for (size_t p = 0; p < w.reduce_list.size(); ++p) {
+        const int32_t n = w.reduce_list[p].first;
+        ProgDesc pd{root_code[n], root_len[n], (int32_t)p, w.reduce_list[p].second};
         reduce.push_back(pd);
         exec_roots += root_len[n] - 1;
         cache_reads_roots += reads_of[n];
         valu_roots += valu_of[n];
     }
-    for (int32_t n : store_list) {
-        ProgDesc pd{root_code[n], root_len[n], store_of[n], 0};
+    for (int32_t n : w.store_list) {
+        ProgDesc pd{root_code[n], root_len[n], w.store_of[n], 0};
         store.push_back(pd);
     }
-    ctx->times.plan_emit_ms = now_ms() - td1;
     // reduce programs keep dest = their row; order them longest first
     longest_first(reduce);
     longest_first(store);
@@ -897,6 +932,10 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     for (auto &pd : fill) exec_fill += pd.len - 1;
     double valu = 0;
     for (int64_t n = 0; n < U; ++n) valu += kOpCost[d->op[n] & 0xff];
+    P.D = D;
+    P.reorder = reorder;
+    P.access_cost = access_cost;
+    P.fold = fold;
     P.exec_per_case = exec_fill + exec_roots;
     P.valu_dag_per_case = valu;
     P.valu_fill_per_case = valu_fill;
@@ -914,45 +953,167 @@ static tgp_status build_plan_impl(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     P.n_fill = (int32_t)fill.size();
     P.n_reduce = (int32_t)reduce.size();
     P.n_store = (int32_t)store.size();
-
-    if (ctx->plan_upload) {
-        // One device block (256-byte aligned parts) filled by one copy from the
-        // pinned staging; later launches on the stream see it in order.
-        const size_t part[5] = {sizeof(uint2) * code.size(), sizeof(ProgDesc) * fill.size(),
-                                sizeof(ProgDesc) * reduce.size(), sizeof(ProgDesc) * store.size(),
-                                sizeof(int32_t) * ind_rows.size()};
-        const void *src[5] = {code.data(), fill.data(), reduce.data(), store.data(), ind_rows.data()};
-        size_t off[5], total = 0;
-        for (int i = 0; i < 5; ++i) {
-            off[i] = total;
-            total += (part[i] + 255) & ~(size_t)255;
-        }
-        void *stage = nullptr;
-        hipError_t e = ctx->pool.alloc(&P.blob, total);
-        if (e == hipSuccess) e = ctx_pinned(ctx, total, &stage);
-        if (e == hipSuccess) {
-            for (int i = 0; i < 5; ++i)
-                if (part[i]) memcpy((char *)stage + off[i], src[i], part[i]);
-            e = hipMemcpyAsync(P.blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
-        }
-        if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
-        if (e != hipSuccess) {
-            hipStreamSynchronize(ctx->stream);
-            P.release(ctx->pool);
-            return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
-        }
-        char *b = static_cast<char *>(P.blob);
-        P.code_dev = reinterpret_cast<uint2 *>(b + off[0]);
-        P.fill_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
-        P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
-        P.store_dev = reinterpret_cast<ProgDesc *>(b + off[3]);
-        P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[4]);
-    }
     P.code_host = std::move(code);
     P.fill_host = std::move(fill);
     P.reduce_host = std::move(reduce);
-    P.ind_rows_host = std::move(ind_rows);
-    P.cases = cases;
+    P.store_host = std::move(store);
+    P.ind_rows_host = std::move(w.ind_rows);
+    P.cases = w.cases;
+    w.t_emit = now_ms() - t1;
+    return TGP_OK;
+}
+
+// One device block (256-byte aligned parts) filled by one copy from the
+// pinned staging; later launches on the stream see it in order.
+static tgp_status plan_upload(tgp_ctx ctx, Plan &P) {
+    const size_t part[5] = {sizeof(uint2) * P.code_host.size(), sizeof(ProgDesc) * P.fill_host.size(),
+                            sizeof(ProgDesc) * P.reduce_host.size(), sizeof(ProgDesc) * P.store_host.size(),
+                            sizeof(int32_t) * P.ind_rows_host.size()};
+    const void *src[5] = {P.code_host.data(), P.fill_host.data(), P.reduce_host.data(), P.store_host.data(),
+                          P.ind_rows_host.data()};
+    size_t off[5], total = 0;
+    for (int i = 0; i < 5; ++i) {
+        off[i] = total;
+        total += (part[i] + 255) & ~(size_t)255;
+    }
+    void *stage = nullptr;
+    hipError_t e = ctx->pool.alloc(&P.blob, total);
+    if (e == hipSuccess) e = ctx_pinned(ctx, total, &stage);
+    if (e == hipSuccess) {
+        for (int i = 0; i < 5; ++i)
+            if (part[i]) memcpy((char *)stage + off[i], src[i], part[i]);
+        e = hipMemcpyAsync(P.blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
+    }
+    if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
+    if (e != hipSuccess) {
+        hipStreamSynchronize(ctx->stream);
+        P.release(ctx->pool);
+        return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
+    }
+    char *b = static_cast<char *>(P.blob);
+    P.code_dev = reinterpret_cast<uint2 *>(b + off[0]);
+    P.fill_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
+    P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
+    P.store_dev = reinterpret_cast<ProgDesc *>(b + off[3]);
+    P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[4]);
+    return TGP_OK;
+}
+
+int ctx_stack_slots(tgp_ctx ctx) { return ctx->stack_lds ? interp_lds_stack() : interp_max_stack(); }
+
+static bool plan_current(tgp_ctx ctx, const Plan &P, int64_t cases) {
+    return P.cases == cases && P.D == ctx_stack_slots(ctx) && P.reorder == (ctx->reorder != 0) &&
+           P.access_cost == ctx->cache_access_cost && P.fold == ctx->fold;
+}
+
+static size_t budget_slots(tgp_ctx ctx, int64_t cases) {
+    return (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
+}
+
+tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
+    const double t0 = now_ms();
+    Plan &P = d->plan;
+    if (plan_current(ctx, P, cases)) {
+        tgp_status st = ctx->plan_upload && !P.blob ? plan_upload(ctx, P) : TGP_OK;
+        ctx->times.plan_ms = now_ms() - t0;
+        return st;
+    }
+    if (P.blob) {
+        HCHK(ctx, hipStreamSynchronize(ctx->stream));
+        P.release(ctx->pool);
+    }
+    P.cases = -1;
+    const int D = ctx_stack_slots(ctx);
+    PlanJob w(d, cases, D, budget_slots(ctx, cases));
+    plan_prepare(w, ctx->fold != 0);
+    const double tf0 = now_ms();
+    tgp_status st = fold_run(ctx, {&w});
+    if (st != TGP_OK) return st;
+    ctx->times.plan_fold_ms = now_ms() - tf0;
+    st = plan_decide_emit(w, D, ctx->reorder != 0, ctx->cache_access_cost, ctx->fold, 8);
+    if (st != TGP_OK) return fail(ctx, st, "%s", w.err.c_str());
+    ctx->times.plan_decide_ms = w.t_decide;
+    ctx->times.plan_emit_ms = w.t_emit;
+    if (ctx->plan_upload) {
+        st = plan_upload(ctx, P);
+        if (st != TGP_OK) return st;
+    }
+    ctx->times.plan_ms = now_ms() - t0;
+    return TGP_OK;
+}
+
+tgp_status build_plans(tgp_ctx ctx, int32_t n, const tgp_dag *dags, const int64_t *cases) {
+    const double t0 = now_ms();
+    // one plan per distinct DAG, for the largest domain it is evaluated on
+    // (the cache budget in rows is tightest there)
+    std::unordered_map<tgp_dag, int64_t> want;
+    std::vector<tgp_dag> order;
+    for (int32_t i = 0; i < n; ++i) {
+        auto it = want.find(dags[i]);
+        if (it == want.end()) {
+            want.emplace(dags[i], cases[i]);
+            order.push_back(dags[i]);
+        } else {
+            it->second = std::max(it->second, cases[i]);
+        }
+    }
+    const int D = ctx_stack_slots(ctx);
+    std::vector<std::unique_ptr<PlanJob>> jobs;
+    bool synced = false;
+    for (tgp_dag d : order) {
+        const int64_t c = want[d];
+        if (plan_current(ctx, d->plan, c)) continue;
+        if (d->plan.blob) {
+            if (!synced) HCHK(ctx, hipStreamSynchronize(ctx->stream));
+            synced = true;
+            d->plan.release(ctx->pool);
+        }
+        d->plan.cases = -1;
+        jobs.emplace_back(new PlanJob(d, c, D, budget_slots(ctx, c)));
+    }
+    if (jobs.empty()) {
+        ctx->times.plan_ms = now_ms() - t0;
+        return TGP_OK;
+    }
+    // largest first, taken by host threads in turn
+    std::stable_sort(jobs.begin(), jobs.end(), [](const std::unique_ptr<PlanJob> &a, const std::unique_ptr<PlanJob> &b) {
+        return a->d->stats.dag_nodes > b->d->stats.dag_nodes;
+    });
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = (int)std::min<size_t>(std::min<unsigned>(16, hw), jobs.size());
+    auto parallel = [&](auto &&fn) {
+        std::atomic<size_t> next{0};
+        auto run = [&]() {
+            for (size_t i; (i = next.fetch_add(1)) < jobs.size();) fn(*jobs[i]);
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < T; ++t) th.emplace_back(run);
+        run();
+        for (auto &x : th) x.join();
+    };
+    const bool fold = ctx->fold != 0;
+    parallel([&](PlanJob &w) { plan_prepare(w, fold); });
+    const double tf0 = now_ms();
+    std::vector<PlanJob *> ptrs;
+    for (auto &w : jobs) ptrs.push_back(w.get());
+    tgp_status st = fold_run(ctx, ptrs);
+    if (st != TGP_OK) return st;
+    const double tf1 = now_ms();
+    const bool reorder = ctx->reorder != 0;
+    const double access = ctx->cache_access_cost;
+    const int fold_flag = ctx->fold;
+    const int emit_threads = T > 1 ? 1 : 8;
+    parallel([&](PlanJob &w) {
+        w.st = plan_decide_emit(w, D, reorder, access, fold_flag, emit_threads);
+        if (w.st != TGP_OK) w.d->plan.cases = -1;
+    });
+    for (auto &w : jobs)
+        if (w->st != TGP_OK) return fail(ctx, w->st, "%s", w->err.c_str());
+    const double tf2 = now_ms();
+    ctx->times.plan_fold_ms = tf1 - tf0;
+    ctx->times.plan_decide_ms = tf2 - tf1;
+    ctx->times.plan_emit_ms = 0;
+    ctx->times.plan_ms = tf2 - t0;
     return TGP_OK;
 }
 

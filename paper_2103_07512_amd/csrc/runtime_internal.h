@@ -90,7 +90,7 @@ struct Plan {
     int32_t *ind_rows_dev = nullptr;
     // host copies (the batched path packs them into its own buffers)
     std::vector<uint2> code_host;
-    std::vector<ProgDesc> fill_host, reduce_host;
+    std::vector<ProgDesc> fill_host, reduce_host, store_host;
     std::vector<int32_t> ind_rows_host;
     std::vector<int32_t> slot_node;     // DAG node held by each cache slot
     std::vector<uint8_t> slot_pre;      // slot already resident (no fill program)
@@ -185,7 +185,13 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
 
 // --------------------------------------------------------------- shared helpers
 extern const double kOpCost[TGP_NUM_OPS];
+// Plans d for domains of `cases` cases (a no-op when its plan is current) and
+// uploads the programs when the context keeps plans on the device.
 tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases);
+// Plans many DAGs at once (host threads, one device round trip for constant
+// folding); programs stay on the host.  A DAG listed more than once is
+// planned once, for its largest domain.
+tgp_status build_plans(tgp_ctx ctx, int32_t n, const tgp_dag *dags, const int64_t *cases);
 int choose_K(tgp_ctx ctx, int64_t cases, bool ext);
 int ctx_stack_slots(tgp_ctx ctx);
 void choose_split(tgp_ctx ctx, int64_t n_progs, int64_t cases, int K, int32_t *stripes,

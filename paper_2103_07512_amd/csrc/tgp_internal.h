@@ -150,9 +150,15 @@ uint32_t batch_parts();
 const void *reset_kernel();           // (uint32_t *counters, int32_t n)
 const void *finalize_batch_kernel();  // (const FinJob *, const int32_t *n_jobs, const uint32_t *n_ind)
 hipError_t launch_reset(uint32_t *counters, int32_t n, hipStream_t s);
-// Constant folding: evaluates the n nodes of `list` (one height) into val.
-hipError_t launch_fold_level(const int32_t *node_op, const float *node_value, const int32_t *node_kid,
-                             const int32_t *list, int32_t n, float *val, hipStream_t s);
+// Constant folding over the DAGs of a batch: evaluates the n (DAG, node)
+// entries of `list` (one height) into each DAG's val (indexed by node id).
+struct FoldDesc {
+    const int32_t *node_op;
+    const float *node_value;
+    const int32_t *node_kid;
+    float *val;
+};
+hipError_t launch_fold_level(const FoldDesc *jobs, const int2 *list, int32_t n, hipStream_t s);
 hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
                                  int32_t grid, hipStream_t s);
 bool interp_variant_exists(int K, int D, bool bit = false);

@@ -91,6 +91,36 @@ def test_batch_equals_plain_bitwise(env):
         ctx.set_tuning(0, 0)
 
 
+def test_batch_plans_fresh_dags(env):
+    """A batch of fresh DAGs plans them all at once (host threads, one
+    constant-folding round trip for the whole batch); plain calls on the same
+    DAGs afterwards reuse or redo those plans and give bitwise the same
+    fitness.  One DAG is listed twice, on two domain sizes."""
+    tgp, ctx, torch = env
+    work = small_c4(13, 10)
+    jobs = make_jobs(env, work)
+    pop0, shape0, spec0 = work[0]
+    shape2 = (3, 4) if len(shape0) == 2 else (2, 3, 4)
+    dom2 = tgp.Domain(ctx, shape2)
+    _, target2 = pg.pick_target(pg.TargetSpec(3, 1313, pg.F18, len(shape2), 1),
+                                oracle.target_renderer(shape2))
+    out2 = torch.full((pop0.n_individuals,), -1.0, dtype=torch.float64, device="cuda:0")
+    jobs.append((jobs[0][0], dom2, torch.from_numpy(target2).to("cuda:0"), 0, out2))
+    folded = sum(1 for p, _, _ in work for t in p.tokens if t["op"] == 1)
+    say("batch of", len(jobs), "fresh jobs;", folded, "constant tokens")
+    ctx.set_tuning(4, 1)
+    try:
+        b = tgp.Batch(ctx, use_graph=True)
+        b.run(jobs)
+        torch.cuda.synchronize()
+        got = [o.cpu().numpy().copy() for *_, o in jobs]
+        want = plain(env, jobs)
+        for g, w in zip(got, want):
+            assert np.array_equal(g.view(np.uint64), w.view(np.uint64))
+    finally:
+        ctx.set_tuning(0, 0)
+
+
 def test_batch_graph_replay_with_new_jobs(env):
     tgp, ctx, torch = env
     b = tgp.Batch(ctx, use_graph=True)
