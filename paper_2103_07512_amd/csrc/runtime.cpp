@@ -462,19 +462,38 @@ struct Planner {
 
     std::vector<uint8_t> folded;  // constant subtrees replaced by their value
     std::vector<float> fold_val;
-    // A folded node is a constant leaf for the planner.
-    int op(int64_t n) const { return !folded.empty() && folded[n] ? TGP_CONST : (d.op[n] & 0xff); }
-    int arity(int64_t n) const { return kArity[op(n)]; }
+    // Operator and arity of every node as the planner sees it (a folded node
+    // is a constant leaf), filled at the start of decide.
+    std::vector<uint8_t> opv, arv;
+    double valu_dag = 0;  // cost-model slots of every DAG node once (unfolded)
+    int op(int64_t n) const { return opv[n]; }
+    int arity(int64_t n) const { return arv[n]; }
 
     // Decide the cached nodes; returns TGP_OK or an error.
     tgp_status decide(const std::vector<int32_t> &rootrefs, std::string &why) {
         const int64_t U = (int64_t)d.op.size();
+        const int32_t *kid = d.kid.data();
+        opv.resize(U);
+        arv.resize(U);
+        valu_dag = 0;
+        const bool any_folded = !folded.empty();
+        for (int64_t n = 0; n < U; ++n) {
+            const int o = d.op[n] & 0xff;
+            valu_dag += kOpCost[o];
+            const int v = any_folded && folded[n] ? TGP_CONST : o;
+            opv[n] = (uint8_t)v;
+            arv[n] = (uint8_t)kArity[v];
+        }
         cached.assign(U, 0);
         pre.assign(U, 0);
-        cost.assign(U, 0.0);
+        cost.resize(U);
         for (int64_t n = 0; n < U; ++n) {
-            double c = kOpCost[op(n)];
-            for (int j = 0; j < arity(n); ++j) c += cost[d.kid[3 * n + j]];
+            double c = kOpCost[opv[n]];
+            const int32_t *k = kid + 3 * n;
+            const int a = arv[n];
+            if (a > 0) c += cost[k[0]];
+            if (a > 1) c += cost[k[1]];
+            if (a > 2) c += cost[k[2]];
             cost[n] = c;
         }
         // Subtrees whose values over this domain are already resident (kept
@@ -482,32 +501,33 @@ struct Planner {
         // recomputing costs more than the read.
         if (!d.precached.empty() && access_cost >= 0)
             for (int64_t n = 0; n < U; ++n)
-                if (d.precached[n] && arity(n) > 0 && cost[n] > access_cost) cached[n] = pre[n] = 1;
+                if (d.precached[n] && arv[n] > 0 && cost[n] > access_cost) cached[n] = pre[n] = 1;
         // The value a warp gathers from is read at other cases than the one
         // being evaluated, so it is always materialised (a cached row).
         size_t used = 0;
         for (int64_t n = 0; n < U; ++n)
-            if (op(n) == TGP_WARP && !cached[d.kid[3 * n]]) {
-                cached[d.kid[3 * n]] = 1;
+            if (opv[n] == TGP_WARP && !cached[kid[3 * n]]) {
+                cached[kid[3 * n]] = 1;
                 ++used;
             }
         // Bottom-up: bound the register stack of every program.  Children are
         // evaluated in decreasing order of the stack they need (Sethi-Ullman);
         // a node whose children still cannot be evaluated within D slots gets
         // its most demanding child's subtree spilled to a cache row.
-        std::vector<int32_t> need(U, 1);
+        std::vector<uint8_t> need(U, 1);
         perm.assign(U, 0);
-        auto ref_need = [&](int32_t c) { return cached[c] ? 1 : need[c]; };
+        auto ref_need = [&](int32_t c) { return cached[c] ? 1 : (int)need[c]; };
         for (int64_t n = 0; n < U; ++n) {
-            const int a = arity(n);
+            const int a = arv[n];
             if (a == 0) continue;
-            if (op(n) == TGP_WARP) {  // t0 then t1 on the stack, in that order
+            const int32_t *k = kid + 3 * n;
+            if (opv[n] == TGP_WARP) {  // t0 then t1 on the stack, in that order
                 for (;;) {
-                    const int32_t c1 = d.kid[3 * n + 1], c2 = d.kid[3 * n + 2];
+                    const int32_t c1 = k[1], c2 = k[2];
                     const int r1 = ref_need(c1), r2 = ref_need(c2);
                     const int v = std::max(r1, 1 + r2);
                     if (v <= D) {
-                        need[n] = v;
+                        need[n] = (uint8_t)v;
                         break;
                     }
                     cached[r1 >= r2 ? c1 : c2] = 1;
@@ -515,12 +535,16 @@ struct Planner {
                 }
                 continue;
             }
+            if (a == 1) {  // a unary node needs what its operand needs
+                need[n] = (uint8_t)ref_need(k[0]);
+                continue;
+            }
             for (;;) {
                 int r[3] = {0, 0, 0};
-                for (int j = 0; j < a; ++j) r[j] = ref_need(d.kid[3 * n + j]);
+                for (int j = 0; j < a; ++j) r[j] = ref_need(k[j]);
                 // stable sort of child positions by need, largest first
                 int best_p = 0, best = 1 << 30;
-                const int n_orders = reorder ? (a == 3 ? 6 : (a == 2 ? 2 : 1)) : 1;
+                const int n_orders = reorder ? (a == 3 ? 6 : 2) : 1;
                 for (int p = 0; p < n_orders; ++p) {
                     const uint8_t *o = a == 2 ? (p ? kPerms[2] : kPerms[0]) : kPerms[p];
                     int v = 0;
@@ -531,14 +555,14 @@ struct Planner {
                     }
                 }
                 if (best <= D) {
-                    need[n] = best;
+                    need[n] = (uint8_t)best;
                     perm[n] = (uint8_t)best_p;
                     break;
                 }
                 int wj = 0;
                 for (int j = 1; j < a; ++j)
                     if (r[j] > r[wj]) wj = j;
-                cached[d.kid[3 * n + wj]] = 1;
+                cached[k[wj]] = 1;
                 ++used;
             }
         }
@@ -549,10 +573,10 @@ struct Planner {
         }
         // Top-down: how often each node would be evaluated, and whether
         // caching it pays for its HBM traffic (within the remaining budget).
-        std::vector<double> uses(U, 0.0);
-        for (int64_t n = 0; n < U; ++n) uses[n] = rootrefs[n];
+        std::vector<double> uses(rootrefs.begin(), rootrefs.end());
         for (int64_t n = U - 1; n >= 0; --n) {
-            if (!cached[n] && access_cost >= 0 && arity(n) > 0 && uses[n] >= 2 && used < budget_slots) {
+            const int a = arv[n];
+            if (!cached[n] && access_cost >= 0 && a > 0 && uses[n] >= 2 && used < budget_slots) {
                 const double save = cost[n] * (uses[n] - 1);
                 const double pay = access_cost * (uses[n] + 1);
                 if (save > pay) {
@@ -562,24 +586,23 @@ struct Planner {
             }
             const double contrib = pre[n] ? 0.0 : (cached[n] ? 1.0 : uses[n]);
             if (contrib > 0)
-                for (int j = 0; j < arity(n); ++j) uses[d.kid[3 * n + j]] += contrib;
+                for (int j = 0; j < a; ++j) uses[kid[3 * n + j]] += contrib;
         }
         // A spill below a resident subtree that nothing else reads is dropped
-        // (its fill would be wasted).
-        for (int64_t n = 0; n < U; ++n)
-            if (cached[n] && !pre[n] && uses[n] == 0) {
-                cached[n] = 0;
-                --used;
-            }
-        // Levels and slots.
+        // (its fill would be wasted).  Then levels and slots.
         std::vector<int32_t> dep(U, 0);
         level.assign(U, -1);
         slot.assign(U, -1);
         int32_t ns = 0;
         for (int64_t n = 0; n < U; ++n) {
+            if (cached[n] && !pre[n] && uses[n] == 0) {
+                cached[n] = 0;
+                --used;
+            }
             int32_t dp = 0;
-            for (int j = 0; j < arity(n); ++j) {
-                const int32_t c = d.kid[3 * n + j];
+            const int32_t *k = kid + 3 * n;
+            for (int j = 0; j < arv[n]; ++j) {
+                const int32_t c = k[j];
                 dp = std::max(dp, cached[c] ? level[c] + 1 : dep[c]);
             }
             dep[n] = dp;
@@ -595,8 +618,10 @@ struct Planner {
     }
 
     // Postfix program of node n (n itself is expanded even when cached).
-    // Adds the cost-model slots of its instructions to *valu.
-    void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads, double *valu) const {
+    // Adds the cost-model slots of its instructions to *valu; sets *ext when
+    // it emits a bitwise operator or warp, *warp_used for warp.
+    void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads, double *valu, bool *ext,
+              bool *warp_used) const {
         std::vector<std::pair<int32_t, int32_t>> st;  // (node, children emitted)
         st.push_back({root, 0});
         while (!st.empty()) {
@@ -627,8 +652,10 @@ struct Planner {
                     memcpy(&ins.y, !folded.empty() && folded[n] ? &fold_val[n] : &d.value[n], 4);
                 } else if (o == TGP_OR || o == TGP_XOR || o == TGP_AND) {
                     ins.x = (kFnBase + TGP_OR) | ((uint32_t)(o - TGP_OR) << 8);
+                    *ext = true;
                 } else if (o == TGP_WARP) {
                     ins.x = I_WARP;
+                    *ext = *warp_used = true;
                     ins.y = (uint32_t)slot[d.kid[3 * n]];
                     ++cache_reads;
                 } else if (perm[n] == 0 || (kArity[o] == 2 && is_commutative(o))) {
@@ -652,12 +679,13 @@ struct Emitted {
     uint32_t off, len;
     int64_t reads;
     double valu;
+    bool ext, warp;  // uses the bitwise operators or warp
 };
 
 void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<uint2> &code,
               std::vector<Emitted> &out, int threads) {
     const size_t n = nodes.size();
-    out.assign(n, Emitted{0, 0, 0, 0.0});
+    out.assign(n, Emitted{0, 0, 0, 0.0, false, false});
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int T = n < 512 ? 1 : (int)std::min<unsigned>((unsigned)std::max(threads, 1), hw);
     std::vector<std::vector<uint2>> local(T);
@@ -666,7 +694,7 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
         for (size_t i = b; i < e; ++i) {
             Emitted &m = out[i];
             m.off = (uint32_t)local[t].size();
-            pl.emit(nodes[i], local[t], m.reads, &m.valu);
+            pl.emit(nodes[i], local[t], m.reads, &m.valu, &m.ext, &m.warp);
             m.len = (uint32_t)(local[t].size() - m.off);
         }
     };
@@ -741,25 +769,29 @@ static void plan_prepare(PlanJob &w, bool fold) {
     if (!fold) return;
     // Constant subtrees (no variable below) that some non-constant node or a
     // root uses are folded: marked in pl.folded, evaluated on the device.
+    // novar: no variable below; 2 = also an operator (a foldable subtree)
     std::vector<uint8_t> novar(U, 0), use(U, 0);
     int32_t max_h = -1;
-    for (int64_t n = 0; n < U; ++n) {  // children have smaller ids
-        const int o = d->op[n] & 0xff;
-        bool nv = o != TGP_VAR;
-        for (int j = 0; j < kArity[o]; ++j) nv = nv && novar[d->kid[3 * n + j]];
-        novar[n] = nv;
-        if (nv) max_h = std::max(max_h, d->height[n]);
-    }
     int64_t n_use = 0;
     auto mark = [&](int32_t c) {
-        if (novar[c] && kArity[d->op[c] & 0xff] > 0 && !use[c]) {
+        if (novar[c] == 2 && !use[c]) {
             use[c] = 1;
             ++n_use;
         }
     };
-    for (int64_t n = 0; n < U; ++n)
-        if (!novar[n])
-            for (int j = 0; j < kArity[d->op[n] & 0xff]; ++j) mark(d->kid[3 * n + j]);
+    const int32_t *kid = d->kid.data();
+    for (int64_t n = 0; n < U; ++n) {  // children have smaller ids
+        const int o = d->op[n] & 0xff;
+        const int a = kArity[o];
+        bool nv = o != TGP_VAR;
+        for (int j = 0; j < a; ++j) nv = nv && novar[kid[3 * n + j]];
+        if (nv) {
+            novar[n] = a > 0 ? 2 : 1;
+            max_h = std::max(max_h, d->height[n]);
+        } else {
+            for (int j = 0; j < a; ++j) mark(kid[3 * n + j]);
+        }
+    }
     for (int32_t r : d->roots) mark(r);
     if (n_use == 0) return;
     // every variable-free node, by height (children before parents)
@@ -897,30 +929,25 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
         fill.insert(fill.end(), by_level[l].begin(), by_level[l].end());
     }
     P.level_first[max_level + 1] = (int32_t)fill.size();
-    std::vector<uint32_t> root_code(U, 0), root_len(U, 0);
     int64_t cache_reads_roots = 0;
     double exec_roots = 0;
-    std::vector<int64_t> reads_of(U, 0);
-    std::vector<double> valu_of(U, 0.0);
+    const std::vector<Emitted> em_fill = std::move(em);
     emit_all(pl, w.store_list, code, em, emit_threads);
-    for (size_t i = 0; i < w.store_list.size(); ++i) {
-        const int32_t n = w.store_list[i];
-        root_code[n] = em[i].off;
-        root_len[n] = em[i].len;
-        reads_of[n] = em[i].reads;
-        valu_of[n] = em[i].valu;
-    }
+    // program of each distinct root: store_list[i] <-> em[i]
+    std::unordered_map<int32_t, int32_t> prog_of;
+    prog_of.reserve(w.store_list.size() * 2);
+    for (size_t i = 0; i < w.store_list.size(); ++i) prog_of.emplace(w.store_list[i], (int32_t)i);
     double valu_roots = 0;
     for (size_t p = 0; p < w.reduce_list.size(); ++p) {
-        const int32_t n = w.reduce_list[p].first;
-        ProgDesc pd{root_code[n], root_len[n], (int32_t)p, w.reduce_list[p].second};
+        const Emitted &m = em[prog_of[w.reduce_list[p].first]];
+        ProgDesc pd{m.off, m.len, (int32_t)p, w.reduce_list[p].second};
         reduce.push_back(pd);
-        exec_roots += root_len[n] - 1;
-        cache_reads_roots += reads_of[n];
-        valu_roots += valu_of[n];
+        exec_roots += m.len - 1;
+        cache_reads_roots += m.reads;
+        valu_roots += m.valu;
     }
-    for (int32_t n : w.store_list) {
-        ProgDesc pd{root_code[n], root_len[n], w.store_of[n], 0};
+    for (size_t i = 0; i < w.store_list.size(); ++i) {
+        ProgDesc pd{em[i].off, em[i].len, w.store_of[w.store_list[i]], 0};
         store.push_back(pd);
     }
     // reduce programs keep dest = their row; order them longest first
@@ -930,8 +957,7 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
 
     double exec_fill = 0;
     for (auto &pd : fill) exec_fill += pd.len - 1;
-    double valu = 0;
-    for (int64_t n = 0; n < U; ++n) valu += kOpCost[d->op[n] & 0xff];
+    const double valu = pl.valu_dag;
     P.D = D;
     P.reorder = reorder;
     P.access_cost = access_cost;
@@ -943,11 +969,14 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
     P.cache_reads_per_case = cache_reads_fill + cache_reads_roots;
     P.instructions = (int64_t)code.size();
     P.ext = P.warp = false;
-    for (const uint2 &ins : code) {
-        const uint32_t c = ins.x & 0xffu;
-        if (c == kFnBase + TGP_OR) P.ext = true;
-        if (c == I_WARP) P.ext = P.warp = true;
-    }
+    auto flags = [&P](const std::vector<Emitted> &v) {
+        for (const Emitted &m : v) {
+            P.ext = P.ext || m.ext;
+            P.warp = P.warp || m.warp;
+        }
+    };
+    flags(em_fill);
+    flags(em);
     P.n_slots = (int32_t)cached_nodes.size();
     P.n_spills = pl.spills;
     P.n_fill = (int32_t)fill.size();
