@@ -8,6 +8,9 @@ shares no code with the HIP library and imports nothing from it.
                     optionally with the FP32-shaped variants and stability flags)
     fitness(...)    RMSE / MSE per individual in FP64 (oracle.c)
     build_dag(...)  Handley's population DAG by hash-consing (dag.py)
+    breed.breed(...) one generation of tournament selection, subtree crossover,
+                    subtree mutation and reproduction on counter-based draws
+                    (breed.py)
 """
 from .core import (build, coords, evaluate, fitness, library_path, max_threads,
                    render_target, target_renderer, STABLE, NONFINITE_STABLE)
