@@ -442,6 +442,81 @@ typedef struct {
 } tgp_server_stats;
 tgp_status tgp_server_stats_get(tgp_server server, tgp_server_stats *out);
 
+
+/* ------------------------------------------------- genetic operators */
+
+/* One generation bred on the device from a population and its fitness, so
+ * that a GP run can stay on the GPU between evaluations (the paper runs its
+ * genetic operators on the host, Sec. 4.2, and names ramped half-and-half as
+ * its generation method, Table 2; it does not fix selection or variation).
+ * The operators are the textbook tree-GP ones (Koza 1992):
+ *
+ *   offspring o draws its decisions from a counter-based stream: draw k is
+ *   output number o * 2^32 + k + 1 of SplitMix64 (Steele, Lea & Flood 2014)
+ *   started from `seed`; below(m) = floor(x * m / 2^64), uniform() =
+ *   (x >> 11) * 2^-53, a new constant = fl32(2u - 1) with u = (x >> 40) * 2^-24.
+ *   Draws in order: u = uniform(); parent p1 by tournament; when
+ *   u < p_crossover parent p2 by tournament.  A tournament draws
+ *   `tournament` parents below(n_parents) with replacement and keeps the
+ *   first of the lowest fitness (NaN and +-inf count as +inf; fitness NULL:
+ *   the first draw).  Then, for each channel ch, with a = tree ch of p1:
+ *     crossover: up to crossover_tries times draw i = below(len a) and
+ *       j = below(len b), b = tree ch of p2, and accept when depth_a(i) +
+ *       height_b(j) <= max_depth: the child is a with the subtree rooted at
+ *       token i replaced by b's subtree rooted at token j; with no accepted
+ *       draw the child is a copy of a;
+ *     mutation (p_crossover <= u < p_crossover + p_mutation): i = below(len a),
+ *       d = below(min(max(max_depth - depth_a(i), 0), max_mutation_depth) + 1),
+ *       full = below(2) == 0, and the subtree at i is replaced by a new random
+ *       tree of depth d, full or grow (nodes chosen in pre-order: at depth 0
+ *       a terminal below(n_terminals); full: a function below(n_functions);
+ *       grow: below(n_functions + n_terminals), a function when below
+ *       n_functions, else that terminal; terminals are the variables
+ *       0..ndim-1, then the constant when use_constants, which draws its
+ *       value);
+ *     reproduction (otherwise): a copy of a.
+ *   depth_a(i) is token i's distance from the root of a, height_b(j) the
+ *   height of the subtree at j (a leaf has height 0).
+ *
+ * Offspring are independent of each other (the first m of n offspring do not
+ * depend on n), and the output is a pure function of the inputs and seed. */
+typedef struct {
+    uint64_t seed;
+    int32_t n_offspring;        /* individuals bred (each of the parents' n_channels trees) */
+    int32_t tournament;         /* >= 1 */
+    double p_crossover;         /* in [0, 1] */
+    double p_mutation;          /* in [0, 1 - p_crossover]; the rest is reproduction */
+    int32_t max_depth;          /* >= 0 */
+    int32_t max_mutation_depth; /* >= 0 */
+    int32_t crossover_tries;    /* >= 1 */
+    int32_t ndim;               /* variables 0..ndim-1 (1 to 3) */
+    int32_t use_constants;      /* the ephemeral constant is a terminal */
+    int32_t n_functions;        /* >= 1 */
+    const uint8_t *functions;   /* host [n_functions] operator codes, each of arity >= 1 */
+} tgp_breed_params;
+
+typedef struct tgp_offspring_s *tgp_offspring;
+
+/* Breeds params->n_offspring individuals from `parents` (device or host
+ * memory; at least one individual when n_offspring > 0).  fitness_dev is a
+ * device array of n_individuals doubles (e.g. the output of tgp_fitness) or
+ * NULL.  Work is ordered on the context stream; the call blocks once, to
+ * learn the offspring's size.  Errors: TGP_EINVAL for bad parameters,
+ * TGP_EOP for an operator code that is not a function, TGP_EPARSE when a
+ * parent tree is not one postfix tree, TGP_EHIP, TGP_ENOMEM. */
+tgp_status tgp_breed(tgp_ctx ctx, const tgp_population *parents, const double *fitness_dev,
+                     const tgp_breed_params *params, tgp_offspring *out);
+/* A device view of the offspring (memory = TGP_MEM_DEVICE), valid until
+ * tgp_offspring_destroy; it can be passed to tgp_build_dag or be the parents
+ * of the next tgp_breed. */
+tgp_status tgp_offspring_population(tgp_offspring offspring, tgp_population *view);
+/* *n_tokens = the offspring's token count; when offsets_host and tokens_host
+ * are not NULL, also copies the offsets (n_individuals * n_channels + 1) and
+ * the tokens (*n_tokens) to host memory (blocks until they are written). */
+tgp_status tgp_offspring_export(tgp_offspring offspring, int64_t *n_tokens, int64_t *offsets_host,
+                                tgp_token *tokens_host);
+void tgp_offspring_destroy(tgp_offspring offspring);
+
 #ifdef __cplusplus
 }
 #endif

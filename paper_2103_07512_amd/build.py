@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtgp.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["runtime.cpp", "batch.cpp", "server.cpp", "k_dag.hip", "k_interp.hip", "k_fold.hip"]
+SOURCES = ["runtime.cpp", "batch.cpp", "server.cpp", "breed.cpp", "k_dag.hip", "k_interp.hip", "k_fold.hip",
+           "k_breed.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

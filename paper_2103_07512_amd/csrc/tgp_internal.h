@@ -161,6 +161,40 @@ struct FoldDesc {
 hipError_t launch_fold_level(const FoldDesc *jobs, const int2 *list, int32_t n, hipStream_t s);
 hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
                                  int32_t grid, hipStream_t s);
+// Genetic operators (k_breed.hip).  A child tree is the first parent's
+// tokens [a0, cut_lo) + a middle part of `mid` tokens + [cut_hi, a1); the
+// middle is the second parent's tokens from b_lo (splice) or a new random
+// subtree regenerated from draw sub_k of the offspring's stream (mutate).
+constexpr int kMaxMutationDepth = 16;
+enum { kBreedCopy = 0, kBreedSplice = 1, kBreedMutate = 2 };
+struct BreedRec {
+    int64_t a0, a1, cut_lo, cut_hi, b_lo;
+    int32_t mid, kind;
+    uint32_t sub_k;
+    int32_t sub_depth, sub_full, pad;
+};
+struct BreedArgs {
+    const uint2 *tok;          // parent tokens
+    const int64_t *off;        // parent offsets
+    const int32_t *size, *height, *depth;  // shape of every parent token
+    const double *fitness;     // [n_parents] or nullptr
+    const uint8_t *functions;  // [n_functions] operator codes (device)
+    BreedRec *recs;            // [n_offspring * n_channels]
+    int64_t *lens;             // [n_offspring * n_channels]
+    uint64_t seed;
+    double p_crossover, p_mutation;
+    int32_t n_parents, n_channels, n_offspring, tournament, max_depth, max_mutation_depth, tries;
+    int32_t ndim, use_constants, n_functions;
+};
+hipError_t launch_shape(const uint2 *tok, const int64_t *off, int64_t R, int64_t T, int32_t *size,
+                        int32_t *height, int32_t *depth, int32_t *bad, hipStream_t s);
+// Decisions, then the exclusive scan of the child lengths into out_off
+// (n_offspring * n_channels + 1 entries; block_sum holds breed_scan_blocks
+// entries, at least one).
+hipError_t launch_breed(const BreedArgs &A, const int32_t *bad, int64_t *out_off, int64_t *block_sum,
+                        hipStream_t s);
+int64_t breed_scan_blocks(int64_t n);
+hipError_t launch_breed_write(const BreedArgs &A, const int64_t *out_off, uint2 *out_tok, hipStream_t s);
 bool interp_variant_exists(int K, int D, bool bit = false);
 int interp_max_stack();   // register stack slots
 int interp_lds_stack();   // LDS stack slots (the other stack form, K = 2)

@@ -69,6 +69,15 @@ class Timing(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class BreedParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_offspring", ctypes.c_int32), ("tournament", ctypes.c_int32),
+                ("p_crossover", ctypes.c_double), ("p_mutation", ctypes.c_double),
+                ("max_depth", ctypes.c_int32), ("max_mutation_depth", ctypes.c_int32),
+                ("crossover_tries", ctypes.c_int32), ("ndim", ctypes.c_int32),
+                ("use_constants", ctypes.c_int32), ("n_functions", ctypes.c_int32),
+                ("functions", ctypes.c_void_p)]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("dag", ctypes.c_void_p), ("domain", ctypes.c_void_p), ("target_dev", ctypes.c_void_p),
                 ("loss", ctypes.c_int32), ("out_dev", ctypes.c_void_p)]
@@ -141,6 +150,10 @@ SIGNATURES = [
     ("tgp_domain_destroy", None, [P]),
     ("tgp_domain_cases", I64, [P]),
     ("tgp_build_dag", I32, [P, ctypes.POINTER(_Population), PP]),
+    ("tgp_breed", I32, [P, ctypes.POINTER(_Population), P, ctypes.POINTER(BreedParams), PP]),
+    ("tgp_offspring_population", I32, [P, ctypes.POINTER(_Population)]),
+    ("tgp_offspring_export", I32, [P, ctypes.POINTER(ctypes.c_int64), P, P]),
+    ("tgp_offspring_destroy", None, [P]),
     ("tgp_dag_stats_get", I32, [P, ctypes.POINTER(DagStats)]),
     ("tgp_dag_export", I32, [P, P, P, P, P, P]),
     ("tgp_dag_destroy", None, [P]),
@@ -292,26 +305,37 @@ class Domain:
             pass
 
 
-class Dag:
-    """tgp_dag: a population hash-consed on the GPU."""
+def _population_struct(tokens, offsets, n_individuals: int, n_channels: int):
+    """(struct, arrays to keep alive) for host numpy arrays or device tensors."""
+    pop = _Population()
+    pop.n_individuals = n_individuals
+    pop.n_channels = n_channels
+    keep = []
+    if hasattr(tokens, "data_ptr"):          # torch tensors on the device
+        pop.memory = MEM_DEVICE
+        pop.offsets = offsets.data_ptr()
+        pop.tokens = tokens.data_ptr()
+    else:
+        t = np.ascontiguousarray(tokens, dtype=TOKEN_DTYPE)
+        o = np.ascontiguousarray(offsets, dtype=np.int64)
+        keep += [t, o]
+        pop.memory = MEM_HOST
+        pop.offsets = o.ctypes.data
+        pop.tokens = t.ctypes.data
+    return pop, keep
 
-    def __init__(self, ctx: Context, tokens, offsets, n_individuals: int, n_channels: int = 1):
+
+class Dag:
+    """tgp_dag: a population hash-consed on the GPU.  tokens/offsets are host
+    arrays, device tensors, or tokens is an Offspring (offsets unused)."""
+
+    def __init__(self, ctx: Context, tokens, offsets=None, n_individuals: int = 0, n_channels: int = 1):
         self.ctx = ctx
-        pop = _Population()
-        pop.n_individuals = n_individuals
-        pop.n_channels = n_channels
-        keep = []
-        if hasattr(tokens, "data_ptr"):          # torch tensors on the device
-            pop.memory = MEM_DEVICE
-            pop.offsets = offsets.data_ptr()
-            pop.tokens = tokens.data_ptr()
+        if isinstance(tokens, Offspring):
+            pop, keep = tokens.population_struct(), [tokens]
+            n_individuals, n_channels = tokens.n_individuals, tokens.n_channels
         else:
-            t = np.ascontiguousarray(tokens, dtype=TOKEN_DTYPE)
-            o = np.ascontiguousarray(offsets, dtype=np.int64)
-            keep += [t, o]
-            pop.memory = MEM_HOST
-            pop.offsets = o.ctypes.data
-            pop.tokens = t.ctypes.data
+            pop, keep = _population_struct(tokens, offsets, n_individuals, n_channels)
         h = ctypes.c_void_p()
         _check(lib().tgp_build_dag(ctx.h, ctypes.byref(pop), ctypes.byref(h)), ctx.h)
         self.h = h
@@ -507,3 +531,81 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Offspring:
+    """tgp_offspring: one generation bred on the device (tgp_breed) from
+    parents (a host Population, an Offspring, or (tokens, offsets,
+    n_individuals, n_channels) device tensors) and their fitness (a device
+    float64 tensor, or None)."""
+
+    def __init__(self, ctx: Context, parents, fitness=None, *, seed: int, n_offspring: int, functions,
+                 tournament: int = 3, p_crossover: float = 0.8, p_mutation: float = 0.1,
+                 max_depth: int = 10, max_mutation_depth: int = 4, crossover_tries: int = 8,
+                 ndim: int = 2, use_constants: bool = True):
+        self.ctx = ctx
+        self.h = None
+        if isinstance(parents, Offspring):
+            pop, keep = parents.population_struct(), [parents]
+        elif isinstance(parents, tuple):
+            pop, keep = _population_struct(*parents)
+        else:
+            pop, keep = _population_struct(parents.tokens, parents.offsets, parents.n_individuals,
+                                           parents.n_channels)
+        codes = np.array([int(f) for f in functions], np.uint8)  # operator codes
+        p = BreedParams()
+        p.seed = seed & ((1 << 64) - 1)
+        p.n_offspring = n_offspring
+        p.tournament = tournament
+        p.p_crossover = p_crossover
+        p.p_mutation = p_mutation
+        p.max_depth = max_depth
+        p.max_mutation_depth = max_mutation_depth
+        p.crossover_tries = crossover_tries
+        p.ndim = ndim
+        p.use_constants = 1 if use_constants else 0
+        p.n_functions = len(codes)
+        p.functions = codes.ctypes.data
+        fit = fitness.data_ptr() if fitness is not None else None
+        h = ctypes.c_void_p()
+        _check(lib().tgp_breed(ctx.h, ctypes.byref(pop), fit, ctypes.byref(p), ctypes.byref(h)), ctx.h)
+        self.h = h
+        self.n_individuals = n_offspring
+        self.n_channels = pop.n_channels
+        del keep
+
+    def population_struct(self) -> "_Population":
+        pop = _Population()
+        _check(lib().tgp_offspring_population(self.h, ctypes.byref(pop)))
+        return pop
+
+    @property
+    def n_tokens(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().tgp_offspring_export(self.h, ctypes.byref(n), None, None))
+        return n.value
+
+    def to_host(self):
+        """(tokens, offsets) as numpy arrays."""
+        n = self.n_tokens
+        offs = np.zeros(self.n_individuals * self.n_channels + 1, np.int64)
+        toks = np.zeros(n, TOKEN_DTYPE)
+        m = ctypes.c_int64()
+        _check(lib().tgp_offspring_export(self.h, ctypes.byref(m), offs.ctypes.data, toks.ctypes.data),
+               self.ctx.h)
+        return toks, offs
+
+    def close(self):
+        if self.h:
+            lib().tgp_offspring_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def breed(ctx: Context, parents, fitness=None, **params) -> Offspring:
+    return Offspring(ctx, parents, fitness, **params)
