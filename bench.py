@@ -43,6 +43,9 @@ WORKLOADS = {
           "depth-4 tree",
     "c4": "64 populations (sizes log-uniform 20-2000, depths 4-14, 18 operators), domains 2-D "
           "32^2-1024^2 or 3-D 64^3, RMSE; one batched persistent step vs 64 plain launches",
+    "evolve": "a GP run on the headline workload kept on the GPU: each generation hash-conses and "
+              "evaluates the population (1000 x 3 trees, 1024x1024, MSE) and breeds the next one "
+              "on the device (tournament 3, crossover 0.8, mutation 0.1, depth <= 12, 18 operators)",
     "c5": "16 concurrent GP runs (grids 512^2-4096^2, populations log-uniform 200-2000, bred "
           "closed-loop from returned fitness, depth <= 12, 18 operators), RMSE; served with "
           "continuous batching and a resident subtree cache",
@@ -175,6 +178,114 @@ def bench_c4(args):
                    "eval_only_batched_over_plain": eval_plain / eval_batch,
                    "autotune": tune, "batch": st, "max_rel_diff_batched_vs_plain": agree},
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_evolve(args):
+    """Generations of a GP run that never leave the GPU: DAG build from the
+    device-resident population, plan, fitness, then tgp_breed on the device
+    from that fitness.  Reports node-evals/s over whole generations and the
+    breeding kernels' times; the oracle's breeding (host) is timed beside it."""
+    import numpy as np
+    import torch
+
+    from oracle import breed as oracle_breed
+    from paper_2103_07512_amd import popgen as pg
+    from paper_2103_07512_amd import tgp
+
+    dev = torch.device("cuda:0")
+    pop, dspec, tspec, loss = load_workload("c3")
+    F = [pg.OP_CODE[f] for f in pg.F18]
+    params = dict(functions=F, tournament=3, p_crossover=0.8, p_mutation=0.1, max_depth=12,
+                  max_mutation_depth=4, ndim=2)
+    ctx = tgp.Context(0)
+    dom = tgp.Domain(ctx, dspec.shape)
+
+    def render(tree):
+        d = tgp.Dag(ctx, tree, np.array([0, len(tree)], np.int64), 1)
+        v = torch.empty(1, dom.cases, dtype=torch.float32, device=dev)
+        tgp.evaluate(ctx, d, dom, v)
+        return v[0].cpu().numpy() if bool(torch.isfinite(v).all()) else None
+
+    _, target = pg.pick_target(tspec, render)
+    target_dev = torch.from_numpy(target).to(dev)
+    out = torch.empty(pop.n_individuals, dtype=torch.float64, device=dev)
+    ctx.set_timing(True)
+    parents = pop
+    rows = []
+    keep = None
+    n_gen = args.warmup + args.steps
+    torch.cuda.synchronize()
+    for g in range(n_gen):
+        if g == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        tg = time.perf_counter()
+        dag = tgp.Dag(ctx, parents) if isinstance(parents, tgp.Offspring) else tgp.Dag.from_population(ctx, parents)
+        tgp.fitness(ctx, dag, dom, target_dev, loss, out)
+        tm_eval = ctx.last_timing()
+        st = dag.stats()
+        dag.close()
+        tb = time.perf_counter()
+        child = tgp.Offspring(ctx, parents, out, seed=1000 + g, n_offspring=pop.n_individuals, **params)
+        tm = ctx.last_timing()
+        torch.cuda.synchronize()
+        rows.append(dict(dag_nodes=st["dag_nodes"], tree_nodes=st["tree_nodes"],
+                         breed_host_ms=(time.perf_counter() - tb) * 1e3,
+                         generation_ms=(time.perf_counter() - tg) * 1e3,
+                         interp_ms=tm_eval["interp_ms"], plan_ms=tm_eval["plan_ms"],
+                         build_dag_ms=tm_eval["build_dag_ms"],
+                         breed_shape_ms=tm["breed_shape_ms"], breed_plan_ms=tm["breed_plan_ms"],
+                         breed_write_ms=tm["breed_write_ms"], offspring_tokens=child.n_tokens,
+                         best=float(np.nanmin(out.cpu().numpy()))))
+        keep = parents
+        parents = child
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timed = rows[args.warmup:]
+    credited = sum(r["dag_nodes"] for r in timed) * dom.cases
+    ms = wall / args.steps * 1e3
+    # the breeding kernels: parent tokens read and the shapes written (shape),
+    # the child trees read from the parents and written (copy), per launch
+    last = timed[-1]
+    par_tokens = sum(r["tree_nodes"] for r in timed) / len(timed)
+    kid_tokens = float(np.mean([r["offspring_tokens"] for r in timed]))
+    shape_ms = float(np.mean([r["breed_shape_ms"] for r in timed]))
+    write_ms = float(np.mean([r["breed_write_ms"] for r in timed]))
+    shape_bytes = par_tokens * (8 + 12)
+    write_bytes = kid_tokens * 16
+    # oracle breeding of one generation on the host, from the last parents
+    cpu = None
+    if not args.no_cpu_baseline and isinstance(keep, tgp.Offspring):
+        toks, offs = keep.to_host()
+        fit = out.cpu().numpy()
+        c0 = time.perf_counter()
+        oracle_breed.breed(toks, offs, pop.n_channels, fit, 1, pop.n_individuals,
+                           tries=8, use_const=True, **{k: v for k, v in params.items()})
+        cpu_s = time.perf_counter() - c0
+        cpu = {"value": pop.n_individuals / cpu_s, "unit": "offspring/s", "cores": 1, "kind": "oracle",
+               "sample": f"one generation of {pop.n_individuals} offspring (x{pop.n_channels} trees) bred "
+                         f"by the oracle from the device-bred parents"}
+    breed_ms = float(np.mean([r["breed_shape_ms"] + r["breed_plan_ms"] + r["breed_write_ms"] for r in timed]))
+    line = {
+        "metric": METRIC, "value": credited / (ms / 1e3), "unit": "node-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["evolve"], "individuals": pop.n_individuals,
+                   "channels": pop.n_channels, "domain": list(dspec.shape), "generations": args.steps},
+        "roofline": {"bound": "hbm", "achieved": max(shape_bytes / (shape_ms / 1e3), write_bytes / (write_ms / 1e3)) / 1e9
+                     if shape_ms > 0 and write_ms > 0 else None,
+                     "peak": 8000.0, "unit": "GB/s", "frac": None, "traffic": None,
+                     "kernel": "breeding: k_shape (20 B per parent token) and k_breed_write (16 B per "
+                               "offspring token); the larger of the two rates",
+                     "kernel_ms": {"shape": shape_ms, "write": write_ms}},
+        "cpu_baseline": cpu,
+        "detail": {"generations": rows, "breed_device_ms": breed_ms,
+                   "breed_offspring_per_s": pop.n_individuals / (breed_ms / 1e3) if breed_ms > 0 else None,
+                   "breed_host_ms": float(np.mean([r["breed_host_ms"] for r in timed]))},
+    }
+    if line["roofline"]["achieved"] is not None:
+        line["roofline"]["frac"] = line["roofline"]["achieved"] / 8000.0
     print(json.dumps(line), flush=True)
 
 
@@ -401,6 +512,8 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.workload == "evolve":
+        return bench_evolve(args)
 
     import numpy as np
     import torch

@@ -278,8 +278,8 @@ typedef struct {
 } tgp_work_stats;
 tgp_status tgp_last_work(tgp_ctx ctx, tgp_work_stats *out);
 
-/* Phase times of the last tgp_build_dag and tgp_fitness / tgp_evaluate on
- * ctx.  Device times come from HIP events recorded on the context's stream
+/* Phase times of the last tgp_build_dag, tgp_fitness / tgp_evaluate and
+ * tgp_breed on ctx.  Device times come from HIP events recorded on the context's stream
  * around the launches, and are only taken while timing is enabled
  * (tgp_ctx_set_timing); tgp_last_timing blocks until those events complete. */
 typedef struct {
@@ -294,6 +294,9 @@ typedef struct {
     /* parts of plan_ms: constant folding (with its device round trip), the
      * caching and stack decisions, program emission, the rest */
     double plan_fold_ms, plan_decide_ms, plan_emit_ms;
+    /* device times of the last tgp_breed: the parents' shape launch, the
+     * decisions and the offset scan, the copy of the child trees */
+    double breed_shape_ms, breed_plan_ms, breed_write_ms;
 } tgp_timing;
 tgp_status tgp_ctx_set_timing(tgp_ctx ctx, int32_t enable);
 tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out);

@@ -181,8 +181,11 @@ tgp_status tgp_breed(tgp_ctx ctx, const tgp_population *par, const double *fitne
     A.n_functions = p->n_functions;
 
     e = hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream);
+    record(ctx, 6);
     if (e == hipSuccess) e = launch_shape(tok_dev, off_dev, R, T, size, height, depth, bad, ctx->stream);
+    record(ctx, 7);
     if (e == hipSuccess) e = launch_breed(A, bad, o->offsets, bsum, ctx->stream);
+    record(ctx, 8);
     // the offspring's token count and the parents' verdict
     int64_t total = 0;
     int32_t verdict = 0;
@@ -209,7 +212,9 @@ tgp_status tgp_breed(tgp_ctx ctx, const tgp_population *par, const double *fitne
     if (e != hipSuccess) return give_up(TGP_ENOMEM, "offspring tokens", e);
     o->tokens = static_cast<tgp_token *>(tb);
     o->n_tokens = total;
+    record(ctx, 9);
     e = launch_breed_write(A, o->offsets, reinterpret_cast<uint2 *>(o->tokens), ctx->stream);
+    record(ctx, 10);
     if (e != hipSuccess) return give_up(TGP_EHIP, "offspring write", e);
     *out = o;
     return TGP_OK;

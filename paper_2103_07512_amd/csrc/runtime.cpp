@@ -175,17 +175,23 @@ tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out) {
     if (!ctx || !out) return fail(ctx, TGP_EINVAL, "NULL argument");
     tgp_timing t = ctx->times;
     t.fill_ms = t.interp_ms = t.finalize_ms = 0;
+    t.breed_shape_ms = t.breed_plan_ms = t.breed_write_ms = 0;
     if (ctx->timing && ctx->ev_ready) {
-        HCHK(ctx, hipEventSynchronize(ctx->ev[5]));
-        float ms = 0;
-        if (ctx->fill_recorded) {
-            HCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
-            t.fill_ms = ms;
-        }
-        HCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
-        t.interp_ms = ms;
-        HCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]));
-        t.finalize_ms = ms;
+        // device time between two recorded events (0 when one never was)
+        auto span = [ctx](int a, int b, double *out) -> hipError_t {
+            if (!(ctx->recorded >> a & 1u) || !(ctx->recorded >> b & 1u)) return hipSuccess;
+            hipError_t e = hipEventSynchronize(ctx->ev[b]);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]);
+            if (e == hipSuccess) *out = ms;
+            return e;
+        };
+        if (ctx->fill_recorded) HCHK(ctx, span(0, 1, &t.fill_ms));
+        HCHK(ctx, span(2, 3, &t.interp_ms));
+        HCHK(ctx, span(4, 5, &t.finalize_ms));
+        HCHK(ctx, span(6, 7, &t.breed_shape_ms));
+        HCHK(ctx, span(7, 8, &t.breed_plan_ms));
+        HCHK(ctx, span(9, 10, &t.breed_write_ms));
     }
     *out = t;
     return TGP_OK;

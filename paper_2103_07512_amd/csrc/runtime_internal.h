@@ -43,7 +43,10 @@ struct tgp_ctx_s {
     bool pin_pending = false;
     bool timing = false;
     bool ev_ready = false;
-    hipEvent_t ev[6] = {};  // fill begin/end, interp begin/end, finalize begin/end
+    // fill begin/end, interp begin/end, finalize begin/end, then breeding:
+    // shape begin, shape end = decisions begin, decisions end, copy begin/end
+    hipEvent_t ev[11] = {};
+    uint32_t recorded = 0;  // bit i: ev[i] has been recorded
     bool fill_recorded = false;
     tgp_timing times{};
 };
@@ -55,7 +58,8 @@ inline double now_ms() {
 }
 
 inline void record(tgp_ctx ctx, int i) {
-    if (ctx->timing && ctx->ev_ready) hipEventRecord(ctx->ev[i], ctx->stream);
+    if (ctx->timing && ctx->ev_ready && hipEventRecord(ctx->ev[i], ctx->stream) == hipSuccess)
+        ctx->recorded |= 1u << i;
 }
 
 struct tgp_domain_s {

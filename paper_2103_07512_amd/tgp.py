@@ -63,7 +63,8 @@ class Timing(ctypes.Structure):
                 ("finalize_ms", ctypes.c_double), ("interp_items", ctypes.c_int64),
                 ("cases_per_lane", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32),
                 ("plan_fold_ms", ctypes.c_double), ("plan_decide_ms", ctypes.c_double),
-                ("plan_emit_ms", ctypes.c_double)]
+                ("plan_emit_ms", ctypes.c_double), ("breed_shape_ms", ctypes.c_double),
+                ("breed_plan_ms", ctypes.c_double), ("breed_write_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
