@@ -124,33 +124,20 @@ __device__ inline uint32_t tournament(Draws &dr, const BreedArgs &A) {
     return best;
 }
 
-// Shape of every token of one tree (one thread per tree): subtree size and
-// height from the operands (the last operand ends just before its parent,
-// each earlier one just before the next), then the depth from the root,
-// parents before children.  A tree that is not exactly one postfix tree, or
-// holds an unknown operator, raises *bad (1 = malformed, 2 = operator).
-__global__ void k_shape(const uint2 *tok, const int64_t *off, int64_t R, int64_t T, int32_t *size,
-                        int32_t *height, int32_t *depth, int32_t *bad) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const int64_t o0 = off[r], o1 = off[r + 1];
-    if (o0 < 0 || o1 <= o0 || o1 > T) {
-        atomicMax(bad, 1);
-        return;
-    }
+// Shape of one tree in global memory (the fallback for trees whose operand
+// stack outgrows the LDS stack): subtree size and height from the operands
+// (the last operand ends just before its parent, each earlier one just
+// before the next), then the depth from the root, parents before children.
+// Returns 0, 1 (malformed) or 2 (unknown operator).
+__device__ int shape_global(const uint2 *tok, int64_t o0, int64_t o1, int32_t *size, int32_t *height,
+                            int32_t *depth) {
     for (int64_t i = o0; i < o1; ++i) {
         const int op = tok_op(tok[i]);
-        if (op >= TGP_NUM_OPS) {
-            atomicMax(bad, 2);
-            return;
-        }
+        if (op >= TGP_NUM_OPS) return 2;
         int32_t s = 1, h = 0;
         int64_t c = i - 1;
         for (int j = 0; j < c_arity_b[op]; ++j) {
-            if (c < o0) {
-                atomicMax(bad, 1);
-                return;
-            }
+            if (c < o0) return 1;
             s += size[c];
             h = max(h, height[c] + 1);
             c -= size[c];
@@ -158,10 +145,7 @@ __global__ void k_shape(const uint2 *tok, const int64_t *off, int64_t R, int64_t
         size[i] = s;
         height[i] = h;
     }
-    if (size[o1 - 1] != (int32_t)(o1 - o0)) {
-        atomicMax(bad, 1);
-        return;
-    }
+    if (size[o1 - 1] != (int32_t)(o1 - o0)) return 1;
     depth[o1 - 1] = 0;
     for (int64_t i = o1 - 1; i >= o0; --i) {
         const int32_t d = depth[i] + 1;
@@ -171,6 +155,85 @@ __global__ void k_shape(const uint2 *tok, const int64_t *off, int64_t R, int64_t
             c -= size[c];
         }
     }
+    return 0;
+}
+
+constexpr int kShapeStack = 32;  // LDS operand-stack entries per thread
+
+// Shape of every token, one thread per tree.  Forward, an operand stack of
+// (size, height) pairs in LDS gives each token's subtree size and height
+// from its operands' entries; backward from the root, a stack of (depth of
+// the children, children still to come) frames gives each token's depth.
+// Both stacks hold at most the tree's postfix stack depth; a tree that needs
+// more than kShapeStack entries is redone with shape_global.  A tree that is
+// not exactly one postfix tree, or holds an unknown operator, raises *bad
+// (1 = malformed, 2 = operator).
+__global__ __launch_bounds__(64) void k_shape(const uint2 *tok, const int64_t *off, int64_t R, int64_t T,
+                                              int32_t *size, int32_t *height, int32_t *depth, int32_t *bad) {
+    __shared__ int2 stk[kShapeStack][64];
+    const int lane = threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + lane;
+    if (r >= R) return;
+    const int64_t o0 = off[r], o1 = off[r + 1];
+    if (o0 < 0 || o1 <= o0 || o1 > T) {
+        atomicMax(bad, 1);
+        return;
+    }
+    int sp = 0, verdict = 0;
+    bool overflow = false;
+    for_tokens<8, false>(tok, o0, o1, [&](int64_t i, uint2 w) {
+        const int op = tok_op(w);
+        if (op >= TGP_NUM_OPS) {
+            verdict = 2;
+            return false;
+        }
+        const int a = c_arity_b[op];
+        if (sp < a) {
+            verdict = 1;
+            return false;
+        }
+        int32_t s = 1, h = 0;
+        for (int j = 0; j < a; ++j) {
+            const int2 e = stk[--sp][lane];
+            s += e.x;
+            h = max(h, e.y + 1);
+        }
+        size[i] = s;
+        height[i] = h;
+        if (sp == kShapeStack) {
+            overflow = true;
+            return false;
+        }
+        stk[sp++][lane] = int2{s, h};
+        return true;
+    });
+    if (verdict) {
+        atomicMax(bad, verdict);
+        return;
+    }
+    if (overflow) {
+        const int v = shape_global(tok, o0, o1, size, height, depth);
+        if (v) atomicMax(bad, v);
+        return;
+    }
+    if (sp != 1) {
+        atomicMax(bad, 1);
+        return;
+    }
+    // backward: frames (depth of the children, children still to come)
+    sp = 0;
+    for_tokens<8, true>(tok, o0, o1, [&](int64_t i, uint2 w) {
+        const int a = c_arity_b[tok_op(w)];
+        int32_t d = 0;
+        if (sp > 0) {
+            int2 &f = stk[sp - 1][lane];
+            d = f.x;
+            if (--f.y == 0) --sp;
+        }
+        depth[i] = d;
+        if (a > 0) stk[sp++][lane] = int2{d + 1, a};
+        return true;
+    });
 }
 
 // The decisions of one offspring (one thread each): operator, parents, and

@@ -43,11 +43,90 @@ __device__ __forceinline__ void report(BuildStatus *st, int64_t r, int code) {
     atomicMin(&st->first_error, ((unsigned long long)r << 4) | (unsigned long long)code);
 }
 
-// 1. Structure scan, one thread per tree.  stk is T ints of scratch; tree r
-// uses stk[off[r] .. off[r+1]) as its stack.
-__global__ void k_structure(const uint2 *tok, const int64_t *off, int64_t R, int64_t T, int32_t *kid,
-                            int32_t *height, int32_t *stk, int32_t *root_tok, BuildStatus *st) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// 1. Structure scan, one thread per tree: children, subtree heights, the
+// postfix stack depth.  The operand stack of pending (token, height) pairs
+// lives in LDS (kStructStack entries per thread); a tree whose stack needs
+// more is rescanned with its stack in stk[off[r] .. off[r+1]) of global
+// scratch.
+constexpr int kStructStack = 32;
+
+template <bool LDS>
+__device__ __forceinline__ bool structure_scan(const uint2 *tok, int64_t o0, int64_t o1, int64_t r, int32_t *kid,
+                                               int32_t *height, int32_t *stk_g, int2 (*stk_l)[64], int lane,
+                                               BuildStatus *st, int32_t *out_maxsp, int32_t *out_internal,
+                                               int32_t *out_maxvar) {
+    int64_t sp = 0;
+    int32_t maxsp = 0, internal = 0, maxvar = -1;
+    int verdict = 0;  // 1 reported, 2 needs the global stack
+    for_tokens<8, false>(tok, o0, o1, [&](int64_t t, uint2 w) {
+        const uint32_t op = w.x & 0xffu;
+        if (op >= TGP_NUM_OPS) {
+            report(st, r, ERR_OP);
+            verdict = 1;
+            return false;
+        }
+        const int a = c_arity[op];
+        if (sp < a) {
+            report(st, r, ERR_PARSE);
+            verdict = 1;
+            return false;
+        }
+        int32_t h = 0;
+        int32_t k3[3] = {-1, -1, -1};
+        for (int j = a - 1; j >= 0; --j) {
+            --sp;
+            int32_t c, hc;
+            if constexpr (LDS) {
+                const int2 e = stk_l[sp][lane];
+                c = e.x;
+                hc = e.y + 1;
+            } else {
+                c = stk_g[o0 + sp];
+                hc = height[c] + 1;
+            }
+            k3[j] = c;
+            h = hc > h ? hc : h;
+        }
+        kid[3 * t + 0] = k3[0];
+        kid[3 * t + 1] = k3[1];
+        kid[3 * t + 2] = k3[2];
+        height[t] = h;
+        if constexpr (LDS) {
+            if (sp == kStructStack) {
+                verdict = 2;
+                return false;
+            }
+            stk_l[sp][lane] = int2{(int32_t)t, h};
+        } else {
+            stk_g[o0 + sp] = (int32_t)t;
+        }
+        ++sp;
+        if (sp > maxsp) maxsp = (int32_t)sp;
+        if (a > 0) ++internal;
+        if (op == TGP_VAR) {
+            const int32_t v = (int32_t)((w.x >> 8) & 0xffu);
+            maxvar = v > maxvar ? v : maxvar;
+        }
+        return true;
+    });
+    if (verdict == 1) return true;
+    if (verdict == 2) return false;
+    if (sp != 1) {
+        report(st, r, ERR_PARSE);
+        return true;
+    }
+    *out_maxsp = maxsp;
+    *out_internal = internal;
+    *out_maxvar = maxvar;
+    return true;
+}
+
+__global__ __launch_bounds__(64) void k_structure(const uint2 *tok, const int64_t *off, int64_t R, int64_t T,
+                                                  int32_t *kid, int32_t *height, int32_t *stk, int32_t *root_tok,
+                                                  BuildStatus *st) {
+    __shared__ int2 stk_l[kStructStack][64];
+    const int lane = threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + lane;
     if (r >= R) return;
     const int64_t o0 = off[r], o1 = off[r + 1];
     if (o0 < 0 || o1 > T || o1 < o0) {
@@ -58,45 +137,10 @@ __global__ void k_structure(const uint2 *tok, const int64_t *off, int64_t R, int
         report(st, r, ERR_PARSE);
         return;
     }
-    int64_t sp = 0;
-    int32_t maxsp = 0, internal = 0, maxvar = -1;
-    for (int64_t t = o0; t < o1; ++t) {
-        const uint2 w = tok[t];
-        const uint32_t op = w.x & 0xffu;
-        if (op >= TGP_NUM_OPS) {
-            report(st, r, ERR_OP);
-            return;
-        }
-        const int a = c_arity[op];
-        if (sp < a) {
-            report(st, r, ERR_PARSE);
-            return;
-        }
-        int32_t h = 0;
-        int32_t k3[3] = {-1, -1, -1};
-        for (int j = a - 1; j >= 0; --j) {
-            const int32_t c = stk[o0 + (--sp)];
-            k3[j] = c;
-            const int32_t hc = height[c] + 1;
-            h = hc > h ? hc : h;
-        }
-        kid[3 * t + 0] = k3[0];
-        kid[3 * t + 1] = k3[1];
-        kid[3 * t + 2] = k3[2];
-        height[t] = h;
-        stk[o0 + sp] = (int32_t)t;
-        ++sp;
-        if (sp > maxsp) maxsp = (int32_t)sp;
-        if (a > 0) ++internal;
-        if (op == TGP_VAR) {
-            const int32_t v = (int32_t)((w.x >> 8) & 0xffu);
-            maxvar = v > maxvar ? v : maxvar;
-        }
-    }
-    if (sp != 1) {
-        report(st, r, ERR_PARSE);
-        return;
-    }
+    int32_t maxsp = -1, internal = 0, maxvar = -1;
+    if (!structure_scan<true>(tok, o0, o1, r, kid, height, stk, stk_l, lane, st, &maxsp, &internal, &maxvar))
+        structure_scan<false>(tok, o0, o1, r, kid, height, stk, stk_l, lane, st, &maxsp, &internal, &maxvar);
+    if (maxsp < 0) return;  // reported
     root_tok[r] = (int32_t)(o1 - 1);
     atomicMax(&st->max_height, height[o1 - 1]);
     atomicMax(&st->max_stack, maxsp);

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "pow_fp64.h"
+
 namespace tgp {
 
 __device__ __forceinline__ float f_add(float a, float b) { return a + b; }
@@ -24,8 +26,9 @@ __device__ __forceinline__ float f_cos(float a) { return cospif(a) + 0.0f; }
 __device__ __forceinline__ float f_tan(float a) { return (sinpif(a) + 0.0f) / (cospif(a) + 0.0f); }
 __device__ __forceinline__ float f_exp(float a) { return expf(a); }
 __device__ __forceinline__ float f_log(float a) { return a < 0.0f ? -1.0f : logf(a); }
+// x^y with 0^0 = 0, otherwise C99 pow, carried in FP64 (pow_fp64.h).
 __device__ __forceinline__ float f_pow(float a, float b) {
-    return (a == 0.0f && b == 0.0f) ? 0.0f : powf(a, b);
+    return (a == 0.0f && b == 0.0f) ? 0.0f : pow_fp64(a, b);
 }
 __device__ __forceinline__ float f_min(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ float f_max(float a, float b) { return fmaxf(a, b); }

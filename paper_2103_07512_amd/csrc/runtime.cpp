@@ -90,7 +90,7 @@ const double kOpCost[TGP_NUM_OPS] = {
     1,  1,              // var const
     1,  1,  1, 13,      // add sub mult div
     38, 35, 55,         // sin cos tan
-    14, 15, 169,        // exp log pow
+    14, 15, 83,         // exp log pow
     3,  3,  3,  1,      // min max mdist neg
     19, 4,  1,  5,      // sqrt sign abs clip
     42, 2,  2,          // mod frac if

@@ -161,6 +161,34 @@ struct FoldDesc {
 hipError_t launch_fold_level(const FoldDesc *jobs, const int2 *list, int32_t n, hipStream_t s);
 hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, const uint32_t *n_ind,
                                  int32_t grid, hipStream_t s);
+#ifdef __HIPCC__
+// Calls f(i, token i) for the tokens of [lo, hi) in order (REV: from hi - 1
+// down to lo), reading them N at a time with the next N in flight, until f
+// returns false; returns whether every token was visited.  Per-tree scans
+// (one thread per tree) use it so that each token's load does not stall the
+// scan's dependent steps.
+template <int N, bool REV, typename F>
+__device__ __forceinline__ bool for_tokens(const uint2 *tok, int64_t lo, int64_t hi, F &&f) {
+    uint2 cur[N], nxt[N];
+    auto at = [&](int64_t base, int j) { return REV ? base - j : base + j; };
+    auto ok = [&](int64_t i) { return i >= lo && i < hi; };
+    const int64_t first = REV ? hi - 1 : lo;
+#pragma unroll
+    for (int j = 0; j < N; ++j) cur[j] = ok(at(first, j)) ? tok[at(first, j)] : uint2{0u, 0u};
+    for (int64_t base = first; ok(base); base = at(base, N)) {
+        const int64_t nb = at(base, N);
+#pragma unroll
+        for (int j = 0; j < N; ++j) nxt[j] = ok(at(nb, j)) ? tok[at(nb, j)] : uint2{0u, 0u};
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (ok(at(base, j)) && !f(at(base, j), cur[j])) return false;
+#pragma unroll
+        for (int j = 0; j < N; ++j) cur[j] = nxt[j];
+    }
+    return true;
+}
+#endif
+
 // Genetic operators (k_breed.hip).  A child tree is the first parent's
 // tokens [a0, cut_lo) + a middle part of `mid` tokens + [cut_hi, a1); the
 // middle is the second parent's tokens from b_lo (splice) or a new random

@@ -77,6 +77,19 @@ def test_breed_selection_and_sizes(env):
         _check(env, pop, fit, 11, n_off, functions=F18, tournament=t)
 
 
+def test_breed_deep_postfix_stacks(env):
+    """Parents whose postfix stack is deeper than the shape scan keeps in LDS
+    (32 entries) take its global-memory path; offspring still match."""
+    def chain(n, op):
+        text = "x"
+        for i in range(n):
+            text = f"{op}({'y' if i % 2 else 'x'}, {text})"
+        return text
+    texts = [chain(40, "add"), chain(20, "mult"), chain(35, "sub"), "x", chain(33, "max")]
+    pop = pg.population_from_texts(texts)
+    _check(env, pop, np.array([1.0, 2.0, 0.5, 3.0, 1.5]), 41, 30, functions=F18, max_depth=50)
+
+
 def test_breed_full_size_population(env):
     """The 1000 x 3 headline population (F18, depths 2-12), one generation."""
     pop = pg.workload_c3()[0]

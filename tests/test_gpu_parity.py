@@ -210,6 +210,38 @@ def test_dag_bit_exact(env):
     _dag_bit_exact(env, False)
 
 
+def right_chain(n, op="add", leaves=("x", "y")):
+    """op(l0, op(l1, ... op(l_{n-1}, l_n))): a postfix stack n + 1 deep."""
+    text = leaves[n % len(leaves)]
+    for i in range(n - 1, -1, -1):
+        text = f"{op}({leaves[i % len(leaves)]}, {text})"
+    return text
+
+
+def test_dag_deep_postfix_stacks(env):
+    """Trees whose postfix operand stack is deeper than the structure scan
+    keeps in LDS (32 entries) take its global-memory path: the DAG is still
+    bit-exact and the values match the oracle."""
+    tgp, ctx, torch = env
+    lerp_chain = "y"
+    for i in range(23):  # lerp(x, 0.5, lerp(x, 0.5, ...)): two pending operands per level
+        lerp_chain = f"lerp(x, {0.25 + i / 64}, {lerp_chain})"
+    texts = [right_chain(40), right_chain(31), right_chain(32), "add(x, y)", lerp_chain,
+             right_chain(33, "mult", ("x", "1.5", "y"))]
+    pop = pg.population_from_texts(texts)
+    dag = tgp.build_dag(ctx, pop)
+    g = dag.export()
+    o = oracle.build_dag(pop.tokens, pop.offsets)
+    say("deep stacks: max_stack", g["max_stack"], o["max_stack"])
+    assert g["dag_nodes"] == o["dag_nodes"] and g["max_stack"] == o["max_stack"] == 47
+    assert np.array_equal(g["children"], o["children"])
+    assert np.array_equal(g["roots"], o["roots"])
+    assert np.array_equal(g["multiplicity"], o["multiplicity"])
+    got, _, dom = gpu_eval(env, pop, (12, 10))
+    v64, v32, st, eb = oracle.evaluate(pop.tokens, pop.offsets, (12, 10), bound=True)
+    _parity.check_cases(got, v64, v32, st, "deep stacks")
+
+
 def test_dag_commutative_hashing(env):
     """Hash-consing up to operand order: bit-exact against the oracle's DAG of
     the same identity, fewer nodes, and the same per-case values and fitness."""
