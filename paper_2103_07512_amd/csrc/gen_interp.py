@@ -3,14 +3,17 @@
 
 The interpreter keeps the operand stack of a postfix program in registers.
 One wave runs one program and each lane owns K fitness cases, so the stack
-depth S before every instruction is the same for all lanes and is known when
-the instruction is dispatched.  The generated code has one dispatch block per
-depth S = 0..D.  In block S the stack slots are plain named values s0..s{D-1}
-(each a vector of K lanes' cases), an operator of arity a reads
-s{S-a}..s{S-1} and writes s{S-a}, and then jumps straight to the dispatch
-block of depth S-a+1.  No register is ever indexed at run time, and because
-the depth only rises by pushes of one value the control flow stays reducible:
-the block of depth S dominates every block of greater depth.
+depth S before every instruction is the same for all lanes (a scalar).  The
+stack slots are plain named values s0..s{D-1} (each a vector of K lanes'
+cases), and one dispatch loop switches on the pair (S, opcode): the case of
+an operator of arity a at depth S reads s{S-a}..s{S-1}, writes s{S-a} and
+sets S to S-a+1, so no register is ever indexed at run time.  A single loop
+around a single switch keeps the control flow simple for the compiler: with
+one dispatch block per depth, jumping between blocks, the blocks became a
+nest of loops whose multi-level exits the compiler implemented with boolean
+flags in scalar registers (tens of scalar moves and register spills per
+dispatched instruction); the flat loop costs a branch tree over the case
+keys.
 
 Operators with long bodies (transcendentals, floored modulo, the FP64 image
 operators) are compiled once as out-of-line functions that take and return
@@ -83,91 +86,88 @@ def called_functions():
 def body_for_depth(D):
     L = []
     e = L.append
-    e(f"// Stack of {D} register slots.  Returns when the program's I_END is reached")
-    e(f"// at depth 1 (res = the program's value); a malformed program gives NaN.")
+    e(f"// Stack of {D} register slots, one dispatch loop over (depth, opcode).")
     e("template <int K, bool EXT>")
     e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
     e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
     e("        const int32_t (&cidx)[K], const WarpGeom &wg, FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
-    e("    // The next instruction is fetched one dispatch ahead so that the scalar")
-    e("    // load overlaps the current operator's vector work.")
     e("    uint2 ins, nxt = *ip;")
     e("    ++ip;")
+    e("    uint32_t S = 0;")
+    e("    for (;;) {")
+    e("    ins = nxt;")
+    e("    nxt = *ip;")
+    e("    ++ip;")
+    e("    switch ((S << 8) | (ins.x & 0xffu)) {")
+    variants = []
+    for name, op, ar in FUNCS:
+        if name in BITWISE[1:]:
+            continue
+        variants.append((FN_BASE + op, name, ar, tuple(range(ar))))
+        if name in REVERSIBLE:
+            variants.append((REV_BASE + op, name, ar, (1, 0)))
+        if name in TERNARY:
+            t = TERNARY.index(name)
+            for p, order in enumerate(PERMS):
+                if p:
+                    variants.append((PERM_BASE + 6 * t + p, name, ar, order))
     for S in range(D + 1):
-        e(f"L{S}:")
-        e("    ins = nxt;")
-        e("    nxt = *ip;")
-        e("    ++ip;")
-        e("    switch (ins.x & 0xffu) {")
+        key = lambda c: f"({S}u << 8) | {c}"
         if S < D:
             for name, reg in (("I_X", "xv"), ("I_Y", "yv"), ("I_Z", "zv")):
-                e(f"    case {name}: s{S} = {reg}; goto L{S + 1};")
-            e("    case I_CONST: {")
+                e(f"    case {key(name)}: s{S} = {reg}; S = {S + 1}; continue;")
+            e(f"    case {key('I_CONST')}: {{")
             e("        const float c = __uint_as_float(ins.y);")
             e("#pragma unroll")
             e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = c;")
-            e(f"        goto L{S + 1};")
+            e(f"        S = {S + 1}; continue;")
             e("    }")
-            e("    case I_CACHE: {")
+            e(f"    case {key('I_CACHE')}: {{")
             e("        const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
             e("#pragma unroll")
             e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];")
-            e(f"        goto L{S + 1};")
+            e(f"        S = {S + 1}; continue;")
             e("    }")
         if S == 1:
-            e("    case I_END: res = s0; return;")
+            e(f"    case {key('I_END')}: res = s0; return;")
         if S >= 2:
-            e("    case I_WARP:")
+            e(f"    case {key('I_WARP')}:")
             e("        if constexpr (EXT) {")
             e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
             e("#pragma unroll")
             e(f"            for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row[warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], cidx[k])];")
-            e(f"            goto L{S - 1};")
+            e(f"            S = {S - 1}; continue;")
             e("        } else {")
             e("            goto BAD;")
             e("        }")
-        variants = []
-        for name, op, ar in FUNCS:
-            if name in BITWISE[1:]:
-                continue
-            variants.append((FN_BASE + op, name, ar, tuple(range(ar))))
-            if name in REVERSIBLE:
-                variants.append((REV_BASE + op, name, ar, (1, 0)))
-            if name in TERNARY:
-                t = TERNARY.index(name)
-                for p, order in enumerate(PERMS):
-                    if p:
-                        variants.append((PERM_BASE + 6 * t + p, name, ar, order))
         for c, name, ar, order in variants:
             if S < ar:
                 continue
             dst = S - ar
-            # child i was evaluated order.index(i)-th, so it sits in slot dst + that position
             src = [f"s{dst + order.index(i)}" for i in range(ar)]
             if name == BITWISE[0]:
-                # only in the interpreters built with EXT (the others are
-                # never given programs that use these operators)
-                e(f"    case {c}:")
+                e(f"    case {key(c)}:")
                 e("        if constexpr (EXT) {")
                 e("            const uint32_t kind = (ins.x >> 8) & 3u;")
                 e("#pragma unroll")
                 e(f"            for (int k = 0; k < K; ++k) s{dst}.v[k] = f_bitop({src[0]}.v[k], {src[1]}.v[k], kind);")
-                e(f"            goto L{dst + 1};")
+                e(f"            S = {dst + 1}; continue;")
                 e("        } else {")
                 e("            goto BAD;")
                 e("        }")
             elif name in CALLED:
-                e(f"    case {c}: s{dst} = vcall_{name}<K>({', '.join(src)}); goto L{dst + 1};")
+                e(f"    case {key(c)}: s{dst} = vcall_{name}<K>({', '.join(src)}); S = {dst + 1}; continue;")
             else:
-                e(f"    case {c}:")
+                e(f"    case {key(c)}:")
                 e("#pragma unroll")
                 args = ", ".join(f"{x}.v[k]" for x in src)
                 e(f"        for (int k = 0; k < K; ++k) s{dst}.v[k] = f_{name}({args});")
-                e(f"        goto L{dst + 1};")
-        e("    default: goto BAD;")
-        e("    }")
+                e(f"        S = {dst + 1}; continue;")
+    e("    default: goto BAD;")
+    e("    }")
+    e("    }")
     e("BAD:")
     e("#pragma unroll")
     e("    for (int k = 0; k < K; ++k) res.v[k] = __builtin_nanf(\"\");")
