@@ -128,11 +128,11 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t c = (uint32_t)cidx[k];
-            const uint32_t i0 = c / (uint32_t)a.stride[0];
+            const uint32_t i0 = div_by_magic(c, a.div_m[0], a.div_s[0]);
             xv.v[k] = a.coord[0][i0];
             if (a.ndim > 1) {
                 const uint32_t r = c - i0 * (uint32_t)a.stride[0];
-                const uint32_t i1 = r / (uint32_t)a.stride[1];
+                const uint32_t i1 = div_by_magic(r, a.div_m[1], a.div_s[1]);
                 yv.v[k] = a.coord[1][i1];
                 if (a.ndim > 2) {
                     const uint32_t i2 = r - i1 * (uint32_t)a.stride[1];
@@ -144,6 +144,14 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
                 yv.v[k] = 0.0f;
                 zv.v[k] = 0.0f;
             }
+        }
+        // the target values are loaded before the program runs, so that
+        // their latency overlaps its execution
+        FV<K> tv;
+        if constexpr (MODE != MODE_STORE) {
+            const float *trow = a.target + (size_t)chan * (size_t)a.target_stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k) tv.v[k] = trow[cidx[k]];
         }
         FV<K> res;
         WarpGeom wg{};
@@ -158,10 +166,9 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
             for (int k = 0; k < K; ++k)
                 if (valid[k]) row[cidx[k]] = res.v[k];
         } else {
-            const float *trow = a.target + (size_t)chan * (size_t)a.target_stride;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float e = res.v[k] - trow[cidx[k]];
+                const float e = res.v[k] - tv.v[k];
                 if (valid[k]) kahan_add(ks, kc, e * e);
             }
         }

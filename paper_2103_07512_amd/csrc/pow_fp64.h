@@ -21,10 +21,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#ifndef TGP_HD
 #ifdef __HIPCC__
 #define TGP_HD __host__ __device__
 #else
 #define TGP_HD
+#endif
 #endif
 
 namespace tgp {

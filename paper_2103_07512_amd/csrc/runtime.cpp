@@ -1191,6 +1191,7 @@ void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache)
         j.stride[k] = (int32_t)dom->stride[k];
         j.coord[k] = dom->coord[k] ? dom->coord[k] : dom->coord[0];
     }
+    for (int k = 0; k < 2; ++k) div_magic((uint32_t)dom->stride[k], &j.div_m[k], &j.div_s[k]);
     j.cache = cache;
     j.case_base = 0;
     j.cache_stride = j.out_stride = j.target_stride = dom->cases;

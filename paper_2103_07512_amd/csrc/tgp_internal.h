@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/tgp.h"
+#include "div_magic.h"
 
 namespace tgp {
 
@@ -82,6 +83,7 @@ struct JobDesc {
     int32_t ndim;
     int32_t shape[3];
     int32_t stride[3];
+    uint32_t div_m[2], div_s[2]; // multiply-shift division by stride[0], stride[1] (div_magic.h)
     const float *coord[3];       // per-axis coordinate tables of the whole domain
     const float *cache;          // I_CACHE row r: cache + r * cache_stride
     float *out;                  // STORE: row dest at out + dest * out_stride
