@@ -475,6 +475,282 @@ struct Planner {
     int op(int64_t n) const { return opv[n]; }
     int arity(int64_t n) const { return arv[n]; }
 
+    // The same decisions made level by level (DAG node heights) on T host
+    // threads.  Within a level the nodes are independent: each reads only
+    // what lower levels decided (bottom-up passes) or higher levels
+    // contributed (the top-down use counts), so the outcome does not depend
+    // on thread timing.  It can differ from the sequential form in one way:
+    // two parents of one height that share a child do not see each other's
+    // stack spills, so both may spill where the sequential pass spilled
+    // once.  Cache-budget admissions are made in node order within a level.
+    tgp_status decide_parallel(const std::vector<int32_t> &rootrefs, std::string &why, int T) {
+        const int64_t U = (int64_t)d.op.size();
+        const int32_t *kid = d.kid.data();
+        const int32_t *hgt = d.height.data();
+        opv.resize(U);
+        arv.resize(U);
+        cached.assign(U, 0);
+        pre.assign(U, 0);
+        cost.resize(U);
+        perm.assign(U, 0);
+        std::vector<uint8_t> need(U, 1);
+        std::vector<int64_t> uses(U, 0);
+        std::vector<int32_t> dep(U, 0);
+        level.assign(U, -1);
+        slot.assign(U, -1);
+        const bool any_folded = !folded.empty();
+        auto range = [U, T](int t, int64_t &b, int64_t &e) {
+            b = U * t / T;
+            e = U * (t + 1) / T;
+        };
+        // barrier shared by the T threads of this call
+        std::atomic<int> arrived{0}, generation{0};
+        auto barrier = [&]() {
+            const int g = generation.load(std::memory_order_acquire);
+            if (arrived.fetch_add(1, std::memory_order_acq_rel) + 1 == T) {
+                arrived.store(0, std::memory_order_relaxed);
+                generation.fetch_add(1, std::memory_order_acq_rel);
+            } else {
+                while (generation.load(std::memory_order_acquire) == g) std::this_thread::yield();
+            }
+        };
+        std::vector<double> valu_part(T, 0.0);
+        std::vector<std::vector<int64_t>> hist(T);
+        std::vector<int64_t> lvl_first;
+        std::vector<int32_t> order(U);
+        int32_t H = 0;
+        std::vector<int32_t> hmax(T, 0);
+        std::vector<std::vector<int32_t>> spill(T), cand(T);
+        std::vector<int64_t> used_part(T, 0), slot_part(T + 1, 0);
+        std::atomic<int64_t> used{0};
+        tgp_status result = TGP_OK;
+        auto level_nodes = [&](int32_t h, int t, int64_t &b, int64_t &e) {
+            const int64_t n0 = lvl_first[h], n1 = lvl_first[h + 1];
+            b = n0 + (n1 - n0) * t / T;
+            e = n0 + (n1 - n0) * (t + 1) / T;
+        };
+        // Evaluation counts grow with the product of sharing along a path;
+        // they saturate at 2^62 (any count that large decides alike).
+        auto add_sat = [](int64_t *p, int64_t v) {
+            int64_t o = __atomic_load_n(p, __ATOMIC_RELAXED);
+            while (!__atomic_compare_exchange_n(p, &o, std::min<int64_t>(o + v, int64_t(1) << 62), true,
+                                                __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+            }
+        };
+        auto mark = [&](int32_t c) {  // returns whether c was not cached before
+            return __atomic_exchange_n(&cached[c], (uint8_t)1, __ATOMIC_RELAXED) == 0;
+        };
+        auto work = [&](int t) {
+            int64_t b, e;
+            range(t, b, e);
+            // operators, arities, cost-model work; node heights
+            double v = 0;
+            int32_t hm = 0;
+            for (int64_t n = b; n < e; ++n) {
+                const int o = d.op[n] & 0xff;
+                v += kOpCost[o];
+                const int x = any_folded && folded[n] ? TGP_CONST : o;
+                opv[n] = (uint8_t)x;
+                arv[n] = (uint8_t)kArity[x];
+                hm = std::max(hm, hgt[n]);
+            }
+            valu_part[t] = v;
+            hmax[t] = hm;
+            barrier();
+            if (t == 0) {
+                for (int i = 0; i < T; ++i) H = std::max(H, hmax[i]);
+                lvl_first.assign(H + 2, 0);
+            }
+            barrier();
+            // nodes ordered by height, in id order within a height
+            hist[t].assign(H + 1, 0);
+            for (int64_t n = b; n < e; ++n) ++hist[t][hgt[n]];
+            barrier();
+            if (t == 0) {
+                int64_t at = 0;
+                for (int32_t h = 0; h <= H; ++h) {
+                    lvl_first[h] = at;
+                    for (int i = 0; i < T; ++i) {
+                        const int64_t c = hist[i][h];
+                        hist[i][h] = at;
+                        at += c;
+                    }
+                }
+                lvl_first[H + 1] = at;
+            }
+            barrier();
+            for (int64_t n = b; n < e; ++n) order[hist[t][hgt[n]]++] = (int32_t)n;
+            barrier();
+            // cost, bottom-up
+            for (int32_t h = 0; h <= H; ++h) {
+                int64_t lb, le;
+                level_nodes(h, t, lb, le);
+                for (int64_t i = lb; i < le; ++i) {
+                    const int32_t n = order[i];
+                    double c = kOpCost[opv[n]];
+                    const int32_t *k = kid + 3 * (int64_t)n;
+                    const int a = arv[n];
+                    if (a > 0) c += cost[k[0]];
+                    if (a > 1) c += cost[k[1]];
+                    if (a > 2) c += cost[k[2]];
+                    cost[n] = c;
+                }
+                barrier();
+            }
+            // resident subtrees and warp sources
+            if (!d.precached.empty() && access_cost >= 0)
+                for (int64_t n = b; n < e; ++n)
+                    if (d.precached[n] && arv[n] > 0 && cost[n] > access_cost) cached[n] = pre[n] = 1;
+            barrier();
+            int64_t u = 0;
+            for (int64_t n = b; n < e; ++n)
+                if (opv[n] == TGP_WARP && mark(kid[3 * n])) ++u;
+            used.fetch_add(u);
+            barrier();
+            // stack need, bottom-up; spills of one level applied after it
+            for (int32_t h = 0; h <= H; ++h) {
+                int64_t lb, le;
+                level_nodes(h, t, lb, le);
+                spill[t].clear();
+                for (int64_t i = lb; i < le; ++i) {
+                    const int32_t n = order[i];
+                    const int a = arv[n];
+                    if (a == 0) continue;
+                    const int32_t *k = kid + 3 * (int64_t)n;
+                    auto ref_need = [&](int32_t c) { return cached[c] ? 1 : (int)need[c]; };
+                    if (opv[n] == TGP_WARP) {  // t0 then t1 on the stack, in that order
+                        int r1 = ref_need(k[1]), r2 = ref_need(k[2]);
+                        while (std::max(r1, 1 + r2) > D) {
+                            const int32_t c = r1 >= r2 ? k[1] : k[2];
+                            spill[t].push_back(c);
+                            if (k[1] == c) r1 = 1;
+                            if (k[2] == c) r2 = 1;
+                        }
+                        need[n] = (uint8_t)std::max(r1, 1 + r2);
+                        continue;
+                    }
+                    if (a == 1) {
+                        need[n] = (uint8_t)ref_need(k[0]);
+                        continue;
+                    }
+                    int r[3] = {0, 0, 0};
+                    for (int j = 0; j < a; ++j) r[j] = ref_need(k[j]);
+                    for (;;) {
+                        int best_p = 0, best = 1 << 30;
+                        const int n_orders = reorder ? (a == 3 ? 6 : 2) : 1;
+                        for (int p = 0; p < n_orders; ++p) {
+                            const uint8_t *o = a == 2 ? (p ? kPerms[2] : kPerms[0]) : kPerms[p];
+                            int vv = 0;
+                            for (int q = 0; q < a; ++q) vv = std::max(vv, q + r[o[q]]);
+                            if (vv < best) {
+                                best = vv;
+                                best_p = a == 2 ? (p ? 2 : 0) : p;
+                            }
+                        }
+                        if (best <= D) {
+                            need[n] = (uint8_t)best;
+                            perm[n] = (uint8_t)best_p;
+                            break;
+                        }
+                        int wj = 0;
+                        for (int j = 1; j < a; ++j)
+                            if (r[j] > r[wj]) wj = j;
+                        spill[t].push_back(k[wj]);
+                        for (int j = 0; j < a; ++j)
+                            if (k[j] == k[wj]) r[j] = 1;
+                    }
+                }
+                barrier();
+                int64_t su = 0;
+                for (int32_t c : spill[t])
+                    if (mark(c)) ++su;
+                used.fetch_add(su);
+                barrier();
+            }
+            if (t == 0) {
+                spills = used.load();
+                if ((size_t)spills > budget_slots) {
+                    why = "the subtree cache needed to bound the evaluator stack exceeds the cache budget";
+                    result = TGP_ENOMEM;
+                }
+            }
+            barrier();
+            if (result != TGP_OK) return;
+            // use counts, top-down; caching where it pays for its HBM traffic
+            for (int64_t n = b; n < e; ++n) uses[n] = rootrefs[n];
+            barrier();
+            for (int32_t h = H; h >= 0; --h) {
+                int64_t lb, le;
+                level_nodes(h, t, lb, le);
+                cand[t].clear();
+                for (int64_t i = lb; i < le; ++i) {
+                    const int32_t n = order[i];
+                    const double un = (double)uses[n];
+                    if (!cached[n] && access_cost >= 0 && arv[n] > 0 && un >= 2 &&
+                        cost[n] * (un - 1) > access_cost * (un + 1))
+                        cand[t].push_back(n);
+                }
+                barrier();
+                if (t == 0) {  // admissions in node order (within the budget)
+                    for (int i = 0; i < T; ++i)
+                        for (int32_t n : cand[i])
+                            if ((size_t)used.load() < budget_slots) {
+                                cached[n] = 1;
+                                used.fetch_add(1);
+                            }
+                }
+                barrier();
+                for (int64_t i = lb; i < le; ++i) {
+                    const int32_t n = order[i];
+                    const int64_t contrib = pre[n] ? 0 : (cached[n] ? 1 : uses[n]);
+                    if (contrib > 0)
+                        for (int j = 0; j < arv[n]; ++j)
+                            add_sat(&uses[kid[3 * (int64_t)n + j]], contrib);
+                }
+                barrier();
+            }
+            // spills below resident subtrees that nothing else reads
+            for (int64_t n = b; n < e; ++n)
+                if (cached[n] && !pre[n] && uses[n] == 0) cached[n] = 0;
+            barrier();
+            // levels of the cached nodes, bottom-up
+            for (int32_t h = 0; h <= H; ++h) {
+                int64_t lb, le;
+                level_nodes(h, t, lb, le);
+                for (int64_t i = lb; i < le; ++i) {
+                    const int32_t n = order[i];
+                    int32_t dp = 0;
+                    for (int j = 0; j < arv[n]; ++j) {
+                        const int32_t c = kid[3 * (int64_t)n + j];
+                        dp = std::max(dp, cached[c] ? level[c] + 1 : dep[c]);
+                    }
+                    dep[n] = dp;
+                    if (pre[n]) level[n] = -1;  // available before the first fill level
+                    else if (cached[n]) level[n] = dp;
+                }
+                barrier();
+            }
+            // slots in node order
+            int64_t cnt = 0;
+            for (int64_t n = b; n < e; ++n) cnt += cached[n];
+            slot_part[t + 1] = cnt;
+            barrier();
+            if (t == 0)
+                for (int i = 0; i < T; ++i) slot_part[i + 1] += slot_part[i];
+            barrier();
+            int32_t ns = (int32_t)slot_part[t];
+            for (int64_t n = b; n < e; ++n)
+                if (cached[n]) slot[n] = ns++;
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+        work(0);
+        for (auto &x : th) x.join();
+        valu_dag = 0;
+        for (double v : valu_part) valu_dag += v;
+        return result;
+    }
+
     // Decide the cached nodes; returns TGP_OK or an error.
     tgp_status decide(const std::vector<int32_t> &rootrefs, std::string &why) {
         const int64_t U = (int64_t)d.op.size();
@@ -718,6 +994,9 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
 }  // namespace
 
 // ------------------------------------------------------------------ planning
+// DAGs of at least this many nodes are planned level-parallel on host threads.
+constexpr int64_t kParallelDecideNodes = 1 << 15;
+
 //
 // Planning one DAG runs in phases so that a batch of many DAGs can run each
 // phase for all of them at once: host preparation (program lists, the
@@ -890,7 +1169,10 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
     for (uint8_t f : pl.folded) P.n_folded += f;
     pl.reorder = reorder;
     pl.access_cost = access_cost;
-    tgp_status st = pl.decide(w.rootrefs, w.err);
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int dt = (int)std::min<unsigned>((unsigned)std::max(emit_threads, 1), hw);
+    tgp_status st = U >= kParallelDecideNodes && dt > 1 ? pl.decide_parallel(w.rootrefs, w.err, dt)
+                                                        : pl.decide(w.rootrefs, w.err);
     if (st != TGP_OK) return st;
     const double t1 = now_ms();
     w.t_decide = t1 - t0;
