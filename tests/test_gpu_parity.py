@@ -99,6 +99,44 @@ TABLE1 = [
 ]
 
 
+def _floored_mod_f32(a, b):
+    """The floored remainder in FP32 from numpy's fmod (exact, sign of a)
+    moved into the divisor's sign by one FP32 addition; 0 for b == 0."""
+    with np.errstate(invalid="ignore", divide="ignore"):
+        r = np.fmod(a, b).astype(np.float32)
+        fix = (r != 0) & ((r < 0) != (b < 0))
+        r = np.where(fix, (r + b).astype(np.float32), r)
+        return np.where(b == 0, np.float32(0), r).astype(np.float32)
+
+
+def test_mod_bitwise_fmod(env):
+    """mod on the device equals fmod's exact remainder, moved into the
+    divisor's sign, bit for bit (signed zeros included; NaN where fmod is
+    NaN), over operand ranges that give exact multiples, huge quotients and
+    subnormal remainders, and with infinite and NaN operands."""
+    ranges = [((-4.0, -1.0), (4.0, 1.0)), ((-1e6, -3.0), (1e6, 3.0)), ((-1e-30, -1e-38), (1e-30, 1e-38)),
+              ((-3e38, -1.0), (3e38, 1.0)), ((-7.0, -7.0), (7.0, 7.0))]
+    ninf = "log(mult(x, 0.0))"  # ln(+-0) = -inf at every case
+    cases = [("mod(x, y)", lambda X, Y: (X, Y)), ("mod(y, x)", lambda X, Y: (Y, X)),
+             (f"mod({ninf}, y)", lambda X, Y: (np.full_like(X, -np.inf), Y)),
+             (f"mod(neg({ninf}), y)", lambda X, Y: (np.full_like(X, np.inf), Y)),
+             (f"mod(y, {ninf})", lambda X, Y: (Y, np.full_like(X, -np.inf))),
+             (f"mod(y, neg({ninf}))", lambda X, Y: (Y, np.full_like(X, np.inf))),
+             ("mod(x, pow(-0.5, 0.5))", lambda X, Y: (X, np.full_like(X, np.nan))),
+             ("mod(pow(-0.5, 0.5), y)", lambda X, Y: (np.full_like(X, np.nan), Y))]
+    pop = pg.population_from_texts([t for t, _ in cases])
+    for lo, hi in ranges:
+        say("mod over", lo, hi)
+        got, _, _ = gpu_eval(env, pop, (801, 799), lo, hi)
+        X, Y = np.meshgrid(oracle.coords(801, lo[0], hi[0]), oracle.coords(799, lo[1], hi[1]), indexing="ij")
+        for g, (text, operands) in zip(got, cases):
+            a, b = operands(X, Y)
+            want = _floored_mod_f32(a.ravel().astype(np.float32), b.ravel().astype(np.float32))
+            nan = np.isnan(want)
+            assert np.array_equal(np.isnan(g), nan), (text, lo, hi)
+            assert np.array_equal(g[~nan].view(np.uint32), want[~nan].view(np.uint32)), (text, lo, hi)
+
+
 def test_table1_points(env):
     say("table 1 special points:", len(TABLE1))
     pop = pg.population_from_texts([t for t, _ in TABLE1])
