@@ -1014,6 +1014,9 @@ struct PlanJob {
     std::vector<int32_t> fold_first, fold_list;
     size_t fold_list_at = 0, fold_val_at = 0;
     double t_decide = 0, t_emit = 0;
+    // fill-program figures carried from the fill emission to the root one
+    int64_t cache_reads_fill = 0;
+    double valu_fill = 0;
     tgp_status st = TGP_OK;
     std::string err;
     PlanJob(tgp_dag dag, int64_t n_cases, int D, size_t budget)
@@ -1155,11 +1158,14 @@ static tgp_status fold_run(tgp_ctx ctx, const std::vector<PlanJob *> &jobs) {
     return TGP_OK;
 }
 
-// Caching and stack decisions, then the programs: fill programs by level,
-// one program per distinct (root, channel) and one per distinct root.
-// Host only; emit_threads host threads emit the programs.
-static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double access_cost, int fold,
-                                   int emit_threads) {
+static void longest_first(std::vector<ProgDesc> &v) {
+    std::stable_sort(v.begin(), v.end(), [](const ProgDesc &a, const ProgDesc &b) { return a.len > b.len; });
+}
+
+// Caching and stack decisions, then the fill programs by level (the first
+// part of code_host).  Host only; emit_threads host threads emit.
+static tgp_status plan_decide_emit_fill(PlanJob &w, int D, bool reorder, double access_cost, int fold,
+                                        int emit_threads) {
     tgp_dag d = w.d;
     Plan &P = d->plan;
     Planner &pl = w.pl;
@@ -1178,7 +1184,7 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
     w.t_decide = t1 - t0;
 
     std::vector<uint2> code;
-    std::vector<ProgDesc> fill, reduce, store;
+    std::vector<ProgDesc> fill;
     int32_t max_level = -1;
     std::vector<int32_t> cached_nodes;
     for (int64_t n = 0; n < U; ++n)
@@ -1208,18 +1214,46 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
         valu_fill += em[i].valu;
         by_level[pl.level[n]].push_back(pd);
     }
-    auto longest_first = [](std::vector<ProgDesc> &v) {
-        std::stable_sort(v.begin(), v.end(), [](const ProgDesc &a, const ProgDesc &b) { return a.len > b.len; });
-    };
     for (int l = 0; l <= max_level; ++l) {
         longest_first(by_level[l]);
         P.level_first[l] = (int32_t)fill.size();
         fill.insert(fill.end(), by_level[l].begin(), by_level[l].end());
     }
     P.level_first[max_level + 1] = (int32_t)fill.size();
+    code.push_back(uint2{I_END, 0});  // padding: the interpreter reads one instruction ahead
+    P.D = D;
+    P.reorder = reorder;
+    P.access_cost = access_cost;
+    P.fold = fold;
+    P.ext = P.warp = false;
+    for (const Emitted &m : em) {
+        P.ext = P.ext || m.ext;
+        P.warp = P.warp || m.warp;
+    }
+    P.n_slots = (int32_t)cached_nodes.size();
+    P.n_spills = pl.spills;
+    P.n_fill = (int32_t)fill.size();
+    P.code_host = std::move(code);
+    P.fill_host = std::move(fill);
+    P.root_code_at = (int64_t)P.code_host.size();
+    w.cache_reads_fill = cache_reads_fill;
+    w.valu_fill = valu_fill;
+    w.t_emit = now_ms() - t1;
+    return TGP_OK;
+}
+
+// The root programs, appended to code_host: one per distinct (root,
+// channel) for the fitness form and one per distinct root for the evaluate
+// form.  Completes the plan.
+static void plan_emit_roots(PlanJob &w, int emit_threads) {
+    const double t0 = now_ms();
+    Plan &P = w.d->plan;
+    const Planner &pl = w.pl;
+    std::vector<uint2> &code = P.code_host;
+    std::vector<ProgDesc> reduce, store;
+    std::vector<Emitted> em;
     int64_t cache_reads_roots = 0;
     double exec_roots = 0;
-    const std::vector<Emitted> em_fill = std::move(em);
     emit_all(pl, w.store_list, code, em, emit_threads);
     // program of each distinct root: store_list[i] <-> em[i]
     std::unordered_map<int32_t, int32_t> prog_of;
@@ -1244,76 +1278,113 @@ static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double acces
     code.push_back(uint2{I_END, 0});  // padding
 
     double exec_fill = 0;
-    for (auto &pd : fill) exec_fill += pd.len - 1;
-    const double valu = pl.valu_dag;
-    P.D = D;
-    P.reorder = reorder;
-    P.access_cost = access_cost;
-    P.fold = fold;
+    for (auto &pd : P.fill_host) exec_fill += pd.len - 1;
     P.exec_per_case = exec_fill + exec_roots;
-    P.valu_dag_per_case = valu;
-    P.valu_fill_per_case = valu_fill;
+    P.valu_dag_per_case = pl.valu_dag;
+    P.valu_fill_per_case = w.valu_fill;
     P.valu_roots_per_case = valu_roots;
-    P.cache_reads_per_case = cache_reads_fill + cache_reads_roots;
+    P.cache_reads_per_case = w.cache_reads_fill + cache_reads_roots;
     P.instructions = (int64_t)code.size();
-    P.ext = P.warp = false;
-    auto flags = [&P](const std::vector<Emitted> &v) {
-        for (const Emitted &m : v) {
-            P.ext = P.ext || m.ext;
-            P.warp = P.warp || m.warp;
-        }
-    };
-    flags(em_fill);
-    flags(em);
-    P.n_slots = (int32_t)cached_nodes.size();
-    P.n_spills = pl.spills;
-    P.n_fill = (int32_t)fill.size();
+    for (const Emitted &m : em) {
+        P.ext = P.ext || m.ext;
+        P.warp = P.warp || m.warp;
+    }
     P.n_reduce = (int32_t)reduce.size();
     P.n_store = (int32_t)store.size();
-    P.code_host = std::move(code);
-    P.fill_host = std::move(fill);
     P.reduce_host = std::move(reduce);
     P.store_host = std::move(store);
     P.ind_rows_host = std::move(w.ind_rows);
     P.cases = w.cases;
-    w.t_emit = now_ms() - t1;
-    return TGP_OK;
+    w.t_emit += now_ms() - t0;
 }
 
-// One device block (256-byte aligned parts) filled by one copy from the
-// pinned staging; later launches on the stream see it in order.
-static tgp_status plan_upload(tgp_ctx ctx, Plan &P) {
-    const size_t part[5] = {sizeof(uint2) * P.code_host.size(), sizeof(ProgDesc) * P.fill_host.size(),
-                            sizeof(ProgDesc) * P.reduce_host.size(), sizeof(ProgDesc) * P.store_host.size(),
-                            sizeof(int32_t) * P.ind_rows_host.size()};
-    const void *src[5] = {P.code_host.data(), P.fill_host.data(), P.reduce_host.data(), P.store_host.data(),
-                          P.ind_rows_host.data()};
-    size_t off[5], total = 0;
-    for (int i = 0; i < 5; ++i) {
+static tgp_status plan_decide_emit(PlanJob &w, int D, bool reorder, double access_cost, int fold,
+                                   int emit_threads) {
+    tgp_status st = plan_decide_emit_fill(w, D, reorder, access_cost, fold, emit_threads);
+    if (st == TGP_OK) plan_emit_roots(w, emit_threads);
+    return st;
+}
+
+// Copies n parts into one new pool block (256-byte aligned parts) by one copy
+// from the pinned staging; later launches on the stream see it in order.
+// A part's `rebase`, when nonzero, is subtracted from the code offset of
+// each of its ProgDesc entries as it is staged.
+struct UploadPart {
+    const void *src;
+    size_t bytes;
+    uint32_t rebase;
+};
+static hipError_t upload_parts(tgp_ctx ctx, int n, const UploadPart *part, void **blob, char **base,
+                               size_t *off) {
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
         off[i] = total;
-        total += (part[i] + 255) & ~(size_t)255;
+        total += (part[i].bytes + 255) & ~(size_t)255;
     }
+    total = std::max<size_t>(total, 256);
     void *stage = nullptr;
-    hipError_t e = ctx->pool.alloc(&P.blob, total);
+    hipError_t e = ctx->pool.alloc(blob, total);
     if (e == hipSuccess) e = ctx_pinned(ctx, total, &stage);
-    if (e == hipSuccess) {
-        for (int i = 0; i < 5; ++i)
-            if (part[i]) memcpy((char *)stage + off[i], src[i], part[i]);
-        e = hipMemcpyAsync(P.blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < n; ++i) {
+        if (!part[i].bytes) continue;
+        char *dst = (char *)stage + off[i];
+        memcpy(dst, part[i].src, part[i].bytes);
+        if (part[i].rebase) {
+            ProgDesc *pd = reinterpret_cast<ProgDesc *>(dst);
+            for (size_t k = 0; k < part[i].bytes / sizeof(ProgDesc); ++k) pd[k].code_off -= part[i].rebase;
+        }
     }
+    e = hipMemcpyAsync(*blob, stage, total, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = ctx_pinned_enqueued(ctx);
+    *base = static_cast<char *>(*blob);
+    return e;
+}
+
+// The fill programs: code_host up to root_code_at and the fill descriptors.
+static tgp_status plan_upload_fill(tgp_ctx ctx, Plan &P) {
+    const UploadPart part[2] = {{P.code_host.data(), sizeof(uint2) * (size_t)P.root_code_at, 0},
+                                {P.fill_host.data(), sizeof(ProgDesc) * P.fill_host.size(), 0}};
+    size_t off[2];
+    char *b = nullptr;
+    hipError_t e = upload_parts(ctx, 2, part, &P.blob, &b, off);
     if (e != hipSuccess) {
         hipStreamSynchronize(ctx->stream);
         P.release(ctx->pool);
         return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
     }
-    char *b = static_cast<char *>(P.blob);
     P.code_dev = reinterpret_cast<uint2 *>(b + off[0]);
     P.fill_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
-    P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
-    P.store_dev = reinterpret_cast<ProgDesc *>(b + off[3]);
-    P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[4]);
     return TGP_OK;
+}
+
+// The root programs: the rest of code_host, the reduce and store descriptors
+// (offsets rebased to the start of that code) and the individual rows.
+static tgp_status plan_upload_roots(tgp_ctx ctx, Plan &P) {
+    const uint32_t at = (uint32_t)P.root_code_at;
+    const UploadPart part[4] = {
+        {P.code_host.data() + at, sizeof(uint2) * (P.code_host.size() - at), 0},
+        {P.reduce_host.data(), sizeof(ProgDesc) * P.reduce_host.size(), at},
+        {P.store_host.data(), sizeof(ProgDesc) * P.store_host.size(), at},
+        {P.ind_rows_host.data(), sizeof(int32_t) * P.ind_rows_host.size(), 0}};
+    size_t off[4];
+    char *b = nullptr;
+    hipError_t e = upload_parts(ctx, 4, part, &P.blob_roots, &b, off);
+    if (e != hipSuccess) {
+        hipStreamSynchronize(ctx->stream);
+        P.release(ctx->pool);
+        return fail(ctx, TGP_EHIP, "plan upload: %s", hipGetErrorString(e));
+    }
+    P.code_roots_dev = reinterpret_cast<uint2 *>(b + off[0]);
+    P.reduce_dev = reinterpret_cast<ProgDesc *>(b + off[1]);
+    P.store_dev = reinterpret_cast<ProgDesc *>(b + off[2]);
+    P.ind_rows_dev = reinterpret_cast<int32_t *>(b + off[3]);
+    return TGP_OK;
+}
+
+static tgp_status plan_upload(tgp_ctx ctx, Plan &P) {
+    tgp_status st = plan_upload_fill(ctx, P);
+    return st == TGP_OK ? plan_upload_roots(ctx, P) : st;
 }
 
 int ctx_stack_slots(tgp_ctx ctx) { return ctx->stack_lds ? interp_lds_stack() : interp_max_stack(); }
@@ -1327,7 +1398,7 @@ static size_t budget_slots(tgp_ctx ctx, int64_t cases) {
     return (size_t)(ctx->cache_budget / (sizeof(float) * (size_t)std::max<int64_t>(cases, 1)));
 }
 
-tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
+tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases, const std::function<tgp_status()> &after_fill) {
     const double t0 = now_ms();
     Plan &P = d->plan;
     if (plan_current(ctx, P, cases)) {
@@ -1347,12 +1418,20 @@ tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases) {
     tgp_status st = fold_run(ctx, {&w});
     if (st != TGP_OK) return st;
     ctx->times.plan_fold_ms = now_ms() - tf0;
-    st = plan_decide_emit(w, D, ctx->reorder != 0, ctx->cache_access_cost, ctx->fold, 8);
+    st = plan_decide_emit_fill(w, D, ctx->reorder != 0, ctx->cache_access_cost, ctx->fold, 8);
     if (st != TGP_OK) return fail(ctx, st, "%s", w.err.c_str());
+    if (ctx->plan_upload) {
+        // the fill goes to the device (and, through after_fill, to work)
+        // while the root programs are emitted
+        st = plan_upload_fill(ctx, P);
+        if (st == TGP_OK && after_fill) st = after_fill();
+        if (st != TGP_OK) return st;
+    }
+    plan_emit_roots(w, 8);
     ctx->times.plan_decide_ms = w.t_decide;
     ctx->times.plan_emit_ms = w.t_emit;
     if (ctx->plan_upload) {
-        st = plan_upload(ctx, P);
+        st = plan_upload_roots(ctx, P);
         if (st != TGP_OK) return st;
     }
     ctx->times.plan_ms = now_ms() - t0;
@@ -1483,9 +1562,9 @@ void fill_job(JobDesc &j, tgp_domain dom, const uint2 *code, const float *cache)
     }
 }
 
-static void fill_args(InterpArgs &a, tgp_domain dom, const Plan &P, const float *cache) {
+static void fill_args(InterpArgs &a, tgp_domain dom, const uint2 *code, const float *cache) {
     memset(&a, 0, sizeof a);
-    fill_job(a.job, dom, P.code_dev, cache);
+    fill_job(a.job, dom, code, cache);
 }
 
 static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float **cache_out) {
@@ -1503,7 +1582,7 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
         const int32_t b = P.level_first[l], e = P.level_first[l + 1];
         if (e == b) continue;
         InterpArgs a;
-        fill_args(a, dom, P, cache);
+        fill_args(a, dom, P.code_dev, cache);
         a.progs = P.fill_dev + b;
         a.n_progs = e - b;
         choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
@@ -1512,6 +1591,21 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
     }
     record(ctx, 1);
     return TGP_OK;
+}
+
+// The plan of d for dom with its cache filled (fill launches queued on the
+// context's stream).  A new plan's fill is queued as soon as its programs
+// are on the device, while the host still emits the root programs; the
+// fill's operand stack form follows the fill programs alone (they may not
+// need the bitwise operators or warp when the root programs do).
+static tgp_status plan_and_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float **cache) {
+    bool filled = false;
+    tgp_status st = build_plan(ctx, d, dom->cases, [&]() {
+        filled = true;
+        return run_fill(ctx, d, dom, choose_K(ctx, dom->cases, d->plan.ext), cache);
+    });
+    if (st != TGP_OK || filled) return st;
+    return run_fill(ctx, d, dom, choose_K(ctx, dom->cases, d->plan.ext), cache);
 }
 
 tgp_status check_eval_args(tgp_ctx ctx, tgp_dag d, tgp_domain dom) {
@@ -1552,15 +1646,13 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     if (d->n_ind == 0) return TGP_OK;
     if (!target_dev || !out_dev) return fail(ctx, TGP_EINVAL, "NULL target or output");
     HCHK(ctx, hipSetDevice(ctx->device));
-    st = build_plan(ctx, d, dom->cases);
+    float *cache = nullptr;
+    st = plan_and_fill(ctx, d, dom, &cache);
     if (st != TGP_OK) return st;
     const Plan &P = d->plan;
     const int K = choose_K(ctx, dom->cases, P.ext);
-    float *cache = nullptr;
-    st = run_fill(ctx, d, dom, K, &cache);
-    if (st != TGP_OK) return st;
     InterpArgs a;
-    fill_args(a, dom, P, cache);
+    fill_args(a, dom, P.code_roots_dev, cache);
     a.progs = P.reduce_dev;
     a.n_progs = P.n_reduce;
     choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
@@ -1587,15 +1679,13 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag d, tgp_domain dom, float *out_dev) 
     if (d->stats.n_roots == 0) return TGP_OK;
     if (!out_dev) return fail(ctx, TGP_EINVAL, "NULL output");
     HCHK(ctx, hipSetDevice(ctx->device));
-    st = build_plan(ctx, d, dom->cases);
+    float *cache = nullptr;
+    st = plan_and_fill(ctx, d, dom, &cache);
     if (st != TGP_OK) return st;
     const Plan &P = d->plan;
     const int K = choose_K(ctx, dom->cases, P.ext);
-    float *cache = nullptr;
-    st = run_fill(ctx, d, dom, K, &cache);
-    if (st != TGP_OK) return st;
     InterpArgs a;
-    fill_args(a, dom, P, cache);
+    fill_args(a, dom, P.code_roots_dev, cache);
     a.progs = P.store_dev;
     a.n_progs = P.n_store;
     choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -88,11 +89,18 @@ struct Plan {
     int32_t n_store = 0;                // programs for distinct roots
     std::vector<int32_t> store_rows;    // for each root r: the store program's dest row, or -1
     std::vector<int32_t> dup_src;       // for each root r: row r copies row dup_src[r] (-1: none)
-    void *blob = nullptr;               // one pool block holding the arrays below
-    uint2 *code_dev = nullptr;
+    // Device copies in two pool blocks, so that the fill can start before the
+    // root programs are emitted: blob holds the fill programs' code and
+    // descriptors, blob_roots the root programs' code (code_roots_dev), the
+    // reduce and store descriptors (code offsets relative to code_roots_dev)
+    // and the individual rows.
+    void *blob = nullptr, *blob_roots = nullptr;
+    uint2 *code_dev = nullptr, *code_roots_dev = nullptr;
     ProgDesc *fill_dev = nullptr, *reduce_dev = nullptr, *store_dev = nullptr;
     int32_t *ind_rows_dev = nullptr;
-    // host copies (the batched path packs them into its own buffers)
+    int64_t root_code_at = 0;           // first root instruction in code_host
+    // host copies (the batched path packs them into its own buffers); code
+    // offsets in all three descriptor lists are into code_host
     std::vector<uint2> code_host;
     std::vector<ProgDesc> fill_host, reduce_host, store_host;
     std::vector<int32_t> ind_rows_host;
@@ -109,8 +117,9 @@ struct Plan {
     // The caller guarantees that no queued kernel still reads the block.
     void release(DevicePool &pool) {
         pool.release(blob);
-        blob = nullptr;
-        code_dev = nullptr;
+        pool.release(blob_roots);
+        blob = blob_roots = nullptr;
+        code_dev = code_roots_dev = nullptr;
         fill_dev = reduce_dev = store_dev = nullptr;
         ind_rows_dev = nullptr;
         cases = -1;
@@ -190,8 +199,12 @@ tgp_status batch_step(tgp_batch b, int32_t n_jobs, const StepJob *jobs, int64_t 
 // --------------------------------------------------------------- shared helpers
 extern const double kOpCost[TGP_NUM_OPS];
 // Plans d for domains of `cases` cases (a no-op when its plan is current) and
-// uploads the programs when the context keeps plans on the device.
-tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases);
+// uploads the programs when the context keeps plans on the device.  When a
+// new plan is uploaded, after_fill (if given) is called once the fill
+// programs are on the device and before the root programs are emitted, so
+// that the caller can queue the cache fill while the host emits the rest.
+tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases,
+                      const std::function<tgp_status()> &after_fill = nullptr);
 // Plans many DAGs at once (host threads, one device round trip for constant
 // folding); programs stay on the host.  A DAG listed more than once is
 // planned once, for its largest domain.
