@@ -9,11 +9,12 @@
 
 namespace tgp {
 
-// The nodes of one height whose subtrees hold no variable, over the DAGs of
-// a batch: entry i of list is (DAG, node).  Each node is evaluated once with
-// the interpreter's own FP32 operators (ops_device.h, built with the same
-// flags, so a folded value is bitwise the value every case computes);
-// children come from the DAG's val, written by the launches of lower heights.
+// The operator nodes of one height whose subtrees hold no variable, over the
+// DAGs of a batch: entry i of list is (DAG, node).  Each node is evaluated
+// once with the interpreter's own FP32 operators (ops_device.h, built with
+// the same flags, so a folded value is bitwise the value every case
+// computes); an operator child's value comes from the DAG's val, written by
+// the launches of lower heights, a constant child's from the node values.
 __global__ void k_fold_level(const FoldDesc *jobs, const int2 *list, int32_t n) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -23,16 +24,16 @@ __global__ void k_fold_level(const FoldDesc *jobs, const int2 *list, int32_t n) 
     const int32_t *node_kid = J.node_kid;
     const float *node_value = J.node_value;
     float *val = J.val;
-    const uint32_t w = (uint32_t)J.node_op[u];
-    const int op = (int)(w & 0xffu);
+    const int32_t *node_op = J.node_op;
+    const int op = (int)((uint32_t)node_op[u] & 0xffu);
     const int32_t *k = node_kid + 3 * (int64_t)u;
-    if (op == TGP_CONST) {
-        val[u] = node_value[u];
-        return;
-    }
-    const float a = val[k[0]];
-    const float b = k[1] >= 0 ? val[k[1]] : 0.0f;
-    const float c = k[2] >= 0 ? val[k[2]] : 0.0f;
+    auto child = [&](int32_t c) {
+        if (c < 0) return 0.0f;
+        return ((uint32_t)node_op[c] & 0xffu) == TGP_CONST ? node_value[c] : val[c];
+    };
+    const float a = child(k[0]);
+    const float b = child(k[1]);
+    const float c = child(k[2]);
     float r;
     switch (op) {
     case TGP_ADD: r = f_add(a, b); break;

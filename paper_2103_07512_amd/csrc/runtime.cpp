@@ -1059,7 +1059,6 @@ static void plan_prepare(PlanJob &w, bool fold) {
     // root uses are folded: marked in pl.folded, evaluated on the device.
     // novar: no variable below; 2 = also an operator (a foldable subtree)
     std::vector<uint8_t> novar(U, 0), use(U, 0);
-    int32_t max_h = -1;
     int64_t n_use = 0;
     auto mark = [&](int32_t c) {
         if (novar[c] == 2 && !use[c]) {
@@ -1067,7 +1066,11 @@ static void plan_prepare(PlanJob &w, bool fold) {
             ++n_use;
         }
     };
+    // the variable-free operator nodes by height (constant leaves are read
+    // from the node values by the fold kernel)
+    std::vector<std::vector<int32_t>> by_h;
     const int32_t *kid = d->kid.data();
+    const int32_t *height = d->height.data();
     for (int64_t n = 0; n < U; ++n) {  // children have smaller ids
         const int o = d->op[n] & 0xff;
         const int a = kArity[o];
@@ -1075,22 +1078,22 @@ static void plan_prepare(PlanJob &w, bool fold) {
         for (int j = 0; j < a; ++j) nv = nv && novar[kid[3 * n + j]];
         if (nv) {
             novar[n] = a > 0 ? 2 : 1;
-            max_h = std::max(max_h, d->height[n]);
+            if (a > 0) {
+                const int32_t h = height[n];
+                if ((int32_t)by_h.size() <= h) by_h.resize(h + 1);
+                by_h[h].push_back((int32_t)n);
+            }
         } else {
             for (int j = 0; j < a; ++j) mark(kid[3 * n + j]);
         }
     }
     for (int32_t r : d->roots) mark(r);
     if (n_use == 0) return;
-    // every variable-free node, by height (children before parents)
-    w.fold_first.assign(max_h + 2, 0);
-    for (int64_t n = 0; n < U; ++n)
-        if (novar[n]) ++w.fold_first[d->height[n] + 1];
-    for (int h = 0; h <= max_h; ++h) w.fold_first[h + 1] += w.fold_first[h];
-    w.fold_list.resize(w.fold_first[max_h + 1]);
-    std::vector<int32_t> at(w.fold_first.begin(), w.fold_first.end() - 1);
-    for (int64_t n = 0; n < U; ++n)
-        if (novar[n]) w.fold_list[at[d->height[n]]++] = (int32_t)n;
+    // children before parents: one list, cut at each height
+    w.fold_first.assign(by_h.size() + 1, 0);
+    for (size_t h = 0; h < by_h.size(); ++h) w.fold_first[h + 1] = w.fold_first[h] + (int32_t)by_h[h].size();
+    w.fold_list.reserve(w.fold_first.back());
+    for (const auto &v : by_h) w.fold_list.insert(w.fold_list.end(), v.begin(), v.end());
     w.pl.folded.swap(use);
 }
 
