@@ -529,14 +529,6 @@ struct Planner {
             b = n0 + (n1 - n0) * t / T;
             e = n0 + (n1 - n0) * (t + 1) / T;
         };
-        // Evaluation counts grow with the product of sharing along a path;
-        // they saturate at 2^62 (any count that large decides alike).
-        auto add_sat = [](int64_t *p, int64_t v) {
-            int64_t o = __atomic_load_n(p, __ATOMIC_RELAXED);
-            while (!__atomic_compare_exchange_n(p, &o, std::min<int64_t>(o + v, int64_t(1) << 62), true,
-                                                __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
-            }
-        };
         auto mark = [&](int32_t c) {  // returns whether c was not cached before
             return __atomic_exchange_n(&cached[c], (uint8_t)1, __ATOMIC_RELAXED) == 0;
         };
@@ -700,12 +692,19 @@ struct Planner {
                             }
                 }
                 barrier();
+                // A count is at most the number of occurrences of the node in
+                // the population's trees (each unit is one root-to-node path),
+                // so it cannot overflow.  Leaves are skipped unless cached (a
+                // warp source): nothing reads their counts, and they are the
+                // most shared nodes, so their additions would contend most.
                 for (int64_t i = lb; i < le; ++i) {
                     const int32_t n = order[i];
                     const int64_t contrib = pre[n] ? 0 : (cached[n] ? 1 : uses[n]);
                     if (contrib > 0)
-                        for (int j = 0; j < arv[n]; ++j)
-                            add_sat(&uses[kid[3 * (int64_t)n + j]], contrib);
+                        for (int j = 0; j < arv[n]; ++j) {
+                            const int32_t c = kid[3 * (int64_t)n + j];
+                            if (arv[c] > 0 || cached[c]) __atomic_fetch_add(&uses[c], contrib, __ATOMIC_RELAXED);
+                        }
                 }
                 barrier();
             }
