@@ -137,6 +137,27 @@ def test_mod_bitwise_fmod(env):
             assert np.array_equal(g[~nan].view(np.uint32), want[~nan].view(np.uint32)), (text, lo, hi)
 
 
+def test_min_max_operand_order(env):
+    """The planner evaluates the children of min and max in either order and
+    emits the plain opcode for both (it treats them as commutative there).
+    That needs fminf/fmaxf on the device to give the same bits in both
+    operand orders, signed zeros and NaN operands included."""
+    z = {"x": "mult(x, 0.0)", "y": "mult(y, 0.0)"}  # +0 or -0 by the sign of the coordinate
+    nan = "pow(x, 0.5)"                              # NaN where x < 0
+    pairs = [(z["x"], z["y"]), (z["x"], "y"), (nan, "y"), (nan, "pow(y, 0.5)"), ("x", "y")]
+    texts = []
+    for op in ("min", "max"):
+        for a, b in pairs:
+            texts += [f"{op}({a}, {b})", f"{op}({b}, {a})"]
+    pop = pg.population_from_texts(texts)
+    got, _, _ = gpu_eval(env, pop, (65, 63), (-1.0, -1.0), (1.0, 1.0))
+    for i in range(0, len(texts), 2):
+        a, b = got[i], got[i + 1]
+        assert np.array_equal(np.isnan(a), np.isnan(b)), texts[i]
+        ok = ~np.isnan(a)
+        assert np.array_equal(a[ok].view(np.uint32), b[ok].view(np.uint32)), texts[i]
+
+
 def test_table1_points(env):
     say("table 1 special points:", len(TABLE1))
     pop = pg.population_from_texts([t for t, _ in TABLE1])
