@@ -252,11 +252,14 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, float *out_dev
 
 /* Fitness (Sec. 4.1): per individual, the RMSE (TGP_RMSE) or MSE (TGP_MSE)
  * over all channels and cases against target_dev[channel][case] (device,
- * n_channels * cases floats), written as FP64 to out_dev[individual]
- * (device pointer).  Squares are accumulated with compensated FP32 sums and
+ * n_channels * cases floats), written as FP64 to out[individual].  out is a
+ * device pointer (the work is queued on the context's stream and the call
+ * returns without waiting for it) or host memory, pageable or pinned (the
+ * values go through a context-owned device buffer and the call blocks until
+ * they are in out).  Squares are accumulated with compensated FP32 sums and
  * combined in FP64; any non-finite term makes the fitness +inf. */
 tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, const float *target_dev,
-                       int32_t loss, double *out_dev);
+                       int32_t loss, double *out);
 
 /* Work counts of the last tgp_evaluate / tgp_fitness on ctx (for reports).
  * VALU figures are lane-slots: cases x the per-operator instruction counts of

@@ -138,6 +138,7 @@ void tgp_ctx_destroy(tgp_ctx ctx) {
     tgp_batch_destroy(ctx->batch);
     hipFree(ctx->partial.p);
     hipFree(ctx->cache.p);
+    hipFree(ctx->fit_out.p);
     ctx->pool.drain();
     if (ctx->pin) hipHostFree(ctx->pin);
     if (ctx->pin_ev) hipEventDestroy(ctx->pin_ev);
@@ -1640,14 +1641,30 @@ static void record_work(tgp_ctx ctx, tgp_dag d, tgp_domain dom, bool fitness) {
 
 extern "C" {
 
+// Whether p is host memory (pageable or pinned) rather than device-resident.
+static bool is_host_memory(const void *p) {
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();  // an unknown (pageable) pointer: clear the error it leaves
+        return true;
+    }
+    return attr.type == hipMemoryTypeHost || attr.type == hipMemoryTypeUnregistered;
+}
+
 tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *target_dev, int32_t loss,
-                       double *out_dev) {
+                       double *out) {
     tgp_status st = check_eval_args(ctx, d, dom);
     if (st != TGP_OK) return st;
     if (loss != TGP_RMSE && loss != TGP_MSE) return fail(ctx, TGP_EINVAL, "loss must be TGP_RMSE or TGP_MSE");
     if (d->n_ind == 0) return TGP_OK;
-    if (!target_dev || !out_dev) return fail(ctx, TGP_EINVAL, "NULL target or output");
+    if (!target_dev || !out) return fail(ctx, TGP_EINVAL, "NULL target or output");
     HCHK(ctx, hipSetDevice(ctx->device));
+    const bool host_out = is_host_memory(out);
+    double *out_dev = out;
+    if (host_out) {
+        HCHK(ctx, ensure(ctx->fit_out, sizeof(double) * (size_t)d->n_ind));
+        out_dev = static_cast<double *>(ctx->fit_out.p);
+    }
     float *cache = nullptr;
     st = plan_and_fill(ctx, d, dom, &cache);
     if (st != TGP_OK) return st;
@@ -1668,6 +1685,11 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
     HCHK(ctx, launch_finalize(a.job.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.job.n_stripes,
                               (double)d->n_ch * (double)dom->cases, loss, out_dev, ctx->stream));
     record(ctx, 5);
+    if (host_out) {
+        HCHK(ctx, hipMemcpyAsync(out, out_dev, sizeof(double) * (size_t)d->n_ind, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+        HCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     ctx->times.interp_items = (int64_t)a.n_progs * a.job.n_stripes;
     ctx->times.cases_per_lane = K;
     ctx->times.tiles_per_item = a.job.tiles_per_stripe;

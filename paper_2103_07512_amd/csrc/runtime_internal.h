@@ -37,6 +37,7 @@ struct tgp_ctx_s {
     int commute = 0;                     // hash-consing up to operand order of commuting operators
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
+    DevBuf fit_out;  // device copy of fitness values bound for host memory
     DevicePool pool;             // DAG, plan and population blocks
     void *pin = nullptr;         // pinned staging for uploads and readbacks
     size_t pin_cap = 0;

@@ -388,9 +388,19 @@ def evaluate(ctx: Context, dag: Dag, dom: Domain, out):
 
 
 def fitness(ctx: Context, dag: Dag, dom: Domain, target, loss: int, out):
-    """RMSE/MSE per individual into out (torch float64, [n_individuals])."""
+    """RMSE/MSE per individual into out ([n_individuals] float64): a device
+    torch tensor (queued, returns at once) or a host array, numpy or CPU
+    torch (the call blocks until the values are there)."""
+    if isinstance(out, np.ndarray):
+        if out.dtype != np.float64 or not out.flags.c_contiguous or not out.flags.writeable:
+            raise ValueError("out must be a writeable C-contiguous float64 array")
+        if out.size < dag.n_individuals:
+            raise ValueError("out is smaller than the number of individuals")
+        ptr = out.ctypes.data
+    else:
+        ptr = out.data_ptr()
     _check(lib().tgp_fitness(ctx.h, dag.h, dom.h, ctypes.c_void_p(target.data_ptr()), loss,
-                             ctypes.c_void_p(out.data_ptr())), ctx.h)
+                             ctypes.c_void_p(ptr)), ctx.h)
     return out
 
 

@@ -137,6 +137,30 @@ def test_mod_bitwise_fmod(env):
             assert np.array_equal(g[~nan].view(np.uint32), want[~nan].view(np.uint32)), (text, lo, hi)
 
 
+def test_fitness_into_host_memory(env):
+    """tgp_fitness writes to a device tensor (queued) or to host memory, a
+    numpy array, a pageable or a pinned CPU tensor (blocking): the same bits
+    each way, and the host forms hold them when the call returns."""
+    tgp, ctx, torch = env
+    pop = pg.ramped_half_and_half(37, 2, 6, 61, pg.F18, 2, 2)
+    dom = tgp.Domain(ctx, (96, 80))
+    dag = tgp.build_dag(ctx, pop)
+    rng = np.random.default_rng(5)
+    t = torch.from_numpy(rng.random((2, dom.cases), dtype=np.float32)).to("cuda:0")
+    dev = torch.empty(pop.n_individuals, dtype=torch.float64, device="cuda:0")
+    tgp.fitness(ctx, dag, dom, t, tgp.RMSE, dev)
+    want = dev.cpu().numpy()
+    host = np.full(pop.n_individuals, np.nan)
+    tgp.fitness(ctx, dag, dom, t, tgp.RMSE, host)  # no synchronisation of our own
+    assert np.array_equal(host.view(np.uint64), want.view(np.uint64))
+    for pinned in (False, True):
+        cpu = torch.full((pop.n_individuals,), float("nan"), dtype=torch.float64, pin_memory=pinned)
+        tgp.fitness(ctx, dag, dom, t, tgp.RMSE, cpu)
+        assert np.array_equal(cpu.numpy().view(np.uint64), want.view(np.uint64)), pinned
+    with pytest.raises(ValueError):
+        tgp.fitness(ctx, dag, dom, t, tgp.RMSE, np.zeros(pop.n_individuals, np.float32))
+
+
 def test_min_max_operand_order(env):
     """The planner evaluates the children of min and max in either order and
     emits the plain opcode for both (it treats them as commutative there).
