@@ -451,6 +451,64 @@ void tgp_dag_destroy(tgp_dag dag) {
 // ------------------------------------------------------------------ planner
 namespace {
 
+// Runs fn(t, barrier) on T host threads (the caller's thread is t = 0);
+// barrier() returns once all T threads have reached it.  A waiting thread
+// spins for a few microseconds first (the threads of one level usually
+// arrive close together), then yields its processor.
+template <class F>
+void run_team(int T, F &&fn) {
+    std::atomic<int> arrived{0}, generation{0};
+    auto barrier = [&]() {
+        const int g = generation.load(std::memory_order_acquire);
+        if (arrived.fetch_add(1, std::memory_order_acq_rel) + 1 == T) {
+            arrived.store(0, std::memory_order_relaxed);
+            generation.fetch_add(1, std::memory_order_acq_rel);
+        } else {
+            for (int i = 0; i < 20000 && generation.load(std::memory_order_acquire) == g; ++i)
+                __builtin_ia32_pause();
+            while (generation.load(std::memory_order_acquire) == g) std::this_thread::yield();
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back([&, t] { fn(t, barrier); });
+    fn(0, barrier);
+    for (auto &x : th) x.join();
+}
+
+// The nodes 0..U-1 ordered by height (id order within a height) on T
+// threads: order[first[h] .. first[h+1]) are the nodes of height h.
+void height_order(const int32_t *hgt, int64_t U, int T, std::vector<int32_t> &order,
+                  std::vector<int64_t> &first) {
+    std::vector<std::vector<int64_t>> hist(T);
+    int32_t H = 0;
+    order.resize(U);
+    run_team(T, [&](int t, auto &barrier) {
+        const int64_t b = U * t / T, e = U * (t + 1) / T;
+        std::vector<int64_t> &c = hist[t];
+        for (int64_t n = b; n < e; ++n) {
+            if ((size_t)hgt[n] >= c.size()) c.resize(hgt[n] + 1, 0);
+            ++c[hgt[n]];
+        }
+        barrier();
+        if (t == 0) {
+            for (int i = 0; i < T; ++i) H = std::max(H, (int32_t)hist[i].size() - 1);
+            first.assign(H + 2, 0);
+            int64_t at = 0;
+            for (int32_t h = 0; h <= H; ++h) {
+                first[h] = at;
+                for (int i = 0; i < T; ++i) {
+                    const int64_t k = (size_t)h < hist[i].size() ? hist[i][h] : 0;
+                    if ((size_t)h < hist[i].size()) hist[i][h] = at;
+                    at += k;
+                }
+            }
+            first[H + 1] = at;
+        }
+        barrier();
+        for (int64_t n = b; n < e; ++n) order[c[hgt[n]]++] = (int32_t)n;
+    });
+}
+
 struct Planner {
     const tgp_dag_s &d;
     int D;
@@ -467,6 +525,9 @@ struct Planner {
 
     Planner(const tgp_dag_s &dag, int stack, size_t slots) : d(dag), D(stack), budget_slots(slots) {}
 
+    // nodes by height (filled by the parallel preparation or decisions)
+    std::vector<int32_t> lorder;
+    std::vector<int64_t> lfirst;
     std::vector<uint8_t> folded;  // constant subtrees replaced by their value
     std::vector<float> fold_val;
     // Operator and arity of every node as the planner sees it (a folded node
@@ -504,23 +565,11 @@ struct Planner {
             b = U * t / T;
             e = U * (t + 1) / T;
         };
-        // barrier shared by the T threads of this call
-        std::atomic<int> arrived{0}, generation{0};
-        auto barrier = [&]() {
-            const int g = generation.load(std::memory_order_acquire);
-            if (arrived.fetch_add(1, std::memory_order_acq_rel) + 1 == T) {
-                arrived.store(0, std::memory_order_relaxed);
-                generation.fetch_add(1, std::memory_order_acq_rel);
-            } else {
-                while (generation.load(std::memory_order_acquire) == g) std::this_thread::yield();
-            }
-        };
+        if (lorder.size() != (size_t)U) height_order(hgt, U, T, lorder, lfirst);
+        const std::vector<int32_t> &order = lorder;
+        const std::vector<int64_t> &lvl_first = lfirst;
+        const int32_t H = (int32_t)lvl_first.size() - 2;
         std::vector<double> valu_part(T, 0.0);
-        std::vector<std::vector<int64_t>> hist(T);
-        std::vector<int64_t> lvl_first;
-        std::vector<int32_t> order(U);
-        int32_t H = 0;
-        std::vector<int32_t> hmax(T, 0);
         std::vector<std::vector<int32_t>> spill(T), cand(T);
         std::vector<int64_t> used_part(T, 0), slot_part(T + 1, 0);
         std::atomic<int64_t> used{0};
@@ -533,46 +582,19 @@ struct Planner {
         auto mark = [&](int32_t c) {  // returns whether c was not cached before
             return __atomic_exchange_n(&cached[c], (uint8_t)1, __ATOMIC_RELAXED) == 0;
         };
-        auto work = [&](int t) {
+        run_team(T, [&](int t, auto &barrier) {
             int64_t b, e;
             range(t, b, e);
-            // operators, arities, cost-model work; node heights
+            // operators, arities, cost-model work
             double v = 0;
-            int32_t hm = 0;
             for (int64_t n = b; n < e; ++n) {
                 const int o = d.op[n] & 0xff;
                 v += kOpCost[o];
                 const int x = any_folded && folded[n] ? TGP_CONST : o;
                 opv[n] = (uint8_t)x;
                 arv[n] = (uint8_t)kArity[x];
-                hm = std::max(hm, hgt[n]);
             }
             valu_part[t] = v;
-            hmax[t] = hm;
-            barrier();
-            if (t == 0) {
-                for (int i = 0; i < T; ++i) H = std::max(H, hmax[i]);
-                lvl_first.assign(H + 2, 0);
-            }
-            barrier();
-            // nodes ordered by height, in id order within a height
-            hist[t].assign(H + 1, 0);
-            for (int64_t n = b; n < e; ++n) ++hist[t][hgt[n]];
-            barrier();
-            if (t == 0) {
-                int64_t at = 0;
-                for (int32_t h = 0; h <= H; ++h) {
-                    lvl_first[h] = at;
-                    for (int i = 0; i < T; ++i) {
-                        const int64_t c = hist[i][h];
-                        hist[i][h] = at;
-                        at += c;
-                    }
-                }
-                lvl_first[H + 1] = at;
-            }
-            barrier();
-            for (int64_t n = b; n < e; ++n) order[hist[t][hgt[n]]++] = (int32_t)n;
             barrier();
             // cost, bottom-up
             for (int32_t h = 0; h <= H; ++h) {
@@ -741,11 +763,7 @@ struct Planner {
             int32_t ns = (int32_t)slot_part[t];
             for (int64_t n = b; n < e; ++n)
                 if (cached[n]) slot[n] = ns++;
-        };
-        std::vector<std::thread> th;
-        for (int t = 1; t < T; ++t) th.emplace_back(work, t);
-        work(0);
-        for (auto &x : th) x.join();
+        });
         valu_dag = 0;
         for (double v : valu_part) valu_dag += v;
         return result;
@@ -1023,7 +1041,7 @@ struct PlanJob {
         : d(dag), cases(n_cases), pl(*dag, D, budget) {}
 };
 
-static void plan_prepare(PlanJob &w, bool fold) {
+static void plan_prepare(PlanJob &w, bool fold, int threads = 1) {
     tgp_dag d = w.d;
     Plan &P = d->plan;
     const int64_t U = d->stats.dag_nodes, R = d->stats.n_roots;
@@ -1066,11 +1084,61 @@ static void plan_prepare(PlanJob &w, bool fold) {
             ++n_use;
         }
     };
+    const int32_t *kid = d->kid.data();
+    const int32_t *height = d->height.data();
+    const int T = (int)std::min<unsigned>((unsigned)std::max(threads, 1), std::max(1u, std::thread::hardware_concurrency()));
+    if (U >= kParallelDecideNodes && T > 1) {
+        // level by level on T threads; the height order is kept for the
+        // parallel decisions
+        std::vector<int32_t> &order = w.pl.lorder;
+        std::vector<int64_t> &first = w.pl.lfirst;
+        height_order(height, U, T, order, first);
+        const int32_t H = (int32_t)first.size() - 2;
+        std::atomic<int64_t> marked{0};
+        run_team(T, [&](int t, auto &barrier) {
+            int64_t m = 0;
+            for (int32_t h = 0; h <= H; ++h) {
+                const int64_t n0 = first[h], n1 = first[h + 1];
+                for (int64_t i = n0 + (n1 - n0) * t / T; i < n0 + (n1 - n0) * (t + 1) / T; ++i) {
+                    const int32_t n = order[i];
+                    const int o = d->op[n] & 0xff;
+                    const int a = kArity[o];
+                    bool nv = o != TGP_VAR;
+                    for (int j = 0; j < a; ++j) nv = nv && novar[kid[3 * (int64_t)n + j]];
+                    if (nv) {
+                        novar[n] = a > 0 ? 2 : 1;
+                    } else {
+                        for (int j = 0; j < a; ++j) {
+                            const int32_t c = kid[3 * (int64_t)n + j];
+                            if (novar[c] == 2) {
+                                __atomic_store_n(&use[c], (uint8_t)1, __ATOMIC_RELAXED);
+                                ++m;
+                            }
+                        }
+                    }
+                }
+                barrier();
+            }
+            marked.fetch_add(m);
+        });
+        n_use = marked.load();
+        for (int32_t r : d->roots) mark(r);
+        if (n_use == 0) return;
+        w.fold_first.assign(1, 0);
+        for (int32_t h = 0; h <= H; ++h) {
+            for (int64_t i = first[h]; i < first[h + 1]; ++i)
+                if (novar[order[i]] == 2) w.fold_list.push_back(order[i]);
+            w.fold_first.push_back((int32_t)w.fold_list.size());
+        }
+        // up to the highest variable-free operator node
+        while (w.fold_first.size() > 1 && w.fold_first[w.fold_first.size() - 2] == w.fold_first.back())
+            w.fold_first.pop_back();
+        w.pl.folded.swap(use);
+        return;
+    }
     // the variable-free operator nodes by height (constant leaves are read
     // from the node values by the fold kernel)
     std::vector<std::vector<int32_t>> by_h;
-    const int32_t *kid = d->kid.data();
-    const int32_t *height = d->height.data();
     for (int64_t n = 0; n < U; ++n) {  // children have smaller ids
         const int o = d->op[n] & 0xff;
         const int a = kArity[o];
@@ -1416,7 +1484,7 @@ tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases, const std::function
     P.cases = -1;
     const int D = ctx_stack_slots(ctx);
     PlanJob w(d, cases, D, budget_slots(ctx, cases));
-    plan_prepare(w, ctx->fold != 0);
+    plan_prepare(w, ctx->fold != 0, 8);
     const double tf0 = now_ms();
     tgp_status st = fold_run(ctx, {&w});
     if (st != TGP_OK) return st;

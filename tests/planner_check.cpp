@@ -13,6 +13,9 @@
 //     permuted opcodes included);
 //   - with the same number of stack spills the two decision passes cache
 //     the same nodes at the same levels;
+//   - the sequential and level-parallel preparations mark the same
+//     variable-free subtrees for folding and list the same operator nodes
+//     by height;
 //   - a cache budget too small for the spills gives TGP_ENOMEM.
 #include "runtime.cpp"
 
@@ -297,6 +300,17 @@ int main() {
                 CHECK(plan_decide_emit(small, c.D, true, c.access, 0, threads) == TGP_ENOMEM,
                       "%s: budget below the spills accepted\n", what);
             }
+        }
+        {  // folding preparation, sequential and level-parallel
+            PlanJob a(&d, 4096, c.D, (size_t)1 << 24), b(&d, 4096, c.D, (size_t)1 << 24);
+            plan_prepare(a, true, 1);
+            plan_prepare(b, true, 8);
+            CHECK(a.pl.folded == b.pl.folded && a.fold_first == b.fold_first && a.fold_list == b.fold_list,
+                  "U=%lld: folding preparation differs between 1 and 8 threads\n", (long long)U);
+            int64_t n_fold = 0;
+            for (uint8_t f : a.pl.folded) n_fold += f;
+            printf("U=%lld: %lld folded subtrees, %zu variable-free operator nodes\n", (long long)U,
+                   (long long)n_fold, a.fold_list.size());
         }
         if (spills[0] == spills[1])
             CHECK(cached[0] == cached[1] && level[0] == level[1],
