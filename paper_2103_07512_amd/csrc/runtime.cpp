@@ -23,6 +23,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -571,7 +572,7 @@ struct Planner {
         const int32_t H = (int32_t)lvl_first.size() - 2;
         std::vector<double> valu_part(T, 0.0);
         std::vector<std::vector<int32_t>> spill(T), cand(T);
-        std::vector<int64_t> used_part(T, 0), slot_part(T + 1, 0);
+        std::vector<int64_t> slot_part(T + 1, 0);
         std::atomic<int64_t> used{0};
         tgp_status result = TGP_OK;
         auto level_nodes = [&](int32_t h, int t, int64_t &b, int64_t &e) {
