@@ -137,6 +137,35 @@ def test_mod_bitwise_fmod(env):
             assert np.array_equal(g[~nan].view(np.uint32), want[~nan].view(np.uint32)), (text, lo, hi)
 
 
+def test_reduction_large_and_small_terms(env):
+    """The error reduction keeps small squared errors that sit among large
+    ones: every 4096th case has (v - t)^2 near 1e8 and every other one near
+    1e-2, so FP32 accumulation in case order drops the small terms (each is
+    below half an ulp of the running sum).  The device's compensated FP32
+    sums with an FP64 final step must match the exact sum of the same FP32
+    squares (math.fsum) to 1e-10; plain FP32 summation of each 4096-case
+    stretch is checked here to miss by far more."""
+    import math
+    tgp, ctx, torch = env
+    n = 1 << 20
+    dom = tgp.Domain(ctx, (n,))
+    v = oracle.coords(n)  # the values of the tree "x"
+    e = np.full(n, 0.1, np.float32)
+    e[::4096] = 1.0e4
+    t = (v - e).astype(np.float32)
+    d = (v - t).astype(np.float32)
+    sq = (d * d).astype(np.float32)  # the FP32 squares the device forms
+    exact = math.fsum(sq.astype(np.float64).tolist()) / n
+    naive = sum(float(np.add.accumulate(c, dtype=np.float32)[-1]) for c in sq.reshape(-1, 4096)) / n
+    assert abs(naive - exact) / exact > 1e-7
+    pop = pg.population_from_texts(["x", "x"])
+    dag = tgp.build_dag(ctx, pop)
+    out = torch.empty(2, dtype=torch.float64, device="cuda:0")
+    tgp.fitness(ctx, dag, dom, torch.from_numpy(t).to("cuda:0").reshape(1, n), tgp.MSE, out)
+    got = out.cpu().numpy()
+    assert np.all(np.abs(got - exact) / exact < 1e-10), (got, exact)
+
+
 def test_fitness_into_host_memory(env):
     """tgp_fitness writes to a device tensor (queued) or to host memory, a
     numpy array, a pageable or a pinned CPU tensor (blocking): the same bits
