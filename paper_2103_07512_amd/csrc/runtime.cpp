@@ -452,6 +452,13 @@ void tgp_dag_destroy(tgp_dag dag) {
 // ------------------------------------------------------------------ planner
 namespace {
 
+// A spin-wait hint to the host processor.
+inline void cpu_relax() {
+#if defined(__x86_64__) || defined(__i386__)
+    __builtin_ia32_pause();
+#endif
+}
+
 // Runs fn(t, barrier) on T host threads (the caller's thread is t = 0);
 // barrier() returns once all T threads have reached it.  A waiting thread
 // spins for a few microseconds first (the threads of one level usually
@@ -466,7 +473,7 @@ void run_team(int T, F &&fn) {
             generation.fetch_add(1, std::memory_order_acq_rel);
         } else {
             for (int i = 0; i < 20000 && generation.load(std::memory_order_acquire) == g; ++i)
-                __builtin_ia32_pause();
+                cpu_relax();
             while (generation.load(std::memory_order_acquire) == g) std::this_thread::yield();
         }
     };
