@@ -264,9 +264,31 @@ __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, 
                               const int32_t *canon, int32_t *table, uint64_t mask,
                               uint32_t hash_bits, bool commute) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t t = list[i];
-    const Key k = key_of(t, tok, kid, canon, commute);
+    const bool live = i < n;
+    int32_t t = live ? list[i] : -1;
+    const Key k = live ? key_of(t, tok, kid, canon, commute) : Key{0xffffffffu, 0, 0, 0};
+    // Leaves (x, y, z and the constants) repeat many times within one wave:
+    // lanes holding the same leaf key (its first two words) insert once,
+    // through the group's lowest lane, with the group's smallest token index.
+    // Every lane of the wave takes part in the ballots and shuffles.
+    const uint32_t op = k.k0 & 0xffu;
+    const bool leaf = live && (op == TGP_VAR || op == TGP_CONST);
+    bool insert = live && !leaf;
+    const int lane = (int)(threadIdx.x & 63u);
+    uint64_t todo = __ballot(leaf);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t l0 = __shfl(k.k0, leader), l1 = __shfl(k.k1, leader);
+        const uint64_t same = __ballot(leaf && k.k0 == l0 && k.k1 == l1) & todo;
+        int32_t m = ((same >> lane) & 1u) ? t : INT32_MAX;
+        for (int d = 32; d > 0; d >>= 1) m = min(m, __shfl_xor(m, d));
+        if (lane == leader) {
+            t = m;
+            insert = true;
+        }
+        todo &= ~same;
+    }
+    if (!insert) return;
     uint64_t s = key_hash(k, hash_bits) & mask;
     for (;;) {
         int32_t e = table[s];
@@ -275,7 +297,12 @@ __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, 
             if (e < 0) return;  // claimed an empty slot
         }
         if (key_eq(key_of(e, tok, kid, canon, commute), k)) {
-            atomicMin(&table[s], t);
+            // A slot's value only decreases and its key never changes, so a
+            // token that is not below the value it read (which may be stale,
+            // never lower than the current one) cannot lower it.  Skipping
+            // those leaves the atomics to the few tokens that can: without
+            // this, every leaf x or y of the level updated one address.
+            if (t < e) atomicMin(&table[s], t);
             return;
         }
         s = (s + 1) & mask;
@@ -382,19 +409,38 @@ __global__ void k_emit_nodes(const uint2 *tok, const int32_t *canon, const int32
 }
 
 // 3b. Children ids, in-degrees and multiplicities.
-__global__ void k_emit_edges(const int32_t *canon, const int32_t *pos, const int32_t *kid, int64_t T,
-                             int32_t *node_kid, int32_t *indeg, int32_t *mult) {
+// counter[id] += 1 for every active lane of the wave: lanes with equal ids
+// add once, by their lowest lane, with their count.  The shared leaves (x, y
+// and common constants) are counted by many tokens of every wave; one
+// atomic per lane would serialise on their few addresses.  The loop runs once
+// per distinct id among the active lanes (wave-uniform, by ballots).
+__device__ __forceinline__ void add_one_per_lane(int32_t *counter, int32_t id) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint64_t todo = __ballot(id >= 0);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lid = __shfl(id, leader);
+        const uint64_t same = __ballot(id == lid) & todo;
+        if (lane == leader) atomicAdd(&counter[lid], (int32_t)__popcll(same));
+        todo &= ~same;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit_edges(const int32_t *canon, const int32_t *pos,
+                                                    const int32_t *kid, int64_t T, int32_t *node_kid,
+                                                    int32_t *indeg, int32_t *mult) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    const int32_t c = canon[t];
-    const int32_t id = pos[c];
-    atomicAdd(&mult[id], 1);
-    if (c != (int32_t)t) return;
+    // every lane reaches the wave-wide ballots; lanes past T take part with
+    // id -1 (nothing to count)
+    const int32_t c = t < T ? canon[t] : -1;
+    const int32_t id = c >= 0 ? pos[c] : -1;
+    add_one_per_lane(mult, id);
+    const bool rep = c == (int32_t)t && t < T;  // the token that represents node id
     for (int j = 0; j < 3; ++j) {
-        const int32_t k = kid[3 * t + j];
+        const int32_t k = rep ? kid[3 * t + j] : -1;
         const int32_t kid_id = k < 0 ? -1 : pos[canon[k]];
-        node_kid[3 * id + j] = kid_id;
-        if (kid_id >= 0) atomicAdd(&indeg[kid_id], 1);
+        if (rep) node_kid[3 * id + j] = kid_id;
+        add_one_per_lane(indeg, kid_id);
     }
 }
 
