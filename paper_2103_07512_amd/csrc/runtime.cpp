@@ -1020,8 +1020,10 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
 }  // namespace
 
 // ------------------------------------------------------------------ planning
-// DAGs of at least this many nodes are planned level-parallel on host threads.
+// DAGs of at least this many nodes are planned level-parallel on host threads,
+// at most kPlanThreads of them (fewer when the host has fewer processors).
 constexpr int64_t kParallelDecideNodes = 1 << 15;
+constexpr int kPlanThreads = 16;
 
 //
 // Planning one DAG runs in phases so that a batch of many DAGs can run each
@@ -1492,12 +1494,12 @@ tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases, const std::function
     P.cases = -1;
     const int D = ctx_stack_slots(ctx);
     PlanJob w(d, cases, D, budget_slots(ctx, cases));
-    plan_prepare(w, ctx->fold != 0, 8);
+    plan_prepare(w, ctx->fold != 0, kPlanThreads);
     const double tf0 = now_ms();
     tgp_status st = fold_run(ctx, {&w});
     if (st != TGP_OK) return st;
     ctx->times.plan_fold_ms = now_ms() - tf0;
-    st = plan_decide_emit_fill(w, D, ctx->reorder != 0, ctx->cache_access_cost, ctx->fold, 8);
+    st = plan_decide_emit_fill(w, D, ctx->reorder != 0, ctx->cache_access_cost, ctx->fold, kPlanThreads);
     if (st != TGP_OK) return fail(ctx, st, "%s", w.err.c_str());
     if (ctx->plan_upload) {
         // the fill goes to the device (and, through after_fill, to work)
@@ -1506,7 +1508,7 @@ tgp_status build_plan(tgp_ctx ctx, tgp_dag d, int64_t cases, const std::function
         if (st == TGP_OK && after_fill) st = after_fill();
         if (st != TGP_OK) return st;
     }
-    plan_emit_roots(w, 8);
+    plan_emit_roots(w, kPlanThreads);
     ctx->times.plan_decide_ms = w.t_decide;
     ctx->times.plan_emit_ms = w.t_emit;
     if (ctx->plan_upload) {
