@@ -409,39 +409,84 @@ __global__ void k_emit_nodes(const uint2 *tok, const int32_t *canon, const int32
 }
 
 // 3b. Children ids, in-degrees and multiplicities.
-// counter[id] += 1 for every active lane of the wave: lanes with equal ids
-// add once, by their lowest lane, with their count.  The shared leaves (x, y
-// and common constants) are counted by many tokens of every wave; one
-// atomic per lane would serialise on their few addresses.  The loop runs once
-// per distinct id among the active lanes (wave-uniform, by ballots).
-__device__ __forceinline__ void add_one_per_lane(int32_t *counter, int32_t id) {
+// Block-level counts: an open-addressing table in LDS of (id, count), filled
+// with LDS atomics and flushed to the device counters with one atomic per
+// distinct id of the block.  An id that finds no free entry within a few
+// probes goes straight to its device counter.
+constexpr int kCountSlots = 2048;
+struct BlockCounts {
+    int32_t id[kCountSlots];
+    int32_t n[kCountSlots];
+};
+
+__device__ __forceinline__ void block_counts_clear(BlockCounts &c) {
+    for (int e = threadIdx.x; e < kCountSlots; e += blockDim.x) {
+        c.id[e] = -1;
+        c.n[e] = 0;
+    }
+}
+
+__device__ __forceinline__ void block_counts_add(BlockCounts &c, int32_t *counter, int32_t id, int32_t k) {
+    uint32_t h = ((uint32_t)id * 2654435761u) & (kCountSlots - 1);
+    for (int probe = 0; probe < 8; ++probe) {
+        const int32_t prev = atomicCAS(&c.id[h], -1, id);
+        if (prev == -1 || prev == id) {
+            atomicAdd(&c.n[h], k);
+            return;
+        }
+        h = (h + 1) & (kCountSlots - 1);
+    }
+    atomicAdd(&counter[id], k);
+}
+
+__device__ __forceinline__ void block_counts_flush(const BlockCounts &c, int32_t *counter) {
+    for (int e = threadIdx.x; e < kCountSlots; e += blockDim.x)
+        if (c.id[e] >= 0) atomicAdd(&counter[c.id[e]], c.n[e]);
+}
+
+// Adds 1 for every lane whose id >= 0: lanes of a wave with equal ids are
+// grouped by ballots (the loop runs once per distinct id, wave-uniform) and
+// add their count through the group's lowest lane into the block's table.
+// The shared leaves (x, y and common constants) are counted by many tokens
+// of every wave; one device atomic per lane serialised on their few
+// addresses.
+__device__ __forceinline__ void add_one_per_lane(BlockCounts &c, int32_t *counter, int32_t id) {
     const int lane = (int)(threadIdx.x & 63u);
     uint64_t todo = __ballot(id >= 0);
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const int32_t lid = __shfl(id, leader);
         const uint64_t same = __ballot(id == lid) & todo;
-        if (lane == leader) atomicAdd(&counter[lid], (int32_t)__popcll(same));
+        if (lane == leader) block_counts_add(c, counter, lid, (int32_t)__popcll(same));
         todo &= ~same;
     }
 }
 
-__global__ __launch_bounds__(256) void k_emit_edges(const int32_t *canon, const int32_t *pos,
-                                                    const int32_t *kid, int64_t T, int32_t *node_kid,
-                                                    int32_t *indeg, int32_t *mult) {
+constexpr int kEmitBlock = 1024;
+
+__global__ __launch_bounds__(kEmitBlock) void k_emit_edges(const int32_t *canon, const int32_t *pos,
+                                                           const int32_t *kid, int64_t T, int32_t *node_kid,
+                                                           int32_t *indeg, int32_t *mult) {
+    __shared__ BlockCounts cm, ci;
+    block_counts_clear(cm);
+    block_counts_clear(ci);
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // every lane reaches the wave-wide ballots; lanes past T take part with
-    // id -1 (nothing to count)
+    // every lane reaches the ballots and barriers; lanes past T take part
+    // with id -1 (nothing to count)
     const int32_t c = t < T ? canon[t] : -1;
     const int32_t id = c >= 0 ? pos[c] : -1;
-    add_one_per_lane(mult, id);
+    add_one_per_lane(cm, mult, id);
     const bool rep = c == (int32_t)t && t < T;  // the token that represents node id
     for (int j = 0; j < 3; ++j) {
         const int32_t k = rep ? kid[3 * t + j] : -1;
         const int32_t kid_id = k < 0 ? -1 : pos[canon[k]];
         if (rep) node_kid[3 * id + j] = kid_id;
-        add_one_per_lane(indeg, kid_id);
+        add_one_per_lane(ci, indeg, kid_id);
     }
+    __syncthreads();
+    block_counts_flush(cm, mult);
+    block_counts_flush(ci, indeg);
 }
 
 __global__ void k_emit_roots(const int32_t *root_tok, const int32_t *canon, const int32_t *pos,
@@ -581,7 +626,7 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
         DCHK(hipMemsetAsync(dev->mult, 0, sizeof(int32_t) * 2 * U, s));
         hipLaunchKernelGGL(k_emit_nodes, grid_for(T), dim3(256), 0, s, tok, canon, pos, height, T,
                            dev->node_op, dev->node_value, dev->node_height);
-        hipLaunchKernelGGL(k_emit_edges, grid_for(T), dim3(256), 0, s, canon, pos, kid, T,
+        hipLaunchKernelGGL(k_emit_edges, grid_for(T, kEmitBlock), dim3(kEmitBlock), 0, s, canon, pos, kid, T,
                            dev->node_kid, dev->indeg, dev->mult);
         hipLaunchKernelGGL(k_emit_roots, grid_for(R), dim3(256), 0, s, root_tok, canon, pos, R,
                            dev->roots);
