@@ -19,7 +19,6 @@ namespace tgp {
 
 namespace {
 
-__constant__ int c_arity_b[TGP_NUM_OPS] = {TGP_ARITY_LIST};
 
 // SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator:
 // output n of the generator started from `seed`.
@@ -88,7 +87,7 @@ __device__ int32_t random_tree(Draws &dr, int depth, bool full, const BreedArgs 
             }
         }
         if (!leaf) {
-            st_left[sp] = (uint8_t)c_arity_b[st_op[sp]];
+            st_left[sp] = (uint8_t)arity_of(st_op[sp]);
             ++sp;
             continue;
         }
@@ -136,7 +135,7 @@ __device__ int shape_global(const uint2 *tok, int64_t o0, int64_t o1, int32_t *s
         if (op >= TGP_NUM_OPS) return 2;
         int32_t s = 1, h = 0;
         int64_t c = i - 1;
-        for (int j = 0; j < c_arity_b[op]; ++j) {
+        for (int j = 0; j < arity_of(op); ++j) {
             if (c < o0) return 1;
             s += size[c];
             h = max(h, height[c] + 1);
@@ -150,7 +149,7 @@ __device__ int shape_global(const uint2 *tok, int64_t o0, int64_t o1, int32_t *s
     for (int64_t i = o1 - 1; i >= o0; --i) {
         const int32_t d = depth[i] + 1;
         int64_t c = i - 1;
-        for (int j = 0; j < c_arity_b[tok_op(tok[i])]; ++j) {
+        for (int j = 0; j < arity_of(tok_op(tok[i])); ++j) {
             depth[c] = d;
             c -= size[c];
         }
@@ -187,7 +186,7 @@ __global__ __launch_bounds__(64) void k_shape(const uint2 *tok, const int64_t *o
             verdict = 2;
             return false;
         }
-        const int a = c_arity_b[op];
+        const int a = arity_of(op);
         if (sp < a) {
             verdict = 1;
             return false;
@@ -223,7 +222,7 @@ __global__ __launch_bounds__(64) void k_shape(const uint2 *tok, const int64_t *o
     // backward: frames (depth of the children, children still to come)
     sp = 0;
     for_tokens<8, true>(tok, o0, o1, [&](int64_t i, uint2 w) {
-        const int a = c_arity_b[tok_op(w)];
+        const int a = arity_of(tok_op(w));
         int32_t d = 0;
         if (sp > 0) {
             int2 &f = stk[sp - 1][lane];

@@ -27,7 +27,6 @@
 
 namespace tgp {
 
-__constant__ int8_t c_arity[TGP_NUM_OPS] = {TGP_ARITY_LIST};
 
 struct BuildStatus {
     unsigned long long first_error;  // (tree << 4) | code, min over trees; ~0 = none
@@ -65,7 +64,7 @@ __device__ __forceinline__ bool structure_scan(const uint2 *tok, int64_t o0, int
             verdict = 1;
             return false;
         }
-        const int a = c_arity[op];
+        const int a = arity_of(op);
         if (sp < a) {
             report(st, r, ERR_PARSE);
             verdict = 1;
@@ -228,7 +227,7 @@ __device__ __forceinline__ Key key_of(int32_t t, const uint2 *tok, const int32_t
     } else if (op == TGP_CONST) {
         k.k1 = w.y;
     } else {
-        const int a = c_arity[op];
+        const int a = arity_of(op);
         k.k1 = (uint32_t)canon[kid[3 * t + 0]];
         if (a > 1) k.k2 = (uint32_t)canon[kid[3 * t + 1]];
         if (a > 2) k.k3 = (uint32_t)canon[kid[3 * t + 2]];

@@ -31,6 +31,20 @@ constexpr int kArityList[] = {TGP_ARITY_LIST};
 static_assert(sizeof(kArityList) / sizeof(int) == TGP_NUM_OPS, "one arity per opcode");
 constexpr int kArity[TGP_NUM_OPS] = {TGP_ARITY_LIST};
 
+// The same arities packed two bits per opcode into one 64-bit constant, so
+// that device code looks an arity up with a shift instead of a memory load
+// (a per-lane load from a constant table is a vector memory load, and its
+// wait also waits for every vector load issued before it).
+constexpr uint64_t pack_arities() {
+    uint64_t r = 0;
+    for (int i = 0; i < TGP_NUM_OPS; ++i) r |= (uint64_t)kArityList[i] << (2 * i);
+    return r;
+}
+constexpr uint64_t kArityPacked = pack_arities();
+static_assert(TGP_NUM_OPS <= 32, "two bits per opcode in 64 bits");
+// Arity of a valid opcode (op < TGP_NUM_OPS).
+__host__ __device__ constexpr int arity_of(uint32_t op) { return (int)((kArityPacked >> (2 * op)) & 3u); }
+
 // Interpreter instruction codes.  An instruction is a uint2: .x = code, .y =
 // the FP32 bits of a constant (I_CONST) or the cache row (I_CACHE: the row
 // starts cache_stride floats times .y past the job's cache base).  Function
@@ -168,26 +182,42 @@ hipError_t launch_finalize_batch(const FinJob *jobs, const int32_t *n_jobs, cons
 // down to lo), reading them N at a time with the next N in flight, until f
 // returns false; returns whether every token was visited.  Per-tree scans
 // (one thread per tree) use it so that each token's load does not stall the
-// scan's dependent steps.
+// scan's dependent steps.  Two buffers alternate (a copy from the in-flight
+// buffer would wait for it), and every load is unconditional, at an index
+// clamped into [lo, hi) (a branch around each load hides from the compiler
+// which loads are outstanding, and it then waits for all of them).
 template <int N, bool REV, typename F>
 __device__ __forceinline__ bool for_tokens(const uint2 *tok, int64_t lo, int64_t hi, F &&f) {
-    uint2 cur[N], nxt[N];
+    if (hi <= lo) return true;
+    uint2 a[N], b[N];
     auto at = [&](int64_t base, int j) { return REV ? base - j : base + j; };
     auto ok = [&](int64_t i) { return i >= lo && i < hi; };
-    const int64_t first = REV ? hi - 1 : lo;
+    auto load = [&](uint2 (&buf)[N], int64_t base) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) cur[j] = ok(at(first, j)) ? tok[at(first, j)] : uint2{0u, 0u};
-    for (int64_t base = first; ok(base); base = at(base, N)) {
-        const int64_t nb = at(base, N);
-#pragma unroll
-        for (int j = 0; j < N; ++j) nxt[j] = ok(at(nb, j)) ? tok[at(nb, j)] : uint2{0u, 0u};
+        for (int j = 0; j < N; ++j) {
+            const int64_t i = at(base, j);
+            buf[j] = tok[i < lo ? lo : (i >= hi ? hi - 1 : i)];
+        }
+    };
+    auto run = [&](const uint2 (&buf)[N], int64_t base) {
 #pragma unroll
         for (int j = 0; j < N; ++j)
-            if (ok(at(base, j)) && !f(at(base, j), cur[j])) return false;
-#pragma unroll
-        for (int j = 0; j < N; ++j) cur[j] = nxt[j];
+            if (ok(at(base, j)) && !f(at(base, j), buf[j])) return false;
+        return true;
+    };
+    int64_t base = REV ? hi - 1 : lo;
+    load(a, base);
+    for (;;) {
+        const int64_t nb = at(base, N);
+        load(b, nb);
+        if (!run(a, base)) return false;
+        if (!ok(nb)) return true;
+        const int64_t nb2 = at(nb, N);
+        load(a, nb2);
+        if (!run(b, nb)) return false;
+        if (!ok(nb2)) return true;
+        base = nb2;
     }
-    return true;
 }
 #endif
 
