@@ -412,7 +412,7 @@ __global__ void k_emit_nodes(const uint2 *tok, const int32_t *canon, const int32
 // with LDS atomics and flushed to the device counters with one atomic per
 // distinct id of the block.  An id that finds no free entry within a few
 // probes goes straight to its device counter.
-constexpr int kCountSlots = 2048;
+constexpr int kCountSlots = 1024;  // at most 256 + 768 distinct ids per block of 256
 struct BlockCounts {
     int32_t id[kCountSlots];
     int32_t n[kCountSlots];
@@ -461,7 +461,10 @@ __device__ __forceinline__ void add_one_per_lane(BlockCounts &c, int32_t *counte
     }
 }
 
-constexpr int kEmitBlock = 1024;
+// Blocks of four waves: a block of many waves waits for that many free wave
+// slots on one compute unit, which it rarely finds while a long evaluation
+// kernel runs beside it (DAGs are built on side streams when serving).
+constexpr int kEmitBlock = 256;
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit_edges(const int32_t *canon, const int32_t *pos,
                                                            const int32_t *kid, int64_t T, int32_t *node_kid,
