@@ -74,3 +74,14 @@ def test_library_built_for_gfx950_only():
     assert b"amdgcn-amd-amdhsa--gfx950" in data
     for other in (b"gfx942", b"gfx90a", b"gfx908", b"gfx1100"):
         assert other not in data
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/tgp.h is a C header: it compiles as strict C99 (no C++ or HIP
+    types cross the boundary)."""
+    src = tmp_path / "abi.c"
+    src.write_text('#include "tgp.h"\nint main(void) { tgp_ctx c = 0; (void)c; return 0; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "abi.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
