@@ -15,8 +15,10 @@
 //     reduction (fitness) or with a store of their values (evaluate).
 #include <hip/hip_runtime.h>
 
+#include <sched.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -452,6 +454,30 @@ void tgp_dag_destroy(tgp_dag dag) {
 // ------------------------------------------------------------------ planner
 namespace {
 
+// Processors this process may use: its affinity mask (the machine's count
+// when the mask cannot be read), capped by a CPU quota of its control group
+// (cgroup v2 cpu.max, "quota period"), rounded up.  The planner's threads
+// wait for each other level by level, so more threads than processors would
+// only slow it down.
+unsigned usable_cpus() {
+    static const unsigned n = [] {
+        unsigned c = std::max(1u, std::thread::hardware_concurrency());
+        cpu_set_t set;
+        if (sched_getaffinity(0, sizeof set, &set) == 0) c = (unsigned)std::max(1, CPU_COUNT(&set));
+        if (FILE *f = fopen("/sys/fs/cgroup/cpu.max", "r")) {
+            char quota[32] = "";
+            long long period = 0;
+            if (fscanf(f, "%31s %lld", quota, &period) == 2 && strcmp(quota, "max") != 0 && period > 0) {
+                const long long q = atoll(quota);
+                if (q > 0) c = std::min<unsigned>(c, (unsigned)std::max(1LL, (q + period - 1) / period));
+            }
+            fclose(f);
+        }
+        return c;
+    }();
+    return n;
+}
+
 // A spin-wait hint to the host processor.
 inline void cpu_relax() {
 #if defined(__x86_64__) || defined(__i386__)
@@ -472,7 +498,7 @@ void run_team(int T, F &&fn) {
             arrived.store(0, std::memory_order_relaxed);
             generation.fetch_add(1, std::memory_order_acq_rel);
         } else {
-            for (int i = 0; i < 20000 && generation.load(std::memory_order_acquire) == g; ++i)
+            for (int i = 0; i < 2000 && generation.load(std::memory_order_acquire) == g; ++i)
                 cpu_relax();
             while (generation.load(std::memory_order_acquire) == g) std::this_thread::yield();
         }
@@ -994,7 +1020,7 @@ void emit_all(const Planner &pl, const std::vector<int32_t> &nodes, std::vector<
               std::vector<Emitted> &out, int threads) {
     const size_t n = nodes.size();
     out.assign(n, Emitted{0, 0, 0, 0.0, false, false});
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned hw = usable_cpus();
     const int T = n < 512 ? 1 : (int)std::min<unsigned>((unsigned)std::max(threads, 1), hw);
     std::vector<std::vector<uint2>> local(T);
     auto work = [&](int t) {
@@ -1096,7 +1122,7 @@ static void plan_prepare(PlanJob &w, bool fold, int threads = 1) {
     };
     const int32_t *kid = d->kid.data();
     const int32_t *height = d->height.data();
-    const int T = (int)std::min<unsigned>((unsigned)std::max(threads, 1), std::max(1u, std::thread::hardware_concurrency()));
+    const int T = (int)std::min<unsigned>((unsigned)std::max(threads, 1), usable_cpus());
     if (U >= kParallelDecideNodes && T > 1) {
         // level by level on T threads; the height order is kept for the
         // parallel decisions
@@ -1256,7 +1282,7 @@ static tgp_status plan_decide_emit_fill(PlanJob &w, int D, bool reorder, double 
     for (uint8_t f : pl.folded) P.n_folded += f;
     pl.reorder = reorder;
     pl.access_cost = access_cost;
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned hw = usable_cpus();
     const int dt = (int)std::min<unsigned>((unsigned)std::max(emit_threads, 1), hw);
     tgp_status st = U >= kParallelDecideNodes && dt > 1 ? pl.decide_parallel(w.rootrefs, w.err, dt)
                                                         : pl.decide(w.rootrefs, w.err);
@@ -1556,7 +1582,7 @@ tgp_status build_plans(tgp_ctx ctx, int32_t n, const tgp_dag *dags, const int64_
     std::stable_sort(jobs.begin(), jobs.end(), [](const std::unique_ptr<PlanJob> &a, const std::unique_ptr<PlanJob> &b) {
         return a->d->stats.dag_nodes > b->d->stats.dag_nodes;
     });
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned hw = usable_cpus();
     const int T = (int)std::min<size_t>(std::min<unsigned>(16, hw), jobs.size());
     auto parallel = [&](auto &&fn) {
         std::atomic<size_t> next{0};
