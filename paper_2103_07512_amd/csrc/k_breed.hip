@@ -19,7 +19,6 @@ namespace tgp {
 
 namespace {
 
-
 // SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator:
 // output n of the generator started from `seed`.
 __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t n) {

@@ -27,7 +27,6 @@
 
 namespace tgp {
 
-
 struct BuildStatus {
     unsigned long long first_error;  // (tree << 4) | code, min over trees; ~0 = none
     int32_t max_height;
