@@ -83,6 +83,15 @@ tgp_status fail(tgp_ctx ctx, tgp_status st, const char *fmt, ...) {
     return st;
 }
 
+// The device code looks arities up in a packed constant; it must agree with
+// the table for every opcode.
+constexpr bool packed_arities_match() {
+    for (int i = 0; i < TGP_NUM_OPS; ++i)
+        if (arity_of((uint32_t)i) != kArityList[i] || kArityList[i] > 3) return false;
+    return true;
+}
+static_assert(packed_arities_match(), "every arity fits two bits and unpacks to the table's value");
+
 // --------------------------------------------------------------- cost model
 // VALU instructions per case of each operator as this library compiles it
 // for gfx950, measured by opcost_probe.hip (SQ_INSTS_VALU of a one-operator
