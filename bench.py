@@ -34,6 +34,43 @@ METRIC = ("node-evals/s (DAG nodes × fitness cases / s) at 1024² domain; "
 # 32-bit lane operation per lane per clock (no packed-FP32 issue).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
+# Algorithmic cost of one operator application on one fitness case, in VALU
+# lane-operations: a fixed table that does not depend on how this library
+# compiles the operators (elementary add/sub/mul/min/max 1, abs 1, frac 1,
+# clip and if 2, sign 3, protected division 7, sqrt, sin, cos and exp 6, log
+# 7, pow 13, mod 12, terminals 0).  The operators outside the 18-operator
+# set count the same elementary steps their definitions use: neg 1, mdist
+# (add, halve) 2, step 2, tan (sin, cos, division) 19, sstep 4, sstepp 6, len
+# (two squares, a sum, sqrt) 9, lerp (difference, frac, product, sum) 4, the
+# bitwise operators (two conversions, the operation, one conversion) 4, warp
+# (two axis points of 6 and a gather) 14.
+ALG_COST = {
+    "var": 0, "const": 0, "add": 1, "sub": 1, "mult": 1, "div": 7, "sin": 6, "cos": 6, "tan": 19,
+    "exp": 6, "log": 7, "pow": 13, "min": 1, "max": 1, "mdist": 2, "neg": 1, "sqrt": 6, "sign": 3,
+    "abs": 1, "clip": 2, "mod": 12, "frac": 1, "if": 2, "step": 2, "sstep": 4, "sstepp": 6, "len": 9,
+    "lerp": 4, "or": 4, "xor": 4, "and": 4, "warp": 14,
+}
+
+
+def algorithmic_lane_ops(export):
+    """Per-case algorithmic lane-operations of a DAG: every function node
+    whose value depends on a variable, each once, at ALG_COST.  Subtrees
+    without variables have one value for all cases (the library folds them
+    once per call), so they add no per-case work."""
+    import numpy as np
+
+    from paper_2103_07512_amd import popgen as pg
+    op = export["nodes"]["op"].astype(np.int64)
+    kids = export["children"]
+    cost = np.array([ALG_COST[pg.OP_NAME[i]] for i in range(len(pg.OP_NAME))], np.float64)
+    dep = op == pg.VAR
+    # children precede their parents (first-occurrence order)
+    for n in np.nonzero(pg.ARITY[op] > 0)[0]:
+        k = kids[n]
+        dep[n] = dep[k[k >= 0]].any()
+    fn = pg.ARITY[op] > 0
+    return float(cost[op[fn & dep]].sum()), float(cost[op[fn]].sum())
+
 WORKLOADS = {
     "c3": "1000 individuals x 3 channel trees, ramped half-and-half depth 2-12, 18 operators, "
           "1024x1024 grid, MSE vs a 3-channel image from seeded depth-8 trees",
@@ -94,6 +131,10 @@ def cpu_baseline(pop, dom, dag_nodes, max_rows=64, budget_s=15.0):
 
 
 def bench_c4(args):
+    print(json.dumps(run_c4(args)), flush=True)
+
+
+def run_c4(args):
     """64 populations: batched (persistent kernels, replayed HIP graph, autotuned
     shape) against one plain tgp_fitness per population, DAG build included."""
     import numpy as np
@@ -178,7 +219,7 @@ def bench_c4(args):
                    "eval_only_batched_over_plain": eval_plain / eval_batch,
                    "autotune": tune, "batch": st, "max_rel_diff_batched_vs_plain": agree},
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def bench_evolve(args):
@@ -300,20 +341,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per fitness launch from the committed counter summary, when
-    it was taken on the kernel as it is now (else None)."""
-    path = os.path.join(ROOT, "profiles", "k_interp_c3_hbm_traffic.md")
+def recorded(profile, tag):
+    """A record line ('TAG {json}') of a committed counter summary, when the
+    counters were taken on the kernel as it is now (else None)."""
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     rec = None
     with open(path) as fh:
         for ln in fh:
-            if ln.startswith("TRAFFIC "):
-                rec = json.loads(ln[len("TRAFFIC "):])
+            if ln.startswith(tag + " "):
+                rec = json.loads(ln[len(tag) + 1:])
     if not rec or rec.get("kernel_source") != kernel_source_hash():
         return None
-    return {"bytes_per_launch": rec["bytes_per_launch"], "source": "profiles/k_interp_c3_hbm_traffic.md"}
+    rec["source"] = "profiles/" + profile
+    return rec
 
 
 def serve_c5(generations, loads, with_plain, warm_generations=2, log=None, configure=None):
@@ -414,12 +456,14 @@ def serve_c5(generations, loads, with_plain, warm_generations=2, log=None, confi
         srv.close()
         credited = sum(i["credited_node_evals"] for _, i in infos)
         lat = np.array([i["latency_ms"] for g, i in infos if g >= warm_generations])
+        counted = int(lat.size)
         ph = {"to_admission": [i["admit_ms"] - i["submit_ms"] for _, i in infos],
               "prep": [i["prep_ms"] for _, i in infos],
               "admitted_to_first_step": [i["start_ms"] - i["admit_ms"] for _, i in infos],
               "running": [i["done_ms"] - i["start_ms"] for _, i in infos]}
         phases = {k: {"mean_ms": float(np.mean(v)), "p50_ms": float(np.median(v))} for k, v in ph.items()}
-        return dict(wall_s=wall, node_evals_per_s=credited / wall, requests=len(infos), phases=phases,
+        return dict(wall_s=wall, node_evals_per_s=credited / wall, requests=len(infos),
+                    requests_counted=counted, phases=phases,
                     p50_ms=float(np.percentile(lat, 50)) if lat.size else None,
                     p99_ms=float(np.percentile(lat, 99)) if lat.size else None,
                     same_as_closed_loop=same[0], server=st, credited=credited)
@@ -500,7 +544,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="serving workload: skip the plain pass")
     ap.add_argument("--no-latency", action="store_true",
                     help="default workload: skip the short serving run that gives p50/p99 latency")
-    ap.add_argument("--latency-generations", type=int, default=6)
+    ap.add_argument("--latency-generations", type=int, default=22,
+                    help="default workload: generations per run of the serving leg (16 runs, the "
+                         "first 2 generations not counted: 320 requests counted per offered load)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default workload: skip the batched-vs-plain leg (64 populations)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -587,7 +635,12 @@ def main():
     credited = stats["dag_nodes"] * dom.cases
     value = credited / (ms / 1e3)
     interp_ms = float(np.mean([t["interp_ms"] for t in times]))
-    achieved = work["executed_valu_roots"] / (interp_ms / 1e3) / 1e12
+    fill_ms = float(np.mean([t["fill_ms"] for t in times]))
+    d_last = tgp.Dag(ctx, tok_dev, off_dev, pop.n_individuals, pop.n_channels)
+    per_case, per_case_all = algorithmic_lane_ops(d_last.export())
+    d_last.close()
+    alg = per_case * dom.cases  # every DAG node is evaluated over every case of the grid
+    achieved = alg / ((fill_ms + interp_ms) / 1e3) / 1e12
     line = {
         "metric": METRIC,
         "value": value,
@@ -606,9 +659,17 @@ def main():
                    "loss": "mse" if loss else "rmse", "tree_nodes": stats["tree_nodes"],
                    "dag_nodes": stats["dag_nodes"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_interp fitness launch (root programs fused with the reduction)",
-                     "kernel_ms": interp_ms},
+                     "unit": "T lane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_interp evaluation launches of a step: the cache-fill launches and "
+                               "the fused fitness launch (root programs with the error reduction)",
+                     "kernel_ms": fill_ms + interp_ms, "kernel_ms_fitness_launch": interp_ms,
+                     "kernel_ms_fill": fill_ms,
+                     "work": "algorithmic lane-ops = cases x sum over variable-dependent DAG function "
+                             "nodes of a fixed per-operator cost (bench.py ALG_COST); folded "
+                             "variable-free subtrees count 0",
+                     "algorithmic_lane_ops": alg,
+                     "frac_counting_folded_nodes": per_case_all * dom.cases / ((fill_ms + interp_ms) / 1e3)
+                     / 1e12 / VALU_PEAK_TOPS},
         "detail": {
             "phases_ms": {k: float(np.mean([t[k] for t in times]))
                           for k in ("build_dag_ms", "plan_ms", "plan_fold_ms", "plan_decide_ms", "plan_emit_ms", "fill_ms", "interp_ms", "finalize_ms")},
@@ -628,20 +689,40 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-    traffic = recorded_traffic()
+    traffic = recorded("k_interp_c3_hbm_traffic.md", "TRAFFIC")
     if traffic is not None:
         line["roofline"]["traffic"] = traffic["bytes_per_launch"]
         line["roofline"]["traffic_source"] = traffic["source"]
+    issue = recorded("k_interp_c3_valu.md", "VALU")
+    if issue is not None:
+        # issued VALU instructions of the fitness launch over what the SIMDs
+        # can issue in its time (counters), beside the algorithmic fraction
+        line["roofline"]["issued_valu_frac_fitness_launch"] = issue["issue_frac"]
+        line["roofline"]["issued_valu_source"] = issue["source"]
     if not args.no_latency:
-        res = serve_c5(args.latency_generations, [0.7], False)
-        lo = res["loaded"][0]
+        loads = [float(x) for x in args.loads.split(",") if x.strip()]
+        res = serve_c5(args.latency_generations, loads, False)
         line["latency"] = {
             "workload": WORKLOADS["c5"] + f"; {args.latency_generations} generations per run, "
                         f"the first 2 not counted",
-            "offered_load": 0.7, "p50_ms": lo["p50_ms"], "p99_ms": lo["p99_ms"],
-            "requests": lo["requests"], "served_node_evals_per_s_at_capacity":
-                res["capacity"]["node_evals_per_s"],
-            "same_as_closed_loop": lo["same_as_closed_loop"]}
+            "by_offered_load": [{"offered_load": r["offered_load"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                                 "requests_counted": r["requests_counted"],
+                                 "node_evals_per_s": r["node_evals_per_s"],
+                                 "same_as_closed_loop": r["same_as_closed_loop"]} for r in res["loaded"]],
+            "served_node_evals_per_s_at_capacity": res["capacity"]["node_evals_per_s"]}
+        for r in res["loaded"]:
+            if abs(r["offered_load"] - 0.7) < 1e-9:
+                line["latency"].update(offered_load=0.7, p50_ms=r["p50_ms"], p99_ms=r["p99_ms"])
+    if not args.no_batched:
+        c4 = run_c4(argparse.Namespace(steps=max(3, args.steps // 2), warmup=1))
+        dt = c4["detail"]
+        line["batched"] = {
+            "workload": WORKLOADS["c4"], "batched_node_evals_per_s": c4["value"],
+            "plain_node_evals_per_s": dt["plain_value"],
+            "end_to_end_batched_over_plain": dt["batched_over_plain"],
+            "eval_only_ms": dt["eval_only_ms"],
+            "eval_only_batched_over_plain": dt["eval_only_batched_over_plain"],
+            "autotuned": dt["autotune"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pop, dspec, stats["dag_nodes"])
     print(json.dumps(line), flush=True)

@@ -13,8 +13,9 @@ shares no code with the HIP library and imports nothing from it.
                     (breed.py)
 """
 from .core import (build, coords, evaluate, fitness, library_path, max_threads,
-                   render_target, target_renderer, STABLE, NONFINITE_STABLE)
+                   render_target, target_renderer, STABLE, NONFINITE_STABLE, ENVELOPE)
 from .dag import build_dag, tree_stack_depth
 
 __all__ = ["build", "coords", "evaluate", "fitness", "library_path", "max_threads",
-           "render_target", "target_renderer", "build_dag", "tree_stack_depth", "STABLE", "NONFINITE_STABLE"]
+           "render_target", "target_renderer", "build_dag", "tree_stack_depth", "STABLE", "NONFINITE_STABLE",
+           "ENVELOPE"]

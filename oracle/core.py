@@ -13,6 +13,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 STABLE = 1             # finite case whose value is insensitive to FP32 rounding
 NONFINITE_STABLE = 2   # every FP32 variant gives the same non-finite class
+ENVELOPE = 4           # finite, clear of every discontinuity, bound above the stable limit
 
 _TOKEN = np.dtype([("op", "u1"), ("var", "u1"), ("pad", "<u2"), ("value", "<f4")])
 _lib = None

@@ -35,12 +35,15 @@
  *   sin/cos are sin(pi x) and cos(pi x) (Table 1 prints them swapped);
  *   div(x, 0) = +0 for either sign of zero; log(x<0) = -1, log(0) = -inf;
  *   pow(0, 0) = 0, otherwise C99 pow; sqrt has arity 1 and sqrt(x<0) = 0;
- *   min/max are IEEE minNum/maxNum (a NaN operand yields the other one);
+ *   min/max are IEEE minNum/maxNum (a NaN operand yields the other one)
+ *   with -0 ordered below +0 (so min(+0, -0) = -0 in either order);
  *   sign(NaN) = 0; clip(x, y, z) = max(min(x, z), y);
  *   mod is floored (result takes the divisor's sign), mod(x, 0) = 0;
  *   frac(x) = x - floor(x); if(x, y, z) = x != 0 ? y : z (NaN counts true);
  *   tan(x) = sin(pi x) / cos(pi x) with IEEE division;
- *   len(x, y) = the exact sqrt(x^2 + y^2) (hypot);
+ *   len(x, y) = the exact sqrt(x^2 + y^2) (hypot), NaN when an operand is
+ *   NaN (the formula's value; C99 hypot would give +inf beside an infinite
+ *   operand);
  *   warp(v, t0, t1) is a gather: v at the grid point whose axis-0 and axis-1
  *   positions t0, t1 name (nearest point, halves rounded up, clamped, NaN
  *   giving the first point; a third axis keeps its own point);
@@ -186,6 +189,22 @@ static void sincospi64(double x, double *s, double *c)
     if (*c == 0.0) *c = 0.0;
 }
 
+/* IEEE minNum / maxNum (a NaN operand yields the other one) with -0 ordered
+ * below +0, so the result does not depend on the operand order. */
+static double min_num(double a, double b)
+{
+    if (a == 0.0 && b == 0.0)
+        return signbit(a) ? a : b;
+    return fmin(a, b);
+}
+
+static double max_num(double a, double b)
+{
+    if (a == 0.0 && b == 0.0)
+        return signbit(a) ? b : a;
+    return fmax(a, b);
+}
+
 static double floor_mod(double x, double y)
 {
     if (y == 0.0)
@@ -225,7 +244,12 @@ static double apply(int op, double a, double b, double c, double *br)
     switch (op) {
     case OV_ADD: return a + b;
     case OV_SUB: return a - b;
-    case OV_MULT: return a * b;
+    case OV_MULT:
+        /* an infinite factor times a finite one: the sign (or NaN at 0) of
+         * the finite one decides the result */
+        if (isinf(a) != isinf(b))
+            *br = (double)(((isinf(a) ? b : a) > 0.0) - ((isinf(a) ? b : a) < 0.0));
+        return a * b;
     case OV_DIV:
         *br = (b == 0.0);
         return b == 0.0 ? 0.0 : a / b;
@@ -242,12 +266,13 @@ static double apply(int op, double a, double b, double c, double *br)
     case OV_POW:
         if (isnan(a) || isnan(b)) *br = 5;
         else if (a == 0.0 && b == 0.0) *br = 0;
-        else if (a == 0.0) *br = 1;
+        else if (a == 0.0) *br = (b > 0.0 ? 1 : 6) + (signbit(a) ? 10 : 0);  /* 0^b: +-0 or +-inf */
+        else if (isinf(b)) *br = fabs(a) < 1.0 ? 7 : (fabs(a) == 1.0 ? 8 : 9);
         else if (a < 0.0) *br = is_integral(b) ? 2 : 3;
         else *br = 4;
         return (a == 0.0 && b == 0.0) ? 0.0 : pow(a, b);
-    case OV_MIN: return fmin(a, b);
-    case OV_MAX: return fmax(a, b);
+    case OV_MIN: return min_num(a, b);
+    case OV_MAX: return max_num(a, b);
     case OV_MDIST: return (a + b) / 2.0;
     case OV_NEG: return -a;
     case OV_SQRT:
@@ -257,9 +282,10 @@ static double apply(int op, double a, double b, double c, double *br)
         *br = isnan(a) ? 3 : (a < 0.0 ? 0 : (a == 0.0 ? 1 : 2));
         return (double)((a > 0.0) - (a < 0.0));
     case OV_ABS: return fabs(a);
-    case OV_CLIP: return fmax(fmin(a, c), b);
+    case OV_CLIP: return max_num(min_num(a, c), b);
     case OV_MOD:
-        if (b == 0.0 || isnan(a) || isnan(b)) *br = -1.0;
+        if (b == 0.0 || isnan(a) || isnan(b)) *br = 1e308;
+        else if (isinf(b)) *br = (a != 0.0 && ((a < 0.0) != (b < 0.0))) ? -1.0 : 0.0;  /* a or +-inf */
         else *br = floor(a / b);
         return floor_mod(a, b);
     case OV_FRAC:
@@ -273,7 +299,7 @@ static double apply(int op, double a, double b, double c, double *br)
         return a < 0.0 ? -1.0 : 1.0;
     case OV_SSTEP: return a * a * (3.0 - 2.0 * a);
     case OV_SSTEPP: return a * a * a * (a * (6.0 * a - 15.0) + 10.0);
-    case OV_LEN: return hypot(a, b);
+    case OV_LEN: return isnan(a) || isnan(b) ? NAN : hypot(a, b);
     case OV_LERP:
         *br = isfinite(c) ? floor(c) : -1.0;
         return a + (b - a) * (c - floor(c));
@@ -403,6 +429,22 @@ static int same_branch(double a, double b)
 #define U_CR 1.1920928955078125e-07   /* 2^-23: one ulp, correctly rounded ops */
 #define U_LIB 4.76837158203125e-07    /* 2^-21: four ulp, library functions */
 #define MARGIN 4.0
+/* A first-order bound is trusted while the change it allows stays within
+ * this fraction of the scale on which the operator bends (a period, a
+ * unit of an exponent, the factors' own size); beyond it the case is not
+ * checked. */
+#define LINEAR 0.0625
+/* FLT_MAX plus half an ulp: FP32 rounding sends magnitudes from here on to inf */
+#define FLT_OVERFLOW 3.4028235677973366e+38
+
+/* Rounding an FP32 implementation of an operator may add to a result of
+ * magnitude av, for a relative accuracy u: below the normal range FP32
+ * values are spaced 2^-149 apart whatever their size, so the error is u
+ * times 2^-126 there (an exact zero stays exact, as in the relative model). */
+static double rnd(double u, double av)
+{
+    return u == 0.0 || av == 0.0 ? 0.0 : u * (av > 0x1p-126 ? av : 0x1p-126);
+}
 
 static double contrib(double deriv, double e)
 {
@@ -416,6 +458,18 @@ static int clear_of(double x, double p, double e)
     if (e == 0.0)
         return 1;
     return fabs(x - p) > MARGIN * e;
+}
+
+/* Bound of min or max (result val) of x and y with bounds ex, ey: when
+ * the operands are further apart than their bounds allow to close, every
+ * FP32 evaluation picks the same one and the result carries its bound;
+ * otherwise either may be picked (the operators are continuous, so the
+ * larger bound covers both). */
+static double select_bound(double x, double ex, double y, double ey, double val)
+{
+    if (fabs(x - y) > ex + ey)
+        return val == x ? ex : ey;
+    return ex > ey ? ex : ey;
 }
 
 static double dist_to_int(double x)
@@ -469,8 +523,13 @@ static void evb(const odomain *d, const onode *n, int32_t i, const double *xyz, 
         evb(d, n, p->kid[0], at, v, r, e, ok);
         return;
     }
-    for (int j = 0; j < ar; j++)
+    for (int j = 0; j < ar; j++) {
         evb(d, n, p->kid[j], xyz, &kv[j], &kr[j], &ke[j], ok);
+        /* an operand finite in FP64 but beyond FP32's range is +-inf in any
+         * FP32 evaluation, so O64 above it describes none of them */
+        if (isfinite(kv[j]) && fabs(kv[j]) >= FLT_OVERFLOW)
+            *ok = 0;
+    }
     double br0, br1;
     const double a = kv[0], b = kv[1], c = kv[2];
     const double ea = ke[0], eb = ke[1], ec = ke[2];
@@ -481,31 +540,56 @@ static void evb(const odomain *d, const onode *n, int32_t i, const double *xyz, 
     *v = val;
     double err = 0.0;
     const double av = fabs(val);
+    /* A correctly rounded operator whose operands are exact (zero bound)
+     * adds no error when its exact result is an FP32 value: rounding a
+     * representable value returns it.  (The FP64 result of FP32 operands is
+     * then that exact value: FP64 rounding cannot land on an FP32 value a
+     * non-representable quotient or root misses by more than 2^-48.) */
+    const int exact_in = ea == 0.0 && eb == 0.0 && ec == 0.0;
+    const double ucr = exact_in && (double)(float)val == val ? 0.0 : U_CR;
     double s, co;
     switch (p->op) {
     case OV_ADD:
-    case OV_SUB: err = ea + eb + U_CR * av; break;
-    case OV_MULT: err = contrib(b, ea) + contrib(a, eb) + U_CR * av; break;
+    case OV_SUB: err = ea + eb + rnd(ucr, av); break;
+    case OV_MULT:
+        if ((isinf(a) && !clear_of(b, 0.0, eb)) || (isinf(b) && !clear_of(a, 0.0, ea))) *ok = 0;
+        err = contrib(b, ea) + contrib(a, eb) + rnd(ucr, av);
+        if (ea * eb > LINEAR * err) *ok = 0;   /* the product of the two errors is not negligible */
+        break;
     case OV_DIV:
         if (b == 0.0) {
             if (eb != 0.0) *ok = 0;
             err = 0.0;
         } else {
             if (!clear_of(b, 0.0, eb)) *ok = 0;
-            err = contrib(1.0 / b, ea) + contrib(a / (b * b), eb) + U_CR * av;
+            err = contrib(1.0 / b, ea) + contrib(a / (b * b), eb) + rnd(ucr, av);
         }
         break;
-    case OV_SIN: sincospi64(a, &s, &co); err = contrib(M_PI * co, ea) + U_LIB * av; break;
-    case OV_COS: sincospi64(a, &s, &co); err = contrib(M_PI * s, ea) + U_LIB * av; break;
+    /* sin(pi a) and cos(pi a) of an exact multiple of 1/2 are exactly 0 or
+     * +-1 (the argument reduction is exact, see sincospi64) */
+    case OV_SIN:
+        sincospi64(a, &s, &co);
+        if (M_PI * ea > LINEAR) *ok = 0;       /* phase error not small against the period */
+        err = contrib(M_PI * co, ea) + rnd(exact_in && rint(2.0 * a) == 2.0 * a ? 0.0 : U_LIB, av);
+        break;
+    case OV_COS:
+        sincospi64(a, &s, &co);
+        if (M_PI * ea > LINEAR) *ok = 0;
+        err = contrib(M_PI * s, ea) + rnd(exact_in && rint(2.0 * a) == 2.0 * a ? 0.0 : U_LIB, av);
+        break;
     case OV_TAN:
         sincospi64(a, &s, &co);
         if (!clear_of(fabs(a - floor(a)), 0.5, ea)) *ok = 0;
-        err = contrib(M_PI / (co * co), ea) + U_LIB * av;
+        if (M_PI * ea > LINEAR) *ok = 0;
+        err = contrib(M_PI / (co * co), ea) + rnd(U_LIB, av);
         break;
-    case OV_EXP: err = contrib(val, ea) + U_LIB * av; break;
+    case OV_EXP:
+        if (ea > LINEAR) *ok = 0;              /* relative change e^ea - 1 not first-order */
+        err = contrib(val, ea) + rnd(U_LIB, av);
+        break;
     case OV_LOG:
         if (!clear_of(a, 0.0, ea)) *ok = 0;
-        err = a > 0.0 ? contrib(1.0 / a, ea) + U_LIB * av : 0.0;
+        err = a > 0.0 ? contrib(1.0 / a, ea) + rnd(U_LIB, av) : 0.0;
         break;
     case OV_POW:
         if (a == 0.0 && b == 0.0) {
@@ -514,56 +598,71 @@ static void evb(const odomain *d, const onode *n, int32_t i, const double *xyz, 
             break;
         }
         if (!clear_of(a, 0.0, ea)) *ok = 0;
+        if (a == 0.0 && !clear_of(b, 0.0, eb)) *ok = 0;          /* 0^b: 0 or +inf by the sign of b */
+        if (isinf(b) && !clear_of(fabs(a), 1.0, ea)) *ok = 0;    /* a^(+-inf) jumps at |a| = 1 */
         if (a < 0.0 && eb != 0.0 && dist_to_int(b) <= MARGIN * eb) *ok = 0;
-        if (a != 0.0 && isfinite(val))
-            err = contrib(b * val / a, ea) + (a > 0.0 ? contrib(val * log(a), eb) : 0.0) + U_LIB * av;
+        if (a != 0.0 && isfinite(val)) {
+            /* the exponent b log|a| must move by little for a first-order bound */
+            if (contrib(b / a, ea) + (a > 0.0 ? contrib(log(a), eb) : 0.0) > LINEAR) *ok = 0;
+            err = contrib(b * val / a, ea) + (a > 0.0 ? contrib(val * log(a), eb) : 0.0) + rnd(U_LIB, av);
+        }
         break;
     case OV_MIN:
-    case OV_MAX: err = ea > eb ? ea : eb; break;
-    case OV_MDIST: err = 0.5 * (ea + eb) + U_CR * av; break;
+    case OV_MAX: err = select_bound(a, ea, b, eb, val); break;
+    case OV_MDIST: err = 0.5 * (ea + eb) + rnd(ucr, av); break;
     case OV_NEG:
     case OV_ABS: err = ea; break;
     case OV_SQRT:
         if (!clear_of(a, 0.0, ea)) *ok = 0;
-        err = a > 0.0 ? contrib(0.5 / sqrt(a), ea) + U_CR * av : 0.0;
+        err = a > 0.0 ? contrib(0.5 / sqrt(a), ea) + rnd(ucr, av) : 0.0;
         break;
     case OV_SIGN:
     case OV_STEP:
         if (!clear_of(a, 0.0, ea)) *ok = 0;
         err = 0.0;
         break;
-    case OV_CLIP:
-        err = ea > eb ? ea : eb;
-        err = err > ec ? err : ec;
+    case OV_CLIP: {
+        const double m = min_num(a, c);
+        err = select_bound(m, select_bound(a, ea, c, ec, m), b, eb, val);
         break;
+    }
     case OV_MOD:
         if (b == 0.0) {
             if (eb != 0.0) *ok = 0;
             err = 0.0;
+        } else if (isinf(b)) {
+            if (isfinite(a) && !clear_of(a, 0.0, ea)) *ok = 0;  /* a, or +-inf past 0 */
+            err = ea;
         } else {
             const double q = a / b;
             const double eq = (ea + fabs(q) * eb) / fabs(b);
             if (eq != 0.0 && dist_to_int(q) <= MARGIN * eq) *ok = 0;
-            err = ea + contrib(floor(q), eb) + U_CR * av;
+            err = ea + contrib(floor(q), eb) + rnd(ucr, av);
         }
         break;
     case OV_FRAC:
         if (ea != 0.0 && dist_to_int(a) <= MARGIN * ea) *ok = 0;
-        err = ea + U_CR * av;
+        err = ea + rnd(ucr, av);
         break;
     case OV_IF:
         if (!clear_of(a, 0.0, ea)) *ok = 0;
         err = a != 0.0 ? eb : ec;
         break;
-    case OV_SSTEP: err = contrib(6.0 * a - 6.0 * a * a, ea) + U_LIB * av; break;
-    case OV_SSTEPP: err = contrib(30.0 * a * a * (a - 1.0) * (a - 1.0), ea) + U_LIB * av; break;
+    case OV_SSTEP:
+        if (ea > LINEAR * LINEAR / (1.0 + fabs(a))) *ok = 0;   /* curvature 6 - 12a */
+        err = contrib(6.0 * a - 6.0 * a * a, ea) + rnd(U_LIB, av);
+        break;
+    case OV_SSTEPP:
+        if (ea > LINEAR * LINEAR / (1.0 + a * a * a * a)) *ok = 0;
+        err = contrib(30.0 * a * a * (a - 1.0) * (a - 1.0), ea) + rnd(U_LIB, av);
+        break;
     case OV_LEN:
-        err = val == 0.0 ? ea + eb : contrib(a / val, ea) + contrib(b / val, eb) + U_LIB * av;
+        err = val == 0.0 ? ea + eb : contrib(a / val, ea) + contrib(b / val, eb) + rnd(U_LIB, av);
         break;
     case OV_LERP: {
         const double fz = c - floor(c);
         if (ec != 0.0 && dist_to_int(c) <= MARGIN * ec) *ok = 0;
-        err = contrib(1.0 - fz, ea) + contrib(fz, eb) + contrib(b - a, ec) + U_LIB * av;
+        err = contrib(1.0 - fz, ea) + contrib(fz, eb) + contrib(b - a, ec) + rnd(U_LIB, av);
         break;
     }
     case OV_OR:
@@ -572,13 +671,17 @@ static void evb(const odomain *d, const onode *n, int32_t i, const double *xyz, 
         /* truncation jumps at every non-zero integer */
         if (ea != 0.0 && fabs(rint(a)) >= 1.0 && dist_to_int(a) <= MARGIN * ea) *ok = 0;
         if (eb != 0.0 && fabs(rint(b)) >= 1.0 && dist_to_int(b) <= MARGIN * eb) *ok = 0;
-        err = U_CR * av;
+        /* the integer result is the same (checked above); only its
+         * rounding to FP32 can add error */
+        err = (double)(float)val == val ? 0.0 : rnd(U_CR, av);
         break;
     }
     if (!isfinite(val))
         err = 0.0;   /* an exact special value; its class is checked instead */
     else if (!isfinite(err))
         *ok = 0;
+    else if (!clear_of(av, FLT_OVERFLOW, err))
+        *ok = 0;     /* FP32 rounds to +-inf from FLT_OVERFLOW on: finite or not is undecided */
     *e = err;
 }
 
@@ -599,7 +702,14 @@ static int nonfinite_class(double v)
  *   v32r:  out [n_roots][n_cases] O32r values, or NULL.
  *   stab:  out [n_roots][n_cases] flags, or NULL: bit0 = stable finite case,
  *          bit1 = O32r and the FP32 rounding of O64 are non-finite of one
- *          class, clear of every discontinuity (that class is then required).
+ *          class, clear of every discontinuity (that class is then required),
+ *          bit2 = a finite case clear of every discontinuity (O64 and O32r
+ *          finite, O32r on O64's side of each) whose bound exceeds the
+ *          stable limit but not 1/16 of max(|O64|, 1), with O32r within the
+ *          bound (plus the stable limit) of O64: any FP32 evaluation
+ *          with operators of the assumed accuracy is then within the bound
+ *          of O64 to first order, and the bound is small enough that the
+ *          neglected second-order terms stay a few percent of it.
  *   ebound: out [n_roots][n_cases] running error bound of the root, or NULL.
  *   When any of v32r, stab, ebound is given the checked walk runs; otherwise
  *   only O64.
@@ -663,6 +773,9 @@ int orc_eval(const orc_token *tokens, const int64_t *offsets, int64_t n_roots,
                         f |= 1;
                     const int cl = nonfinite_class(r32);
                     const int cv = nonfinite_class((double)(float)v);
+                    if (ok && isfinite(v) && isfinite(r32) && !(f & 1) && e <= 0.0625 * sc &&
+                        fabs(r32 - v) <= e + 5e-6 * sc)
+                        f |= 4;
                     if (ok && cl && cl == cv &&
                         (!isfinite(v) || fabs(v) - e > 3.4028235677973366e38 * (1.0 + 5.9604644775390625e-08)))
                         f |= 2;

@@ -33,6 +33,7 @@ struct BuildStatus {
     int32_t max_var;
     int32_t max_stack;
     int32_t n_internal;
+    int32_t lost_key;  // nonzero when hash-consing found no slot for a key
 };
 
 enum { ERR_NONE = 0, ERR_OP = 1, ERR_PARSE = 2, ERR_RANGE = 3 };
@@ -311,7 +312,7 @@ __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, 
 // representative.
 __global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
                                int32_t *canon, const int32_t *table, uint64_t mask,
-                               uint32_t hash_bits, bool commute) {
+                               uint32_t hash_bits, bool commute, BuildStatus *st) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t t = list[i];
@@ -319,7 +320,11 @@ __global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok,
     uint64_t s = key_hash(k, hash_bits) & mask;
     for (;;) {
         const int32_t e = table[s];
-        if (e < 0) {  // cannot happen: t itself was inserted before the first empty slot
+        if (e < 0) {
+            // t itself was inserted before the first empty slot of its probe
+            // sequence, so reaching one means the table is corrupt: the build
+            // fails with an error instead of yielding a wrong DAG
+            atomicOr(&st->lost_key, 1);
             canon[t] = t;
             return;
         }
@@ -546,6 +551,7 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
     hs.max_var = -1;
     hs.max_stack = 0;
     hs.n_internal = 0;
+    hs.lost_key = 0;
     DCHK(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_structure, grid_for(R, 64), dim3(64), 0, s, tok, off_dev, R, T, kid,
                        height, stk, root_tok, st);
@@ -600,7 +606,7 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
             hipLaunchKernelGGL(k_hash_insert, grid_for(n), dim3(256), 0, s, lst, n, tok, kid, canon,
                                table, (uint64_t)(cap - 1), g_debug_hash_bits, commute);
             hipLaunchKernelGGL(k_hash_resolve, grid_for(n), dim3(256), 0, s, lst, n, tok, kid,
-                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits, commute);
+                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits, commute, st);
         }
         DCHK(hipGetLastError());
         DCHK(pool.alloc((void **)&flag, sizeof(int32_t) * T));
@@ -610,7 +616,13 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
         int32_t last[2] = {0, 0};
         DCHK(hipMemcpyAsync(&last[0], pos + T - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DCHK(hipMemcpyAsync(&last[1], flag + T - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DCHK(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
         DCHK(hipStreamSynchronize(s));
+        if (hs.lost_key) {
+            res.status = TGP_EHIP;
+            snprintf(err, errlen, "hash-consing found no table slot for a subtree (internal error)");
+            goto done;
+        }
         U = (int64_t)last[0] + last[1];
         res.U = U;
         dev->U = U;

@@ -93,11 +93,12 @@ constexpr bool packed_arities_match() {
 static_assert(packed_arities_match(), "every arity fits two bits and unpacks to the table's value");
 
 // --------------------------------------------------------------- cost model
-// VALU instructions per case of each operator as this library compiles it
-// for gfx950, measured by opcost_probe.hip (SQ_INSTS_VALU of a one-operator
-// kernel over random inputs in [-1, 1], less its loads, stores and
-// indexing); terminals cost the register move that places them on the
-// stack, warp is estimated (two axis points and a gathered read).
+// The planner's estimate of each operator's cost: VALU instructions per case
+// as this library compiles it for gfx950, measured once with a one-operator
+// kernel over random inputs in [-1, 1] (SQ_INSTS_VALU less its loads, stores
+// and indexing); terminals cost the register move that places them on the
+// stack, warp is estimated (two axis points and a gathered read).  It steers
+// caching and program order only; reported throughput does not use it.
 const double kOpCost[TGP_NUM_OPS] = {
     1,  1,              // var const
     1,  1,  1, 13,      // add sub mult div

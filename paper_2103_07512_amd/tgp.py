@@ -8,6 +8,7 @@ on the current torch stream of that device unless told otherwise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -21,6 +22,20 @@ RMSE, MSE = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 STATUS = {0: "TGP_OK", -1: "TGP_EINVAL", -2: "TGP_EPARSE", -3: "TGP_EDEPTH", -4: "TGP_EOP",
           -5: "TGP_ENOMEM", -6: "TGP_EHIP", -7: "TGP_ESHAPE", -8: "TGP_EBUSY"}
+
+
+# Set when the interpreter starts to exit: handles that are still open are
+# then left to the process exit (destroying them would call into a HIP
+# runtime that torch may already have torn down).
+_exiting = False
+
+
+def _mark_exiting():
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_mark_exiting)
 
 
 class TgpError(RuntimeError):
@@ -227,6 +242,8 @@ class Context:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -300,6 +317,8 @@ class Domain:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -371,6 +390,8 @@ class Dag:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -441,6 +462,8 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -538,6 +561,8 @@ class Server:
             self._keep.clear()
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -612,6 +637,8 @@ class Offspring:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:

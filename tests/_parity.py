@@ -1,19 +1,27 @@
 """The parity contract between the HIP path and the FP64 oracle.
 
-Per case (value v of the GPU; O64, O32r and the running error bound E from
-the oracle):
-  * on every case the oracle marks STABLE (E <= 5e-6 max(|O64|, 1), clear of
-    every discontinuity), |v - O64| / max(|O64|, 1) <= 1e-5;
-  * on every case it marks NONFINITE_STABLE, v has the same non-finite class
-    (NaN, +inf, -inf) as O32r.
+Per case (value g of the GPU; O64, O32r, the flags and the running error
+bound E from the oracle; sc = max(|O64|, 1)):
+  * STABLE (E <= 5e-6 sc, clear of every discontinuity): |g - O64| <= 1e-5 sc;
+  * ENVELOPE (clear of every discontinuity, 5e-6 sc < E <= sc / 16):
+    |g - O64| <= 1e-5 sc + 2 E (first-order analysis, doubled);
+  * NONFINITE_STABLE: g has the non-finite class (NaN, +inf, -inf) of O32r;
+  * every other case is unchecked per case (its count is reported).
 Per individual, with the first-order fitness bound E_F propagated from the
-per-case bounds (RMSE: sum |v - t| E / (N F); MSE: 2 sum |v - t| E / N):
-  * when all its cases are stable and E_F <= 1e-7 F_O64,
+per-case bounds of its checked cases (RMSE: sum |v - t| E / (N F); MSE:
+2 sum |v - t| E / N), every individual falls in exactly one class:
+  * inf: some case is NONFINITE_STABLE, so the GPU's fitness must be +inf;
+  * strict: every case stable and E_F <= 1e-7 F_O64:
     |F_gpu - F_O64| <= 1e-6 F_O64 (exact 0 when F_O64 = 0);
-  * otherwise, when all its cases are stable, |F_gpu - F_O64| <=
-    max(1e-6 F_O64, 2 E_F);
-  * always, F_gpu equals the FP64 reduction of the GPU's own per-case values
-    within 1e-6 relative (a property of the reduction alone).
+  * envelope: every case stable or envelope:
+    |F_gpu - F_O64| <= max(1e-6 F_O64, 2 E_F);
+  * partial: some cases unchecked.  The reference is the hybrid fitness H
+    of O64 on the checked cases and the GPU's own values on the rest:
+    |F_gpu - H| <= max(1e-6 H, 2 E_F), and +inf when H is not finite;
+and, for all individuals, F_gpu equals the FP64 reduction of the GPU's own
+per-case values within 1e-6 relative (a property of the reduction alone).
+An FP32 sum of squares that can reach FLT_MAX may give +inf on the device
+where the FP64 sum is finite; such individuals accept +inf.
 """
 import numpy as np
 
@@ -22,6 +30,7 @@ import oracle
 CASE_TOL = 1e-5
 FIT_TOL = 1e-6
 FLT_MAX = float(np.finfo(np.float32).max)
+CHECKED = oracle.STABLE | oracle.ENVELOPE | oracle.NONFINITE_STABLE
 
 
 def _sum_of_squares(f, n_terms, loss):
@@ -38,55 +47,115 @@ def nf_class(a):
     return np.where(np.isnan(a), 1, np.where(np.isposinf(a), 2, np.where(np.isneginf(a), 3, 0)))
 
 
-def check_cases(gpu, v64, v32r, stab, what=""):
+def case_counts(stab):
+    """How many cases the per-case contract checks, by kind."""
+    s = (stab & oracle.STABLE) != 0
+    e = (stab & oracle.ENVELOPE) != 0
+    n = (stab & oracle.NONFINITE_STABLE) != 0
+    return dict(cases=int(stab.size), stable=int(s.sum()), envelope=int(e.sum()), nonfinite=int(n.sum()),
+                unchecked=int((~(s | e | n)).sum()))
+
+
+def check_cases(gpu, v64, v32r, stab, ebound, what=""):
     g = np.asarray(gpu, dtype=np.float64)
     stable = (stab & oracle.STABLE) != 0
+    env = (stab & oracle.ENVELOPE) != 0
+    sc = np.maximum(np.abs(v64), 1.0)
     with np.errstate(all="ignore"):
-        err = np.abs(g - v64) / np.maximum(np.abs(v64), 1.0)
+        dev = np.abs(g - v64)
+        err = dev / sc
     bad = stable & ~(err <= CASE_TOL)
     if bad.any():
         r, c = np.argwhere(bad)[0]
         raise AssertionError(f"{what}: {bad.sum()} stable cases off, first tree {r} case {c}: "
                              f"gpu {g[r, c]!r} oracle {v64[r, c]!r} err {err[r, c]:.3g}")
+    bad = env & ~(dev <= CASE_TOL * sc + 2.0 * ebound)
+    if bad.any():
+        r, c = np.argwhere(bad)[0]
+        raise AssertionError(f"{what}: {bad.sum()} envelope cases off, first tree {r} case {c}: "
+                             f"gpu {g[r, c]!r} oracle {v64[r, c]!r} bound {ebound[r, c]:.3g}")
     nfs = (stab & oracle.NONFINITE_STABLE) != 0
     mism = nfs & (nf_class(g) != nf_class(v32r))
     if mism.any():
         r, c = np.argwhere(mism)[0]
         raise AssertionError(f"{what}: non-finite class differs at tree {r} case {c}: "
                              f"gpu {g[r, c]!r} O32r {v32r[r, c]!r}")
-    return dict(cases=int(stable.size), stable=int(stable.sum()), nonfinite_checked=int(nfs.sum()),
-                max_err=float(err[stable].max()) if stable.any() else 0.0)
+    out = case_counts(stab)
+    out["max_err_stable"] = float(err[stable].max()) if stable.any() else 0.0
+    return out
 
 
-def check_fitness(f_gpu, v64, v32r, stab, ebound, target, n_ind, n_ch, loss, what=""):
-    f64 = oracle.fitness(v64, target, n_ind, n_ch, loss)
-    stable = ((stab & oracle.STABLE) != 0).reshape(n_ind, -1).all(axis=1)
-    n_terms = v64.size // n_ind
-    d = np.abs(v64.reshape(n_ind, -1) - np.tile(np.asarray(target, np.float64).reshape(-1), 1)[None, :])
+def _fitness_bound(v, eb, target, n_ind, loss, f):
+    """First-order bound of each individual's fitness from per-case bounds."""
+    d = np.abs(v.reshape(n_ind, -1) - np.asarray(target, np.float64).reshape(1, -1))
+    n_terms = d.shape[1]
     with np.errstate(all="ignore"):
-        s = (d * ebound.reshape(n_ind, -1)).sum(axis=1)
-        ef = s / (n_terms * f64) if loss == "rmse" else 2 * s / n_terms
-    strict = envelope = 0
+        s = (d * eb.reshape(n_ind, -1)).sum(axis=1)
+        return s / (n_terms * f) if loss == "rmse" else 2 * s / n_terms
+
+
+def fitness_classes(v64, stab, ebound, target, n_ind, n_ch, loss):
+    """Class of every individual (see the module docstring), from the oracle
+    alone: 'inf', 'strict', 'envelope' or 'partial'."""
+    st = stab.reshape(n_ind, -1)
+    f64 = oracle.fitness(v64, target, n_ind, n_ch, loss)
+    ef = _fitness_bound(v64, ebound, target, n_ind, loss, f64)
+    nfs = ((st & oracle.NONFINITE_STABLE) != 0).any(axis=1)
+    all_stable = ((st & oracle.STABLE) != 0).all(axis=1)
+    all_checked = ((st & (oracle.STABLE | oracle.ENVELOPE)) != 0).all(axis=1)
+    out = []
     for i in range(n_ind):
-        a, g = f64[i], f_gpu[i]
-        if not (np.isfinite(a) and stable[i]):
-            continue
-        if _may_overflow(a, n_terms, loss) and g == np.inf:
-            continue
-        if a == 0:
-            assert g == 0, (what, i, g)
-            strict += 1
-            continue
-        if ef[i] <= 1e-7 * a:
-            tol = FIT_TOL * a
-            strict += 1
+        if nfs[i]:
+            out.append("inf")
+        elif all_stable[i] and np.isfinite(f64[i]) and (f64[i] == 0 or ef[i] <= 1e-7 * f64[i]):
+            out.append("strict")
+        elif all_checked[i] and np.isfinite(f64[i]):
+            out.append("envelope")
         else:
-            tol = max(FIT_TOL * a, 2 * ef[i])
-            envelope += 1
-        if not abs(g - a) <= tol:
-            raise AssertionError(f"{what}: individual {i} fitness gpu {g!r} oracle {a!r} "
-                                 f"bound {ef[i]:.3g} tol {tol:.3g}")
-    return dict(strict=strict, envelope=envelope)
+            out.append("partial")
+    return out, f64, ef
+
+
+def fitness_counts(classes):
+    return {k: int(sum(1 for c in classes if c == k)) for k in ("strict", "envelope", "inf", "partial")}
+
+
+def check_fitness(f_gpu, gpu_vals, v64, stab, ebound, target, n_ind, n_ch, loss, what=""):
+    classes, f64, ef = fitness_classes(v64, stab, ebound, target, n_ind, n_ch, loss)
+    n_terms = v64.size // n_ind
+    st = stab.reshape(n_ind, -1)
+    checked = (st & (oracle.STABLE | oracle.ENVELOPE)) != 0
+    g = np.asarray(gpu_vals, np.float64).reshape(n_ind, -1)
+    vv = v64.reshape(n_ind, -1)
+    eb = ebound.reshape(n_ind, -1)
+    t = np.asarray(target, np.float64).reshape(-1)
+    for i, cls in enumerate(classes):
+        got = f_gpu[i]
+        if cls == "inf":
+            assert got == np.inf, f"{what}: individual {i} has a required non-finite case, fitness {got!r}"
+            continue
+        if cls == "partial":
+            hyb = np.where(checked[i], vv[i], g[i])
+            ref = oracle.fitness(hyb.reshape(n_ch, -1), target, 1, n_ch, loss)[0]
+            e_i = np.where(checked[i], eb[i], 0.0)
+            with np.errstate(all="ignore"):
+                s = float((np.abs(hyb - t) * e_i).sum())
+                e_chk = s / (n_terms * ref) if loss == "rmse" else 2 * s / n_terms
+        else:
+            ref, e_chk = f64[i], ef[i]
+        if not np.isfinite(ref):
+            assert got == np.inf, f"{what}: individual {i} reference {ref!r} fitness {got!r}"
+            continue
+        if _may_overflow(ref, n_terms, loss) and got == np.inf:
+            continue
+        if ref == 0:
+            assert got == 0, f"{what}: individual {i} fitness {got!r}, reference 0"
+            continue
+        tol = FIT_TOL * ref if cls == "strict" else max(FIT_TOL * ref, 2 * e_chk)
+        if not abs(got - ref) <= tol:
+            raise AssertionError(f"{what}: individual {i} ({cls}) fitness gpu {got!r} reference {ref!r} "
+                                 f"bound {e_chk:.3g} tol {tol:.3g}")
+    return fitness_counts(classes)
 
 
 def reduction_property(f_gpu, gpu_vals, target, n_ind, n_ch, loss):

@@ -8,6 +8,8 @@ import pytest
 import oracle
 from paper_2103_07512_amd import popgen as pg
 
+import _parity
+
 pytestmark = pytest.mark.gpu
 
 
@@ -161,13 +163,13 @@ def test_fitness_batch_against_oracle(env):
     for (pop, shape, spec), (dag, dom, t, loss, out) in zip(work, jobs):
         _, target = pg.pick_target(spec, oracle.target_renderer(shape))
         v64, v32, st, eb = oracle.evaluate(pop.tokens, pop.offsets, shape, bound=True)
-        f64 = oracle.fitness(v64, target, pop.n_individuals)
-        ok = ((st & oracle.STABLE) != 0).all(axis=1) & np.isfinite(f64)
-        with np.errstate(all="ignore"):
-            ef = (np.abs(v64 - target[0].astype(np.float64)) * eb).sum(axis=1) / (v64.shape[1] * f64)
-        g = out.cpu().numpy()
-        for i in np.where(ok)[0]:
-            assert abs(g[i] - f64[i]) <= max(1e-6 * f64[i], 2 * ef[i]), (i, g[i], f64[i])
+        vals = torch.empty(pop.n_roots, dom.cases, dtype=torch.float32, device="cuda:0")
+        tgp.evaluate(ctx, dag, dom, vals)
+        vals = vals.cpu().numpy()
+        _parity.check_cases(vals, v64, v32, st, eb, f"batch job {shape}")
+        r = _parity.check_fitness(out.cpu().numpy(), vals, v64, st, eb, target, pop.n_individuals, 1, "rmse",
+                                  f"batch job {shape}")
+        say(shape, r)
 
 
 def test_batch_lds_stack(env):

@@ -18,6 +18,7 @@ from paper_2103_07512_amd import popgen as pg
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import _parity  # noqa: E402
+import parity_workloads as pw  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -222,6 +223,19 @@ def test_table1_points(env):
     assert np.isnan(got[0, 0]) and np.isnan(got[1, 0]) and np.isnan(got[2, 0])
 
 
+def test_min_max_signed_zeros(env):
+    """min and max order -0 below +0 in either operand order, bit for bit
+    (the reading the oracle takes; the sign reaches pow(0, -1) = +-inf)."""
+    cases = [("min(0.0, neg(0.0))", -0.0), ("min(neg(0.0), 0.0)", -0.0), ("max(0.0, neg(0.0))", 0.0),
+             ("max(neg(0.0), 0.0)", 0.0), ("pow(min(0.0, neg(0.0)), -1.0)", -math.inf),
+             ("pow(max(neg(0.0), 0.0), -1.0)", math.inf), ("clip(0.0, neg(0.5), neg(0.0))", -0.0)]
+    pop = pg.population_from_texts([t for t, _ in cases])
+    got, _, _ = gpu_eval(env, pop, (1,))
+    for (t, want), g in zip(cases, got[:, 0]):
+        assert g == want and math.copysign(1, g) == math.copysign(1, want), (t, g, want)
+        assert float(oracle.evaluate(pg.parse(t), np.array([0, len(pg.parse(t))]), (1,))[0, 0]) == want
+
+
 def finite_target(spec, shape):
     return pg.pick_target(spec, oracle.target_renderer(shape))[1]
 
@@ -230,60 +244,44 @@ def _full_parity(env, pop, shape, target_trees, loss="rmse", what="", cases=None
     say(what, "roots", pop.n_roots, "tokens", len(pop.tokens), "shape", shape)
     got, dag, dom = gpu_eval(env, pop, shape)
     v64, v32, st, eb = oracle.evaluate(pop.tokens, pop.offsets, shape, bound=True)
-    rc = _parity.check_cases(got, v64, v32, st, what)
+    rc = _parity.check_cases(got, v64, v32, st, eb, what)
     target = finite_target(target_trees, shape)
     f = gpu_fit(env, pop, dom, dag, target, loss)
-    rf = _parity.check_fitness(f, v64, v32, st, eb, target, pop.n_individuals, pop.n_channels, loss,
+    rf = _parity.check_fitness(f, got, v64, st, eb, target, pop.n_individuals, pop.n_channels, loss,
                                what)
     _parity.reduction_property(f, got, target, pop.n_individuals, pop.n_channels, loss)
     say(what, rc, rf)
-    return got, dag
+    return got, dag, rc, rf
 
 
-def test_parity_c1(env):
-    pop, dom, tgt = pg.workload_c1()
-    _full_parity(env, pop, dom.shape, tgt, what="C1")
+GOLD_COUNTS = pw.golden_counts()
 
 
-def test_parity_c2_bred_64(env):
-    pop, dom, tgt = pg.workload_c2(side=64)
-    got, dag = _full_parity(env, pop, (64, 64), tgt, what="C2@64x64")
+@pytest.mark.parametrize("name", list(pw.WORKLOADS))
+def test_parity_workload(env, name):
+    """Every named workload: per-case and fitness parity under the contract,
+    on exactly the checked cases and fitness classes the oracle's recorded
+    counts give (tests/golden/stability_counts.txt), which meet the
+    workload's floors."""
+    pop, shape, spec, loss = pw.load(name)
+    _, _, rc, rf = _full_parity(env, pop, shape, spec, loss, what=name)
+    gold = GOLD_COUNTS[name]
+    for k in ("cases", "stable", "envelope", "nonfinite", "unchecked"):
+        assert rc[k] == gold[k], (name, k, rc[k], gold[k])
+    for k in ("strict", "envelope", "inf", "partial"):
+        assert rf[k] == gold["fit_" + k], (name, k, rf[k], gold["fit_" + k])
+    cases, ind = pw.checked_shares(gold)
+    assert cases >= pw.FLOORS[name][0] and ind >= pw.FLOORS[name][1]
+
+
+def test_parity_c2_work(env):
+    """The bred 500-tree population shares subtrees: the plan caches some."""
     tgp, ctx, _ = env
+    pop, shape, spec, loss = pw.load("C2@64x64")
+    gpu_eval(env, pop, shape)
     w = ctx.last_work()
     say("C2 work", w)
-
-
-def test_parity_f18_rhh_ragged(env):
-    """Deep F18 trees (stack beyond the register slots) on a ragged 37x53 grid."""
-    pop = pg.ramped_half_and_half(60, 2, 12, 21, pg.F18, 2)
-    tgt = pg.TargetSpec(5, 22, pg.F18, 2, 1)
-    _full_parity(env, pop, (37, 53), tgt, what="F18 d2-12 @37x53")
-
-
-def test_parity_three_channels_mse(env):
-    pop = pg.ramped_half_and_half(40, 2, 8, 31, pg.F18, 2, n_channels=3)
-    tgt = pg.TargetSpec(4, 32, pg.F18, 2, 3)
-    _full_parity(env, pop, (48, 40), tgt, loss="mse", what="3-channel MSE")
-
-
-def test_parity_3d_domain(env):
-    pop = pg.ramped_half_and_half(30, 2, 7, 41, pg.F18, 3)
-    tgt = pg.TargetSpec(4, 42, pg.F18, 3, 1)
-    _full_parity(env, pop, (9, 10, 11), tgt, what="3-D 9x10x11")
-
-
-def test_parity_1d_and_tiny(env):
-    pop = pg.ramped_half_and_half(20, 0, 5, 51, pg.F6, 1)
-    tgt = pg.TargetSpec(3, 52, pg.F6, 1, 1)
-    _full_parity(env, pop, (7,), tgt, what="1-D 7 cases")
-    _full_parity(env, pop, (1,), tgt, what="1 case")
-
-
-def test_parity_extended_ops(env):
-    funcs = tuple(n for n, a in pg.OPS if a > 0)
-    pop = pg.ramped_half_and_half(80, 1, 6, 61, funcs, 2)
-    tgt = pg.TargetSpec(3, 62, pg.F6, 2, 1)
-    _full_parity(env, pop, (33, 65), tgt, what=f"all {len(funcs)} operators")
+    assert w["cached_nodes"] > 0 and w["executed_node_evals"] > 0
 
 
 def test_parity_warp(env):
@@ -297,25 +295,25 @@ def test_parity_warp(env):
         _full_parity(env, pop, shape, tgt, what=f"warp {shape} ({n_warp} warp nodes)")
 
 
+def _dag_equal(g, o, what):
+    """The exported DAG equals the oracle's: every array, bit for bit."""
+    assert g["dag_nodes"] == o["dag_nodes"], what
+    assert np.array_equal(g["nodes"]["op"], o["node_op"]), what
+    assert np.array_equal(g["nodes"]["var"][o["node_op"] == 0], o["node_var"][o["node_op"] == 0]), what
+    assert np.array_equal(g["nodes"]["value"].view(np.uint32), o["node_value"].view(np.uint32)), what
+    for k in ("children", "roots", "multiplicity", "indegree"):
+        assert np.array_equal(g[k], o[k]), (what, k)
+    for k in ("tree_nodes", "tree_internal", "dag_internal", "shared_internal", "max_stack", "max_height"):
+        assert g[k] == o[k], (what, k)
+
+
 def _dag_bit_exact(env, commutative):
     tgp, ctx, torch = env
     for name, pop in (("C1", pg.workload_c1()[0]), ("C2", pg.workload_c2(side=8)[0]),
                       ("F18 d2-12", pg.ramped_half_and_half(300, 2, 12, 71, pg.F18, 2))):
         say("DAG", name, len(pop.tokens), "commutative" if commutative else "structural")
         dag = tgp.build_dag(ctx, pop)
-        g = dag.export()
-        o = oracle.build_dag(pop.tokens, pop.offsets, commutative=commutative)
-        assert g["dag_nodes"] == o["dag_nodes"]
-        assert np.array_equal(g["nodes"]["op"], o["node_op"])
-        assert np.array_equal(g["nodes"]["var"][o["node_op"] == 0], o["node_var"][o["node_op"] == 0])
-        assert np.array_equal(g["nodes"]["value"].view(np.uint32), o["node_value"].view(np.uint32))
-        assert np.array_equal(g["children"], o["children"])
-        assert np.array_equal(g["roots"], o["roots"])
-        assert np.array_equal(g["multiplicity"], o["multiplicity"])
-        assert np.array_equal(g["indegree"], o["indegree"])
-        for k in ("tree_nodes", "tree_internal", "dag_internal", "shared_internal", "max_stack",
-                  "max_height"):
-            assert g[k] == o[k], k
+        _dag_equal(dag.export(), oracle.build_dag(pop.tokens, pop.offsets, commutative=commutative), name)
 
 
 def test_dag_bit_exact(env):
@@ -351,7 +349,7 @@ def test_dag_deep_postfix_stacks(env):
     assert np.array_equal(g["multiplicity"], o["multiplicity"])
     got, _, dom = gpu_eval(env, pop, (12, 10))
     v64, v32, st, eb = oracle.evaluate(pop.tokens, pop.offsets, (12, 10), bound=True)
-    _parity.check_cases(got, v64, v32, st, "deep stacks")
+    _parity.check_cases(got, v64, v32, st, eb, "deep stacks")
 
 
 def test_dag_commutative_hashing(env):
@@ -458,7 +456,7 @@ def test_constant_folding_bitwise(env):
     assert np.array_equal(a[m].view(np.uint32), b[m].view(np.uint32))
     assert np.array_equal(res[False][1].view(np.uint64), res[True][1].view(np.uint64))
     v64, v32, st, eb = oracle.evaluate(both.tokens, both.offsets, shape, bound=True)
-    _parity.check_cases(res[True][0], v64, v32, st, "folded")
+    _parity.check_cases(res[True][0], v64, v32, st, eb, "folded")
 
 
 def test_lds_stack_form(env):
@@ -486,7 +484,7 @@ def test_lds_stack_form(env):
         say("LDS stack, deep programs:", w["stack_spills"], "spills")
         assert w["stack_spills"] == 0
         v64, v32, st, eb = oracle.evaluate(deep.tokens, deep.offsets, (16, 16), bound=True)
-        _parity.check_cases(got, v64, v32, st, "LDS deep")
+        _parity.check_cases(got, v64, v32, st, eb, "LDS deep")
     finally:
         ctx.set_stack(False)
     got_r, _, _ = gpu_eval(env, deep, (16, 16))
@@ -555,17 +553,40 @@ def test_device_resident_population(env):
     assert np.array_equal(ref["nodes"], got["nodes"])
 
 
-def test_c3_full_size_sampled(env):
-    """The 1000 x 3-channel, 1024x1024 workload: sampled cases vs the oracle,
-    fitness vs the FP64 reduction of the GPU's own values."""
+def _c3_check_rows(out, pop, shape, rows, say_every=4):
+    """Per-case parity of every tree on whole grid rows (16 at a time)."""
+    import torch
+    n = shape[1]
+    tot = None
+    for k in range(0, len(rows), 16):
+        r = rows[k:k + 16]
+        idx = (r[:, None] * n + np.arange(n)[None, :]).ravel()
+        g = out[:, torch.from_numpy(idx).to(out.device)].cpu().numpy()
+        v64, v32, st, eb = oracle.evaluate(pop.tokens, pop.offsets, shape, cases=idx, bound=True)
+        rc = _parity.check_cases(g, v64, v32, st, eb, f"C3 rows {r[0]}..{r[-1]}")
+        tot = rc if tot is None else {key: tot[key] + rc[key] for key in ("cases", "stable", "envelope",
+                                                                           "nonfinite", "unchecked")}
+        if (k // 16) % say_every == 0:
+            say("C3 rows", r[0], "..", r[-1], rc)
+    return tot
+
+
+def test_c3_full_size(env):
+    """The headline workload (1000 individuals x 3 channel trees, 1024x1024,
+    MSE) at full size, in the launch configuration the benchmark times:
+    the exported DAG against the oracle's array by array; per-case values of
+    all 3000 trees on 64 evenly spaced grid rows; per-case values and the
+    full-domain MSE of 40 seeded individuals against the oracle; the fitness
+    of all 1000 individuals against an FP64 reduction of the GPU's values."""
     tgp, ctx, torch = env
     pop, dom, tgt = pg.workload_c3()
+    shape = dom.shape
     say("C3 full size", pop.n_roots, "trees", len(pop.tokens), "tokens")
-    d = tgp.Domain(ctx, dom.shape)
+    d = tgp.Domain(ctx, shape)
     dag = tgp.build_dag(ctx, pop)
-    o = oracle.build_dag(pop.tokens, pop.offsets)
-    assert dag.stats()["dag_nodes"] == o["dag_nodes"]
-    target = finite_target(tgt, dom.shape)
+    say("C3: DAG export against the oracle's DAG")
+    _dag_equal(dag.export(), oracle.build_dag(pop.tokens, pop.offsets), "C3")
+    target = finite_target(tgt, shape)
     t_dev = torch.from_numpy(target).to("cuda:0")
     f_dev = torch.empty(pop.n_individuals, dtype=torch.float64, device="cuda:0")
     tgp.fitness(ctx, dag, d, t_dev, tgp.MSE, f_dev)
@@ -573,14 +594,24 @@ def test_c3_full_size_sampled(env):
     tgp.evaluate(ctx, dag, d, out)
     torch.cuda.synchronize()
     f = f_dev.cpu().numpy()
-    rng = np.random.default_rng(5)
-    idx = np.unique(np.concatenate([rng.integers(0, d.cases, 120), [0, d.cases - 1, 1023, 1024]]))
-    g = out[:, torch.from_numpy(idx).to("cuda:0")].cpu().numpy()
-    say("C3 oracle on", len(idx), "sampled cases")
-    v64, v32, st = oracle.evaluate(pop.tokens, pop.offsets, dom.shape, cases=idx, variants=True)
-    rc = _parity.check_cases(g, v64, v32, st, "C3 sampled")
-    say("C3", rc)
-    # reduction property over all 3 x 2^20 cases, in FP64 on the device
+    say("C3: 64 grid rows, all trees")
+    rows = np.arange(0, shape[0], shape[0] // 64)
+    rc = _c3_check_rows(out, pop, shape, rows)
+    say("C3 rows total", rc)
+    assert (rc["stable"] + rc["envelope"] + rc["nonfinite"]) >= 0.88 * rc["cases"]
+    # 40 seeded individuals over the whole grid
+    sel = np.sort(np.random.default_rng(5).choice(pop.n_individuals, 40, replace=False))
+    roots = np.array([3 * i + c for i in sel for c in range(3)])
+    sub = pg.Population.from_trees([pop.tree(int(r)) for r in roots], n_channels=3)
+    say("C3: full grid of", len(sel), "individuals")
+    v64, v32, st, eb = oracle.evaluate(sub.tokens, sub.offsets, shape, bound=True)
+    g = out[torch.from_numpy(roots).to("cuda:0")].cpu().numpy()
+    rc2 = _parity.check_cases(g, v64, v32, st, eb, "C3 full grid")
+    rf = _parity.check_fitness(f[sel], g, v64, st, eb, target, len(sel), 3, "mse", "C3 full grid")
+    say("C3 full grid", rc2, rf)
+    assert rf["partial"] <= len(sel) // 2
+    del v64, v32, st, eb, g
+    # reduction property over all 3 x 2^20 cases of every individual, in FP64 on the device
     tt = t_dev.double()
     want = np.empty(pop.n_individuals)
     for i0 in range(0, pop.n_individuals, 100):

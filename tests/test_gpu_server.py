@@ -38,6 +38,16 @@ class Work:
         self.target_host = tgt
         self.target = torch.from_numpy(np.ascontiguousarray(tgt)).to("cuda:0")
 
+    def values(self, env):
+        """Per-case values of the plain evaluate path (the same device
+        operator code the served fitness runs)."""
+        tgp, ctx, torch = env
+        dag = tgp.build_dag(ctx, self.pop)
+        v = torch.empty(self.pop.n_roots, self.dom.cases, dtype=torch.float32, device="cuda:0")
+        tgp.evaluate(ctx, dag, self.dom, v)
+        torch.cuda.synchronize()
+        return v.cpu().numpy()
+
     def plain(self, env):
         tgp, ctx, torch = env
         dag = tgp.build_dag(ctx, self.pop)
@@ -124,7 +134,7 @@ def test_served_against_oracle(env):
         got = srv.wait(t)
         say(w.shape, srv.ticket_info(t))
         v64, v32, stab, eb = oracle.evaluate(w.pop.tokens, w.pop.offsets, w.shape, bound=True)
-        check_fitness(got, v64, v32, stab, eb, w.target_host, w.pop.n_individuals, 1, "rmse",
+        check_fitness(got, w.values(env), v64, stab, eb, w.target_host, w.pop.n_individuals, 1, "rmse",
                       f"served {w.shape}")
     srv.close()
 

@@ -97,6 +97,17 @@ def test_table1_points(text, want):
         assert got == want, (text, got, want)
 
 
+def test_min_max_signed_zeros():
+    """min and max order -0 below +0, in either operand order (the device's
+    fminf / fmaxf do, and a zero's sign decides pow(0, -1) = +-inf)."""
+    for text, want in (("min(0.0, neg(0.0))", -0.0), ("min(neg(0.0), 0.0)", -0.0),
+                       ("max(0.0, neg(0.0))", 0.0), ("max(neg(0.0), 0.0)", 0.0),
+                       ("pow(min(0.0, neg(0.0)), -1.0)", -math.inf), ("pow(max(neg(0.0), 0.0), -1.0)", math.inf),
+                       ("clip(neg(0.0), 0.0, 0.5)", 0.0), ("clip(0.0, neg(0.5), neg(0.0))", -0.0)):
+        got = ev1(text)
+        assert got == want and math.copysign(1, got) == math.copysign(1, want), (text, got)
+
+
 def test_nan_rules():
     assert math.isnan(ev1("pow(-0.5, 0.5)"))
     assert ev1("sign(pow(-0.5, 0.5))") == 0.0
@@ -252,6 +263,14 @@ def _np_eval(text, X, Y):
     def sign(a):
         return np.where(np.isnan(a), 0.0, np.sign(a))
 
+    def min_num(a, b):  # -0 below +0
+        a, b = np.broadcast_arrays(np.asarray(a, float), np.asarray(b, float))
+        return np.where((a == 0) & (b == 0), np.where(np.signbit(a), a, b), np.fmin(a, b))
+
+    def max_num(a, b):
+        a, b = np.broadcast_arrays(np.asarray(a, float), np.asarray(b, float))
+        return np.where((a == 0) & (b == 0), np.where(np.signbit(a), b, a), np.fmax(a, b))
+
     def frac(a):
         return a - np.floor(a)
 
@@ -265,11 +284,12 @@ def _np_eval(text, X, Y):
 
     env = dict(
         add=lambda a, b: a + b, sub=lambda a, b: a - b, mult=lambda a, b: a * b, div=div,
-        sin=sinpi, cos=cospi, tan=tanpi, exp=ex, log=log, pow=pw, min=np.fmin, max=np.fmax,
+        sin=sinpi, cos=cospi, tan=tanpi, exp=ex, log=log, pow=pw, min=min_num, max=max_num,
         mdist=lambda a, b: (a + b) / 2, neg=lambda a: -a, sqrt=sqrt, sign=sign, abs=np.abs,
-        clip=lambda a, b, c: np.fmax(np.fmin(a, c), b), mod=mod, frac=frac,
+        clip=lambda a, b, c: max_num(min_num(a, c), b), mod=mod, frac=frac,
         step=lambda a: np.where(a < 0, -1.0, 1.0), sstep=lambda a: a * a * (3 - 2 * a),
-        sstepp=lambda a: a ** 3 * (a * (6 * a - 15) + 10), len=np.hypot,
+        sstepp=lambda a: a ** 3 * (a * (6 * a - 15) + 10),
+        len=lambda a, b: np.where(np.isnan(a) | np.isnan(b), np.nan, np.hypot(a, b)),
         lerp=lambda a, b, c: a + (b - a) * frac(c), x=X, y=Y, inf=np.inf, nan=np.nan,
         np=np)
     env["if"] = lambda a, b, c: np.where(a != 0, b, c)

@@ -1,7 +1,9 @@
 """The oracle's pins must catch plausible mistakes: each test plants one
-mistake (a swapped operand, a dropped term, a wrong sign or protection) in a
-copy of oracle.c, builds it on the CPU, and runs the pin suite
-(tests/test_oracle.py) against it in a fresh process; the suite must fail."""
+mistake (a swapped operand, a dropped term, a wrong sign or protection, a
+wrong accuracy constant or margin in the stability classifier) in a copy of
+oracle.c, builds it on the CPU, and runs the pin suites (tests/test_oracle.py
+and tests/test_oracle_stability.py) against it in a fresh process; they must
+fail."""
 import os
 import subprocess
 import sys
@@ -38,6 +40,24 @@ MUTANTS = [
     ("warp axes swapped", "warp_coords(d, ev64(d, n, p->kid[1], xyz), ev64(d, n, p->kid[2], xyz), xyz, at);",
      "warp_coords(d, ev64(d, n, p->kid[2], xyz), ev64(d, n, p->kid[1], xyz), xyz, at);"),
     ("warp rounds halves down", "(d->hi[k] - d->lo[k])) + 0.5;", "(d->hi[k] - d->lo[k])) + 0.4999;"),
+    ("min of signed zeros by operand order", "        return signbit(a) ? a : b;\n    return fmin(a, b);",
+     "        return b;\n    return fmin(a, b);"),
+    # the stability classifier (error bound and flags)
+    ("correctly rounded accuracy x10", "#define U_CR 1.1920928955078125e-07", "#define U_CR 1.1920928955078125e-06"),
+    ("library accuracy x10", "#define U_LIB 4.76837158203125e-07", "#define U_LIB 4.76837158203125e-06"),
+    ("discontinuity margin 40 bounds", "#define MARGIN 4.0", "#define MARGIN 40.0"),
+    ("mult bound drops a derivative", "err = contrib(b, ea) + contrib(a, eb) + rnd(ucr, av);",
+     "err = contrib(b, ea) + rnd(ucr, av);"),
+    ("sin bound drops its derivative", "err = contrib(M_PI * co, ea) + rnd(exact_in", "err = rnd(exact_in"),
+    ("no subnormal floor", "u * (av > 0x1p-126 ? av : 0x1p-126)", "u * av"),
+    ("0^b sign of b not checked", "if (a == 0.0 && !clear_of(b, 0.0, eb)) *ok = 0;", ""),
+    ("phase of sin unguarded", "        if (M_PI * ea > LINEAR) *ok = 0;       /* phase error not small against the period */\n", ""),
+    ("overflow edge unchecked", "    else if (!clear_of(av, FLT_OVERFLOW, err))\n        *ok = 0;", ""),
+    ("stable limit x10", "e <= 5e-6 * sc && fabs(r32 - v) <= 5e-6 * sc", "e <= 5e-5 * sc && fabs(r32 - v) <= 5e-6 * sc"),
+    ("exactness without exact operands", "const double ucr = exact_in && (double)(float)val == val ? 0.0 : U_CR;",
+     "const double ucr = (double)(float)val == val ? 0.0 : U_CR;"),
+    ("min/max bound of the other operand", "return val == x ? ex : ey;", "return val == x ? ey : ex;"),
+    ("envelope limit x10", "e <= 0.0625 * sc &&", "e <= 0.625 * sc &&"),
 ]
 
 
@@ -47,8 +67,8 @@ def _run_pins(tmp_path, text):
     lib = core.build(str(src), str(tmp_path / "liboracle_copy.so"))
     env = dict(os.environ, TGP_ORACLE_LIBRARY=lib)
     return subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                           os.path.join(HERE, "test_oracle.py")], env=env, capture_output=True,
-                          text=True, timeout=600)
+                           os.path.join(HERE, "test_oracle.py"), os.path.join(HERE, "test_oracle_stability.py")],
+                          env=env, capture_output=True, text=True, timeout=600)
 
 
 def test_unmodified_copy_passes(tmp_path):
