@@ -19,7 +19,10 @@
  *   - "device pointer" means memory on the context's GPU (for instance a torch
  *     tensor's data_ptr()); it belongs to the caller and must be large enough;
  *   - host buffers passed in are only read during the call; handles belong to
- *     the library and are released by the matching *_destroy;
+ *     the library and are released by the matching *_destroy; the DAGs,
+ *     domains, batches and offspring made on a context are destroyed before
+ *     the context (destroying it releases their device memory; a server
+ *     keeps contexts of its own and may outlive the one it was made from);
  *   - device work is ordered on the context's HIP stream and is asynchronous
  *     unless a function says it blocks;
  *   - a context is used by one host thread at a time.
@@ -65,8 +68,8 @@ enum tgp_opcode {
     TGP_EXP = 9,    /* [1] e^x */
     TGP_LOG = 10,   /* [1] ln x, -1 when x < 0 (ln 0 = -inf) */
     TGP_POW = 11,   /* [2] x^y, 0 when x == y == 0, otherwise C99 pow */
-    TGP_MIN = 12,   /* [2] IEEE minNum */
-    TGP_MAX = 13,   /* [2] IEEE maxNum */
+    TGP_MIN = 12,   /* [2] IEEE minNum, -0 below +0 (either operand order) */
+    TGP_MAX = 13,   /* [2] IEEE maxNum, +0 above -0 (either operand order) */
     TGP_MDIST = 14, /* [2] (x + y) / 2 */
     TGP_NEG = 15,   /* [1] -x */
     TGP_SQRT = 16,  /* [1] sqrt(x), 0 when x < 0 (arity 1; the table prints 2) */

@@ -312,6 +312,10 @@ class Domain:
         self.cases = int(lib().tgp_domain_cases(h))
 
     def close(self):
+        # a handle outlived by its context: the context's destruction has
+        # already released its device memory (the library must not see it)
+        if self.h and not self.ctx.h:
+            self.h = None
         if self.h:
             lib().tgp_domain_destroy(self.h)
             self.h = None
@@ -385,6 +389,10 @@ class Dag:
                     indegree=indeg, **st)
 
     def close(self):
+        # a handle outlived by its context: the context's destruction has
+        # already released its device memory (the library must not see it)
+        if self.h and not self.ctx.h:
+            self.h = None
         if self.h:
             lib().tgp_dag_destroy(self.h)
             self.h = None
@@ -457,6 +465,10 @@ class Batch:
         return st.as_dict()
 
     def close(self):
+        # a handle outlived by its context: the context's destruction has
+        # already released its device memory (the library must not see it)
+        if self.h and not self.ctx.h:
+            self.h = None
         if self.h:
             lib().tgp_batch_destroy(self.h)
             self.h = None
@@ -555,6 +567,8 @@ class Server:
         return st.as_dict()
 
     def close(self):
+        # (a server keeps contexts of its own, so it is destroyed even when
+        # the context it was made from is gone)
         if self.h:
             lib().tgp_server_destroy(self.h)
             self.h = None
@@ -632,6 +646,10 @@ class Offspring:
         return toks, offs
 
     def close(self):
+        # a handle outlived by its context: the context's destruction has
+        # already released its device memory (the library must not see it)
+        if self.h and not self.ctx.h:
+            self.h = None
         if self.h:
             lib().tgp_offspring_destroy(self.h)
             self.h = None
