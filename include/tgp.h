@@ -264,6 +264,25 @@ tgp_status tgp_evaluate(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, float *out_dev
 tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, const float *target_dev,
                        int32_t loss, double *out);
 
+/* tgp_fitness without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same kernels, same arguments and the same result
+ * bits as tgp_fitness, with these limits:
+ *   - target_dev and out must be device memory (TGP_EINVAL otherwise);
+ *   - dag must already hold its plan for a domain of dom's size under the
+ *     context's current settings, i.e. it has been evaluated once by
+ *     tgp_fitness or tgp_evaluate on such a domain (TGP_EINVAL otherwise);
+ *   - the partial sums (8 bytes per root program per stripe) and the cached
+ *     subtree rows (4 bytes per cached subtree per case) live in a fixed
+ *     64 MiB device array per GPU, held until the process ends; a call that
+ *     needs more returns TGP_ENOMEM without launching anything (lower the
+ *     cache budget, tgp_ctx_set_cache_budget, before planning to fit).
+ * Every call on a GPU shares that array, so calls that overlap on one GPU
+ * (two streams, or two contexts on the same device) race: order them.
+ * Queued on the context's stream; returns without waiting. */
+tgp_status tgp_fitness_noalloc(tgp_ctx ctx, tgp_dag dag, tgp_domain dom, const float *target_dev,
+                               int32_t loss, double *out);
+
 /* Work counts of the last tgp_evaluate / tgp_fitness on ctx (for reports).
  * VALU figures are lane-slots: cases x the per-operator instruction counts of
  * the compiled interpreter (a cost model, documented with the library). */

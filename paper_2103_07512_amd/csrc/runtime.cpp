@@ -116,6 +116,35 @@ const double kOpCost[TGP_NUM_OPS] = {
 // of VALU issue is about 20 slots per access (the default of
 // tgp_ctx_set_plan's cache_access_cost).
 
+// ------------------------------------------------- fixed device scratch
+// tgp_fitness_noalloc keeps its partial sums and subtree cache rows in this
+// array instead of allocated buffers, so it calls no allocator.  Each GPU
+// the library runs on holds its own copy until the process ends.  In host
+// code `scratch` only names the symbol: its device address is looked up once
+// per device (hipGetSymbolAddress, at context creation, with the device
+// current) and that address is what kernels and copies receive.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+}  // namespace
+
+// With `device` current: its scratch address, looked up on first use.
+static void scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    if (e == hipSuccess) g_scratch_ptr[device] = p;
+    else (void)hipGetLastError();  // leave no error behind for the next call
+}
+
 // --------------------------------------------------------------- contexts
 extern "C" {
 
@@ -136,6 +165,7 @@ tgp_status tgp_ctx_create(int device, void *hip_stream, tgp_ctx *out) {
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, TGP_EHIP, "device %d is %s, libtgp is built for gfx950", device,
                     prop.gcnArchName);
+    scratch_setup(device);
     tgp_ctx c = new tgp_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -1684,15 +1714,9 @@ static void fill_args(InterpArgs &a, tgp_domain dom, const uint2 *code, const fl
     fill_job(a.job, dom, code, cache);
 }
 
-static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float **cache_out) {
+// The cache-fill launches of d's plan, writing its cache rows to `cache`.
+static tgp_status fill_into(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float *cache) {
     const Plan &P = d->plan;
-    *cache_out = nullptr;
-    ctx->fill_recorded = false;
-    if (P.n_slots == 0) return TGP_OK;
-    const size_t bytes = sizeof(float) * (size_t)P.n_slots * (size_t)dom->cases;
-    HCHK(ctx, ensure(ctx->cache, bytes));
-    float *cache = (float *)ctx->cache.p;
-    *cache_out = cache;
     record(ctx, 0);
     ctx->fill_recorded = ctx->timing;
     for (size_t l = 0; l + 1 < P.level_first.size(); ++l) {
@@ -1708,6 +1732,18 @@ static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float 
     }
     record(ctx, 1);
     return TGP_OK;
+}
+
+static tgp_status run_fill(tgp_ctx ctx, tgp_dag d, tgp_domain dom, int K, float **cache_out) {
+    const Plan &P = d->plan;
+    *cache_out = nullptr;
+    ctx->fill_recorded = false;
+    if (P.n_slots == 0) return TGP_OK;
+    const size_t bytes = sizeof(float) * (size_t)P.n_slots * (size_t)dom->cases;
+    HCHK(ctx, ensure(ctx->cache, bytes));
+    float *cache = (float *)ctx->cache.p;
+    *cache_out = cache;
+    return fill_into(ctx, d, dom, K, cache);
 }
 
 // The plan of d for dom with its cache filled (fill launches queued on the
@@ -1804,6 +1840,64 @@ tgp_status tgp_fitness(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *targ
                                  ctx->stream));
         HCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
+    ctx->times.interp_items = (int64_t)a.n_progs * a.job.n_stripes;
+    ctx->times.cases_per_lane = K;
+    ctx->times.tiles_per_item = a.job.tiles_per_stripe;
+    record_work(ctx, d, dom, true);
+    return TGP_OK;
+}
+
+tgp_status tgp_fitness_noalloc(tgp_ctx ctx, tgp_dag d, tgp_domain dom, const float *target_dev,
+                               int32_t loss, double *out_dev) {
+    tgp_status st = check_eval_args(ctx, d, dom);
+    if (st != TGP_OK) return st;
+    if (loss != TGP_RMSE && loss != TGP_MSE) return fail(ctx, TGP_EINVAL, "loss must be TGP_RMSE or TGP_MSE");
+    if (d->n_ind == 0) return TGP_OK;
+    if (!target_dev || !out_dev) return fail(ctx, TGP_EINVAL, "NULL target or output");
+    if (is_host_memory(out_dev) || is_host_memory(target_dev))
+        return fail(ctx, TGP_EINVAL, "tgp_fitness_noalloc takes device-resident target and output");
+    HCHK(ctx, hipSetDevice(ctx->device));
+    if (ctx->device >= kMaxDevices || !g_scratch_ptr[ctx->device])
+        return fail(ctx, TGP_EHIP, "no scratch address for device %d: %s", ctx->device,
+                    ctx->device < kMaxDevices ? hipGetErrorString(g_scratch_err[ctx->device]) : "device index");
+    const Plan &P = d->plan;
+    if (!plan_current(ctx, P, dom->cases) || !P.blob || !P.code_roots_dev)
+        return fail(ctx, TGP_EINVAL,
+                    "the DAG has no plan for a domain of %lld cases under this context's settings "
+                    "(evaluate it once with tgp_fitness or tgp_evaluate)", (long long)dom->cases);
+    const int K = choose_K(ctx, dom->cases, P.ext);
+    InterpArgs a;
+    fill_args(a, dom, P.code_roots_dev, nullptr);
+    a.progs = P.reduce_dev;
+    a.n_progs = P.n_reduce;
+    choose_split(ctx, a.n_progs, dom->cases, K, &a.job.n_stripes, &a.job.tiles_per_stripe);
+    const size_t partial_bytes =
+        (sizeof(float2) * (size_t)a.n_progs * (size_t)a.job.n_stripes + 255) & ~(size_t)255;
+    const size_t cache_bytes = sizeof(float) * (size_t)P.n_slots * (size_t)dom->cases;
+    if (partial_bytes + cache_bytes > kNoAllocScratchBytes)
+        return fail(ctx, TGP_ENOMEM,
+                    "needs %zu bytes of scratch (%zu of partial sums, %zu of cache rows); "
+                    "tgp_fitness_noalloc has %zu", partial_bytes + cache_bytes, partial_bytes, cache_bytes,
+                    kNoAllocScratchBytes);
+    // Every (program, stripe) pair and every cache row is written before it
+    // is read, so nothing in the scratch needs clearing between calls.
+    char *base = static_cast<char *>(g_scratch_ptr[ctx->device]);
+    float *cache = P.n_slots ? reinterpret_cast<float *>(base + partial_bytes) : nullptr;
+    ctx->fill_recorded = false;
+    if (P.n_slots) {
+        st = fill_into(ctx, d, dom, K, cache);
+        if (st != TGP_OK) return st;
+    }
+    a.job.cache = cache;
+    a.job.target = target_dev;
+    a.job.partial = reinterpret_cast<float2 *>(base);
+    record(ctx, 2);
+    HCHK(ctx, launch_interp(K, P.D, false, a, ctx->stream, P.ext));
+    record(ctx, 3);
+    record(ctx, 4);
+    HCHK(ctx, launch_finalize(a.job.partial, P.ind_rows_dev, d->n_ind, d->n_ch, a.job.n_stripes,
+                              (double)d->n_ch * (double)dom->cases, loss, out_dev, ctx->stream));
+    record(ctx, 5);
     ctx->times.interp_items = (int64_t)a.n_progs * a.job.n_stripes;
     ctx->times.cases_per_lane = K;
     ctx->times.tiles_per_item = a.job.tiles_per_stripe;

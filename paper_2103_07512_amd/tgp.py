@@ -175,6 +175,7 @@ SIGNATURES = [
     ("tgp_dag_destroy", None, [P]),
     ("tgp_evaluate", I32, [P, P, P, P]),
     ("tgp_fitness", I32, [P, P, P, P, I32, P]),
+    ("tgp_fitness_noalloc", I32, [P, P, P, P, I32, P]),
     ("tgp_last_work", I32, [P, ctypes.POINTER(WorkStats)]),
     ("tgp_ctx_set_timing", I32, [P, I32]),
     ("tgp_last_timing", I32, [P, ctypes.POINTER(Timing)]),
@@ -430,6 +431,15 @@ def fitness(ctx: Context, dag: Dag, dom: Domain, target, loss: int, out):
         ptr = out.data_ptr()
     _check(lib().tgp_fitness(ctx.h, dag.h, dom.h, ctypes.c_void_p(target.data_ptr()), loss,
                              ctypes.c_void_p(ptr)), ctx.h)
+    return out
+
+
+def fitness_noalloc(ctx: Context, dag: Dag, dom: Domain, target, loss: int, out):
+    """tgp_fitness_noalloc: the same fitness into a device tensor out, with
+    no device allocation (the DAG must already be planned for this domain
+    size, e.g. by one fitness() call; scratch is a fixed per-GPU array)."""
+    _check(lib().tgp_fitness_noalloc(ctx.h, dag.h, dom.h, ctypes.c_void_p(target.data_ptr()), loss,
+                                     ctypes.c_void_p(out.data_ptr())), ctx.h)
     return out
 
 
