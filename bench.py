@@ -334,7 +334,7 @@ def kernel_source_hash():
     """Hash of the sources that make up the fused interpreter kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_interp.hip", "interp_gen.inc", "ops_device.h", "tgp_internal.h", "pow_fp64.h",
+    for f in ("k_interp.hip", "interp_gen.inc", "ops_device.h", "tgp_internal.h", "fp32_math.h",
               "div_magic.h"):
         with open(os.path.join(ROOT, "paper_2103_07512_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())

@@ -10,7 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "pow_fp64.h"
+#include "fp32_math.h"
 
 namespace tgp {
 
@@ -19,16 +19,17 @@ __device__ __forceinline__ float f_sub(float a, float b) { return a - b; }
 __device__ __forceinline__ float f_mult(float a, float b) { return a * b; }
 // Correctly rounded IEEE division; 0 for a zero denominator of either sign.
 __device__ __forceinline__ float f_div(float a, float b) { return b == 0.0f ? 0.0f : a / b; }
-// sin(pi x) / cos(pi x) by the device library's sinpi/cospi (exact at every
-// multiple of 1/2); adding +0 turns a -0 result into +0.
-__device__ __forceinline__ float f_sin(float a) { return sinpif(a) + 0.0f; }
-__device__ __forceinline__ float f_cos(float a) { return cospif(a) + 0.0f; }
-__device__ __forceinline__ float f_tan(float a) { return (sinpif(a) + 0.0f) / (cospif(a) + 0.0f); }
+// sin(pi x), cos(pi x), tan(pi x) in FP32 (fp32_math.h): exact quarter-
+// period reduction, minimax polynomials; exact at every multiple of 1/2,
+// zeros returned as +0.
+__device__ __forceinline__ float f_sin(float a) { return sinpi_f32(a); }
+__device__ __forceinline__ float f_cos(float a) { return cospi_f32(a); }
+__device__ __forceinline__ float f_tan(float a) { return tanpi_f32(a); }
 __device__ __forceinline__ float f_exp(float a) { return expf(a); }
 __device__ __forceinline__ float f_log(float a) { return a < 0.0f ? -1.0f : logf(a); }
-// x^y with 0^0 = 0, otherwise C99 pow, carried in FP64 (pow_fp64.h).
+// x^y with 0^0 = 0, otherwise C99 pow, in FP32 (fp32_math.h).
 __device__ __forceinline__ float f_pow(float a, float b) {
-    return (a == 0.0f && b == 0.0f) ? 0.0f : pow_fp64(a, b);
+    return (a == 0.0f && b == 0.0f) ? 0.0f : pow_f32(a, b);
 }
 __device__ __forceinline__ float f_min(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ float f_max(float a, float b) { return fmaxf(a, b); }
@@ -52,23 +53,12 @@ __device__ __forceinline__ float f_mod(float a, float b) {
 __device__ __forceinline__ float f_frac(float a) { return a - floorf(a); }
 __device__ __forceinline__ float f_if(float a, float b, float c) { return a != 0.0f ? b : c; }
 __device__ __forceinline__ float f_step(float a) { return a < 0.0f ? -1.0f : 1.0f; }
-// The polynomial image operators are formed in FP64 and rounded once.
-__device__ __forceinline__ float f_sstep(float a) {
-    double x = a;
-    return (float)(x * x * (3.0 - 2.0 * x));
-}
-__device__ __forceinline__ float f_sstepp(float a) {
-    double x = a;
-    return (float)(x * x * x * (x * (6.0 * x - 15.0) + 10.0));
-}
-__device__ __forceinline__ float f_len(float a, float b) {
-    double x = a, y = b;
-    return (float)sqrt(x * x + y * y);
-}
-__device__ __forceinline__ float f_lerp(float a, float b, float c) {
-    double x = a, y = b, z = c;
-    return (float)(x + (y - x) * (z - floor(z)));
-}
+// The image operators in FP32 (fp32_math.h): sstep and sstepp as short
+// products, len scaled by a power of two, lerp with exact intermediate parts.
+__device__ __forceinline__ float f_sstep(float a) { return sstep_f32(a); }
+__device__ __forceinline__ float f_sstepp(float a) { return sstepp_f32(a); }
+__device__ __forceinline__ float f_len(float a, float b) { return len_f32(a, b); }
+__device__ __forceinline__ float f_lerp(float a, float b, float c) { return lerp_f32(a, b, c); }
 // warp: the nearest point of an axis of n points to position (t - lo) *
 // scale, halves rounded up, clamped to the axis; NaN gives point 0 (fmaxf
 // returns its other operand).
