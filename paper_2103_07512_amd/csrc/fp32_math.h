@@ -1,7 +1,8 @@
 // fp32_math.h -- FP32 implementations of the operators of Table 1 whose
 // value needs more than one correctly rounded FP32 operation: sin(pi x),
 // cos(pi x) and tan(pi x) (Sec. 3.2 prescales trigonometric arguments by
-// pi), x^y, and the image operators sstep, sstepp, len and lerp.
+// pi), x^y, the floored remainder, and the image operators sstep, sstepp,
+// len and lerp.
 //
 // Everything is FP32 arithmetic: exact range reductions, fused multiply-
 // adds, error-free transformations (TwoSum, Fast2Sum, the fma product
@@ -95,19 +96,22 @@ TGP_HD inline float tanpi_f32(float a) {
 }
 
 // ------------------------------------------------------------------- pow
-// 1 / ln 2 as a sum of two FP32 values.
-constexpr float kLog2eHi = 1.4426950216293335f, kLog2eLo = 1.925963033500011e-08f;
+// 2 / ln 2 as a sum of two FP32 values, and 2 / (ln 2 (2k + 1)) for k = 1..5.
+constexpr float kK2Hi = 2.885390043258667f, kK2Lo = 3.851926067000022e-08f;
+constexpr float kQ3 = 0.9617967009544373f, kQ5 = 0.5770780444145203f, kQ7 = 0.41219857335090637f,
+                kQ9 = 0.32059890031814575f, kQ11 = 0.26230818033218384f, kQ13 = 0.22195307910442352f;
 // 2^f = 1 + f E(f) on |f| <= 1/2 (gen_minimax.py, E of degree 6).
 constexpr float kE0 = 0.6931471824645996f, kE1 = 0.24022650718688965f, kE2 = 0.055504102259874344f,
                 kE3 = 0.009618038311600685f, kE4 = 0.0013333935057744384f, kE5 = 0.00015466756303794682f,
                 kE6 = 1.5196156709862407e-05f;
 
-// log2(ax) as hi + lo (|lo| well below ulp(hi)), for finite ax > 0, to
-// about 2^-30 relative.  ax = m 2^e with m in [sqrt(1/2), sqrt(2));
-// log(m) = 2 atanh(s) = 2s (1 + s^2/3 + s^4/5 + ...) with s = (m-1)/(m+1),
+// log2(ax) as hi + lo, for finite ax > 0, to about 2^-30 relative.
+// ax = m 2^e with m in [sqrt(1/2), sqrt(2)); log2(m) = (2 / ln 2) atanh(s)
+// = (2 / ln 2) s (1 + s^2/3 + s^4/5 + ...) with s = (m - 1) / (m + 1),
 // |s| <= 0.1716.  s is formed as s0 + s1 from a Newton reciprocal of m + 1
-// (itself kept as dh + dl) and the fma residual of the quotient; the series
-// beyond 2s is below 1% of it, so FP32 carries it.
+// (itself kept as dh + dl) and the fma residual of the quotient; the leading
+// term (2 / ln 2) s is carried as a double-float, the series beyond it (below
+// 1% of it) in FP32.
 TGP_HD inline void log2_df(float ax, float &hi, float &lo) {
     int e;
     float m = frexpf(ax, &e);  // [1/2, 1), subnormals included
@@ -122,46 +126,23 @@ TGP_HD inline void log2_df(float ax, float &hi, float &lo) {
     r = fmaf(r, fmaf(-dh, r, 1.0f), r);
     r = fmaf(r, fmaf(-dh, r, 1.0f), r);                              // within 5e-8
     const float s0 = u * r;
-    const float res = fmaf(-s0, dl, fmaf(-s0, dh, u));                // u - s0 (dh + dl)
-    const float s1 = res * r;
+    const float s1 = fmaf(-s0, dl, fmaf(-s0, dh, u)) * r;            // s = s0 + s1
     const float z = s0 * s0;
-    const float Q = fmaf(fmaf(fmaf(fmaf(0.09090909361839294f, z, 0.1111111119389534f), z, 0.1428571492433548f), z,
-                              0.20000000298023224f), z, 0.3333333432674408f);
-    const float l0 = s0 + s0;                          // exact
-    const float l1 = fmaf(l0 * z, Q, s1 + s1);          // the rest of ln m
-    const float lh = l0 + l1;                          // Fast2Sum: |l0| > |l1|
-    const float ll = l1 - (lh - l0);
-    const float ph = lh * kLog2eHi;                    // ln m / ln 2
-    const float pl = fmaf(lh, kLog2eHi, -ph) + fmaf(lh, kLog2eLo, ll * kLog2eHi);
+    const float rest = (s0 * z) * fmaf(fmaf(fmaf(fmaf(fmaf(kQ13, z, kQ11), z, kQ9), z, kQ7), z, kQ5), z, kQ3);
+    const float p0 = s0 * kK2Hi;
+    // s1 (1 + z): the leading term's part of s1 and its first-order share
+    // in the series (which was formed from s0 alone)
+    const float p1 = fmaf(s0, kK2Hi, -p0) + fmaf(s0, kK2Lo, fmaf(fmaf(s1, z, s1), kK2Hi, rest));
+    const float ph = p0 + p1;          // Fast2Sum: |p0| > |p1| (the rest is below 1%)
+    const float pl = p1 - (ph - p0);
     const float fe = (float)e;
-    hi = fe + ph;                                      // Fast2Sum: |e| >= 1 > |ph|, or e = 0
+    hi = fe + ph;                      // Fast2Sum: |e| >= 1 > |ph|, or e = 0
     lo = (ph - (hi - fe)) + pl;
 }
 
-// C99 pow on FP32 operands (Annex F special cases), computed in FP32:
-// 2^t with t = y log2|x| carried as hi + lo; 2^t = 2^n 2^f with n = rint(t)
-// and |f| <= 1/2 + tiny.  Results within about 2 half-ulps of x^y.
-TGP_HD inline float pow_f32(float x, float y) {
-    const float ax = fabsf(x), ay = fabsf(y);
-    const bool y_int = ay < INFINITY && y == rintf(y);
-    // every FP32 value of magnitude >= 2^24 is even
-    const bool y_odd = y_int && ay < 16777216.0f && ((int32_t)y & 1) != 0;
-    if (y == 0.0f || x == 1.0f) return 1.0f;  // even when the other operand is NaN
-    if (x != x || y != y) return x + y;       // NaN
-    if (ay == INFINITY) {
-        if (ax == 1.0f) return 1.0f;          // (-1)^(+-inf)
-        return (ax < 1.0f) == (y < 0.0f) ? INFINITY : 0.0f;
-    }
-    if (x == 0.0f) {
-        if (y < 0.0f) return y_odd ? copysignf(INFINITY, x) : INFINITY;
-        return y_odd ? x : 0.0f;
-    }
-    if (ax == INFINITY) {
-        if (x > 0.0f) return y < 0.0f ? 0.0f : INFINITY;
-        if (y < 0.0f) return y_odd ? -0.0f : 0.0f;
-        return y_odd ? -INFINITY : INFINITY;
-    }
-    if (x < 0.0f && !y_int) return bits_to_float(0x7fc00000u);  // NaN
+// |x|^y for finite x != 0, 1 and finite y != 0: 2^t with t = y log2|x|
+// carried as hi + lo; 2^t = 2^n 2^f with n = rint(t) and |f| <= 1/2 + tiny.
+TGP_HD inline float pow_core(float ax, float y) {
     float th, tl;
     log2_df(ax, th, tl);
     const float h0 = y * th;
@@ -177,8 +158,58 @@ TGP_HD inline float pow_f32(float x, float y) {
     // 2^n p in two steps, so that n's full range stays within the exponent
     const int ni = (int)n;
     const int n1 = ni / 2;
-    const float r = ldexpf(ldexpf(p, n1), ni - n1);
-    return x < 0.0f && y_odd ? -r : r;
+    return ldexpf(ldexpf(p, n1), ni - n1);
+}
+
+// C99 pow on FP32 operands (Annex F special cases), computed in FP32.
+// The common case (x finite, nonzero, not 1; y finite, nonzero; an
+// integral y when x < 0) takes one path; results within about 4 half-ulps.
+TGP_HD inline float pow_f32(float x, float y) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const bool y_int = y == rintf(y);         // false for NaN; true for +-inf
+    // every FP32 value of magnitude >= 2^24 is even
+    const bool y_odd = y_int && ay < 16777216.0f && ((int32_t)y & 1) != 0;
+    if (ax > 0.0f && ax < INFINITY && ay < INFINITY && y != 0.0f && x != 1.0f && (x > 0.0f || y_int)) {
+        const float r = pow_core(ax, y);
+        return x < 0.0f && y_odd ? -r : r;
+    }
+    if (y == 0.0f || x == 1.0f) return 1.0f;  // even when the other operand is NaN
+    if (x != x || y != y) return x + y;       // NaN
+    if (ay == INFINITY) {
+        if (ax == 1.0f) return 1.0f;          // (-1)^(+-inf)
+        return (ax < 1.0f) == (y < 0.0f) ? INFINITY : 0.0f;
+    }
+    if (x == 0.0f) {
+        if (y < 0.0f) return y_odd ? copysignf(INFINITY, x) : INFINITY;
+        return y_odd ? x : 0.0f;
+    }
+    if (ax == INFINITY) {
+        if (x > 0.0f) return y < 0.0f ? 0.0f : INFINITY;
+        if (y < 0.0f) return y_odd ? -0.0f : 0.0f;
+        return y_odd ? -INFINITY : INFINITY;
+    }
+    return bits_to_float(0x7fc00000u);        // x < 0 with a non-integral y: NaN
+}
+
+// ------------------------------------------------------------------- mod
+// The floored remainder of Table 1's mod (the result takes the divisor's
+// sign), b != 0: exact.  With q = floor(RN(a / b)) and |a / b| < 2^23, q is
+// floor(a / b) or one more (rounding is monotone and the integers there are
+// FP32 values), so a - q b has magnitude below |b|, is a multiple of ulp(b)
+// or of ulp(a), and the fma gives it exactly; one more b fixes the sign
+// when q was one too many.  A zero result takes the sign of a (as fmod's
+// does).  Other operands (a quotient of 2^23 or more, a non-finite a or b)
+// go through the library's exact fmodf.
+TGP_HD inline float floor_mod_f32(float a, float b) {
+    const float q = floorf(a / b);
+    if (fabsf(q) < 8388608.0f && fabsf(a) < INFINITY && fabsf(b) < INFINITY) {
+        float r = fmaf(-q, b, a);
+        if (r != 0.0f && ((r < 0.0f) != (b < 0.0f))) r += b;
+        return r == 0.0f ? copysignf(0.0f, a) : r;
+    }
+    float r = fmodf(a, b);
+    if (r != 0.0f && ((r < 0.0f) != (b < 0.0f))) r += b;
+    return r;
 }
 
 // ------------------------------------------------------- image operators

@@ -42,14 +42,9 @@ __device__ __forceinline__ float f_sign(float a) {
 }
 __device__ __forceinline__ float f_abs(float a) { return fabsf(a); }
 __device__ __forceinline__ float f_clip(float a, float b, float c) { return fmaxf(fminf(a, c), b); }
-// Floored remainder: the exact truncated remainder, moved into the divisor's
-// sign when the two signs differ.
-__device__ __forceinline__ float f_mod(float a, float b) {
-    if (b == 0.0f) return 0.0f;
-    float r = fmodf(a, b);
-    if (r != 0.0f && ((r < 0.0f) != (b < 0.0f))) r += b;
-    return r;
-}
+// Floored remainder (the divisor's sign), rounded once from its exact value
+// (fp32_math.h); 0 for a zero divisor of either sign.
+__device__ __forceinline__ float f_mod(float a, float b) { return b == 0.0f ? 0.0f : floor_mod_f32(a, b); }
 __device__ __forceinline__ float f_frac(float a) { return a - floorf(a); }
 __device__ __forceinline__ float f_if(float a, float b, float c) { return a != 0.0f ? b : c; }
 __device__ __forceinline__ float f_step(float a) { return a < 0.0f ? -1.0f : 1.0f; }

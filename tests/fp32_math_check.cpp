@@ -158,7 +158,7 @@ int main() {
                     ++fails;
                 }
             } else {
-                ps.add(got, pow((double)x, (double)y), 4.0, x, y);
+                ps.add(got, pow((double)x, (double)y), 3.0, x, y);
             }
         }
     for (int i = 0; i < 8000000; ++i) {
@@ -173,8 +173,42 @@ int main() {
             y = (float)((u01(rng) < 0.5 ? 1.0 : -1.0) * (90.0 + u01(rng) * 60.0) / log(fmax(fabs(log((double)x)), 1e-3)));
             break;
         }
-        ps.add(tgp::pow_f32(x, y), pow((double)x, (double)y), 4.0, x, y);
+        ps.add(tgp::pow_f32(x, y), pow((double)x, (double)y), 3.0, x, y);
     }
+
+    // floored mod: bit for bit the exact floored remainder rounded once
+    // (fmod in FP64 of FP32 operands is exact; moving it into the divisor's
+    // sign is one FP64 addition, exact too, then one rounding to FP32)
+    long mod_n = 0, mod_bad = 0;
+    auto mod_ref = [](float a, float b) -> float {
+        double r = fmod((double)a, (double)b);
+        if (r != 0.0 && ((r < 0.0) != (b < 0.0f))) r += (double)b;
+        return (float)r;
+    };
+    auto mod_check = [&](float a, float b) {
+        ++mod_n;
+        const float got = tgp::floor_mod_f32(a, b), want = mod_ref(a, b);
+        if (!((got != got && want != want) || bits(got) == bits(want))) {
+            if (mod_bad < 8) printf("mod(%a, %a) = %a, want %a\n", a, b, got, want);
+            ++mod_bad;
+        }
+    };
+    for (int i = 0; i < 8000000; ++i) {
+        float a, b;
+        switch (i % 5) {
+        case 0: a = (float)(u01(rng) * 8 - 4); b = (float)(u01(rng) * 4 - 2); break;
+        case 1: a = (float)((u01(rng) - 0.5) * exp(u01(rng) * 60 - 30)); b = (float)((u01(rng) - 0.5) * exp(u01(rng) * 60 - 30)); break;
+        case 2: b = (float)((u01(rng) - 0.5) * 4); a = b * (float)rint(u01(rng) * 2e7 - 1e7) * (float)(1 + (u01(rng) - 0.5) * 1e-6); break;
+        case 3: b = (float)((u01(rng) - 0.5) * 4); a = (float)(rint(u01(rng) * 40 - 20)) * b; break;  // exact multiples
+        default: a = (float)((u01(rng) - 0.5) * 1e-38); b = (float)((u01(rng) - 0.5) * 4); break;     // subnormal remainders
+        }
+        if (b != 0.0f) mod_check(a, b);
+    }
+    for (float a : sv)
+        for (float b : sv)
+            if (b != 0.0f) mod_check(a, b);
+    printf("mod     %9ld cases, %ld differ from the exact floored remainder rounded once\n", mod_n, mod_bad);
+    fails += mod_bad ? 1 : 0;
 
     // sstep, sstepp, len, lerp
     Stat s1{"sstep"}, s2{"sstepp"}, ls{"len"}, lr{"lerp"};
