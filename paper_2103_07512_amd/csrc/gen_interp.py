@@ -3,17 +3,25 @@
 
 The interpreter keeps the operand stack of a postfix program in registers.
 One wave runs one program and each lane owns K fitness cases, so the stack
-depth S before every instruction is the same for all lanes (a scalar).  The
-stack slots are plain named values s0..s{D-1} (each a vector of K lanes'
-cases), and one dispatch loop switches on the pair (S, opcode): the case of
-an operator of arity a at depth S reads s{S-a}..s{S-1}, writes s{S-a} and
-sets S to S-a+1, so no register is ever indexed at run time.  A single loop
+depth S before every instruction is the same for all lanes.  The stack
+slots are plain named values s0..s{D-1} (each a vector of K lanes' cases),
+and one dispatch loop switches on the pair (S, opcode): the case of an
+operator of arity a at depth S reads s{S-a}..s{S-1} and writes s{S-a}, so no
+register is ever indexed at run time.  The depth of every instruction is
+known when the program is emitted, so the emitter writes the pair itself
+into the instruction word, (S << 8) | code, and the loop switches on the
+loaded word as it is: no depth is carried from one instruction to the next.  A single loop
 around a single switch keeps the control flow simple for the compiler: with
 one dispatch block per depth, jumping between blocks, the blocks became a
 nest of loops whose multi-level exits the compiler implemented with boolean
 flags in scalar registers (tens of scalar moves and register spills per
 dispatched instruction); the flat loop costs a branch tree over the case
 keys.
+
+Superinstructions (Ertl and Gregg): a binary operator whose last-evaluated
+operand is a terminal -- x, y, a constant or a cached subtree row -- reads
+that operand itself (code FUSE_BASE + 16 * kind + v, v the index in FUSED),
+which saves the terminal's own dispatch and the copy into a stack slot.
 
 Operators with long bodies (transcendentals, floored modulo, the FP64 image
 operators) are compiled once as out-of-line functions that take and return
@@ -61,6 +69,61 @@ CALLED = {"sin", "cos", "tan", "exp", "log", "pow", "mod", "sstep", "sstepp", "l
 BITWISE = ("or", "xor", "and")
 DEPTHS = [8]
 ARGS = "abc"
+# Fused forms: (operator, reversed) in the order of kFuseOps (tgp_internal.h);
+# reversed means the terminal is the operator's first operand.
+FUSE_BASE = 96
+FUSED = [("add", False), ("sub", False), ("mult", False), ("div", False), ("pow", False),
+         ("min", False), ("max", False), ("mdist", False), ("mod", False), ("len", False),
+         ("sub", True), ("div", True), ("pow", True), ("mod", True)]
+# terminal kinds of a fused operand: (code offset name, how to read case k)
+FUSE_KINDS = [("kFuseX", "xv.v[k]"), ("kFuseY", "yv.v[k]"), ("kFuseConst", "c"), ("kFuseCache", "row[cidx[k]]")]
+
+
+def fused_checks():
+    """static_asserts tying FUSED to the C++ table the emitter uses."""
+    L = ["// The fused forms' table as the emitter sees it (tgp_internal.h)."]
+    for v, (name, rev) in enumerate(FUSED):
+        op = dict((n, o) for n, o, _ in FUNCS)[name]
+        L.append(f"static_assert(kFuseOps[{v}] == {op} && kFuseRev[{v}] == {'true' if rev else 'false'}, "
+                 f"\"fused form {v}: {name}{' reversed' if rev else ''}\");")
+    L.append(f"static_assert(kFuseBase == {FUSE_BASE} && kNumFused == {len(FUSED)}, \"fused form table\");")
+    L.append("")
+    return "\n".join(L)
+
+
+def fused_case(e, key_expr, name, rev, kind, read, dst, ind, end):
+    """One fused case: dst = name(dst, T) (or name(T, dst) when reversed),
+    T the terminal operand of the given kind; ends with `end`."""
+    e(f"{ind}case {key_expr}: {{")
+    if kind == "kFuseConst":
+        e(f"{ind}    const float c = __uint_as_float(ins.y);")
+    if kind == "kFuseCache":
+        e(f"{ind}    const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+    if name in CALLED:
+        if kind in ("kFuseX", "kFuseY"):
+            tv = "xv" if kind == "kFuseX" else "yv"
+        else:
+            e(f"{ind}    FV<K> tv;")
+            e("#pragma unroll")
+            e(f"{ind}    for (int k = 0; k < K; ++k) tv.v[k] = {read};")
+            tv = "tv"
+        args = f"{tv}, {dst}" if rev else f"{dst}, {tv}"
+        e(f"{ind}    {dst} = vcall_{name}<K>({args});")
+    else:
+        if kind == "kFuseCache":
+            e(f"{ind}    float tv[K];")
+            e("#pragma unroll")
+            e(f"{ind}    for (int k = 0; k < K; ++k) tv[k] = {read};")
+            read = "tv[k]"
+        a, b = (read, f"{dst}.v[k]") if rev else (f"{dst}.v[k]", read)
+        e("#pragma unroll")
+        e(f"{ind}    for (int k = 0; k < K; ++k) {dst}.v[k] = f_{name}({a}, {b});")
+    e(f"{ind}    {end}")
+    e(f"{ind}}}")
+
+
+def fused_key(kind, v):
+    return f"(kFuseBase + 16u * {kind} + {v}u)"
 
 
 def called_functions():
@@ -93,14 +156,10 @@ def body_for_depth(D):
     e("        const int32_t (&cidx)[K], const WarpGeom &wg, FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
-    e("    uint2 ins, nxt = *ip;")
-    e("    ++ip;")
-    e("    uint32_t S = 0;")
+    e("    uint2 ins;")
     e("    for (;;) {")
-    e("    ins = nxt;")
-    e("    nxt = *ip;")
-    e("    ++ip;")
-    e("    switch ((S << 8) | (ins.x & 0xffu)) {")
+    e("    ins = *++ip;")
+    e("    switch (ins.x) {")
     variants = []
     for name, op, ar in FUNCS:
         if name in BITWISE[1:]:
@@ -117,18 +176,18 @@ def body_for_depth(D):
         key = lambda c: f"({S}u << 8) | {c}"
         if S < D:
             for name, reg in (("I_X", "xv"), ("I_Y", "yv"), ("I_Z", "zv")):
-                e(f"    case {key(name)}: s{S} = {reg}; S = {S + 1}; continue;")
+                e(f"    case {key(name)}: s{S} = {reg}; continue;")
             e(f"    case {key('I_CONST')}: {{")
             e("        const float c = __uint_as_float(ins.y);")
             e("#pragma unroll")
             e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = c;")
-            e(f"        S = {S + 1}; continue;")
+            e("        continue;")
             e("    }")
             e(f"    case {key('I_CACHE')}: {{")
             e("        const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
             e("#pragma unroll")
             e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];")
-            e(f"        S = {S + 1}; continue;")
+            e("        continue;")
             e("    }")
         if S == 1:
             e(f"    case {key('I_END')}: res = s0; return;")
@@ -138,7 +197,7 @@ def body_for_depth(D):
             e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
             e("#pragma unroll")
             e(f"            for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row[warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], cidx[k])];")
-            e(f"            S = {S - 1}; continue;")
+            e("            continue;")
             e("        } else {")
             e("            goto BAD;")
             e("        }")
@@ -150,21 +209,26 @@ def body_for_depth(D):
             if name == BITWISE[0]:
                 e(f"    case {key(c)}:")
                 e("        if constexpr (EXT) {")
-                e("            const uint32_t kind = (ins.x >> 8) & 3u;")
+                e("            const uint32_t kind = ins.y;")
                 e("#pragma unroll")
                 e(f"            for (int k = 0; k < K; ++k) s{dst}.v[k] = f_bitop({src[0]}.v[k], {src[1]}.v[k], kind);")
-                e(f"            S = {dst + 1}; continue;")
+                e("            continue;")
                 e("        } else {")
                 e("            goto BAD;")
                 e("        }")
             elif name in CALLED:
-                e(f"    case {key(c)}: s{dst} = vcall_{name}<K>({', '.join(src)}); S = {dst + 1}; continue;")
+                e(f"    case {key(c)}: s{dst} = vcall_{name}<K>({', '.join(src)}); continue;")
             else:
                 e(f"    case {key(c)}:")
                 e("#pragma unroll")
                 args = ", ".join(f"{x}.v[k]" for x in src)
                 e(f"        for (int k = 0; k < K; ++k) s{dst}.v[k] = f_{name}({args});")
-                e(f"        S = {dst + 1}; continue;")
+                e("        continue;")
+        if S >= 1:
+            for kind, read in FUSE_KINDS:
+                for v, (name, rev) in enumerate(FUSED):
+                    fused_case(e, f"({S}u << 8) | {fused_key(kind, v)}", name, rev, kind, read, f"s{S - 1}",
+                               "    ", "continue;")
     e("    default: goto BAD;")
     e("    }")
     e("    }")
@@ -260,7 +324,7 @@ def body_lds():
             e(f"            const FV<K> {names[ar - 1]} = t;")
             args = [names[order.index(i)] for i in range(ar)]
             if name == BITWISE[0]:
-                e("            const uint32_t kind = (ins.x >> 8) & 3u;")
+                e("            const uint32_t kind = ins.y;")
                 e("#pragma unroll")
                 e(f"            for (int k = 0; k < K; ++k) t.v[k] = f_bitop({args[0]}.v[k], {args[1]}.v[k], kind);")
             elif name in CALLED:
@@ -270,6 +334,9 @@ def body_lds():
                 e(f"            for (int k = 0; k < K; ++k) t.v[k] = f_{name}({', '.join(a + '.v[k]' for a in args)});")
             e("            break;")
             e("        }")
+    for kind, read in FUSE_KINDS:
+        for v, (name, rev) in enumerate(FUSED):
+            fused_case(e, fused_key(kind, v), name, rev, kind, read, "t", "        ", "break;")
     e("        default:")
     e("#pragma unroll")
     e("            for (int k = 0; k < K; ++k) res.v[k] = __builtin_nanf(\"\");")
@@ -286,6 +353,7 @@ def generate():
            "// Stack-depth-specialised postfix interpreters, one per stack size.",
            f"// Stack sizes: {', '.join(map(str, DEPTHS))}.",
            "",
+           fused_checks(),
            called_functions()]
     for D in DEPTHS:
         out.append(body_for_depth(D))

@@ -93,7 +93,7 @@ __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const
     if constexpr (D == kLdsSlots)
         run_prog_lds<K>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, sl, lane, res);
     else
-        run_prog_d8<K, EXT>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, res);
+        run_prog_d8<K, EXT>(ip - 1, xv, yv, zv, cache, cache_stride, cidx, wg, res);  // fetches pre-increment
 }
 
 // This wave's LDS stack rows (one wave per workgroup).

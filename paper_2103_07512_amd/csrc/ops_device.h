@@ -27,8 +27,41 @@ __device__ __forceinline__ float f_cos(float a) { return cospi_f32(a); }
 __device__ __forceinline__ float f_tan(float a) { return tanpi_f32(a); }
 __device__ __forceinline__ float f_exp(float a) { return expf(a); }
 __device__ __forceinline__ float f_log(float a) { return a < 0.0f ? -1.0f : logf(a); }
-// x^y with 0^0 = 0, otherwise C99 pow, in FP32 (fp32_math.h).
+// x^y with 0^0 = 0, otherwise C99 pow.  The common case -- a finite
+// nonzero base (positive, or negative with an integer exponent), |y| <= 2,
+// and a result in the normal range -- goes through the hardware base-2
+// logarithm and exponential (v_log_f32, v_exp_f32; both within one ulp,
+// v_log_f32 measured exhaustively over [0.70, 1.42]): x = 2^e m with m in
+// [sqrt(1/2), sqrt(2)), t = y e + y log2(m) is carried as a double-FP32 sum
+// (the products split exactly by fma, the sum by TwoSum), and
+// 2^t = 2^t_hi (1 + t_lo ln 2).  The error of log2(m) (at most 2^-24.37)
+// times |y| <= 2, the exponential's ulp and the last rounding keep the
+// result within 2.4 ulp.  A finite negative base with a finite non-integer
+// exponent gives NaN at once; everything else takes pow_f32 (fp32_math.h).
 __device__ __forceinline__ float f_pow(float a, float b) {
+    const float ax = fabsf(a), ab = fabsf(b);
+    const bool yint = rintf(b) == b;
+    if (a < 0.0f && ax < __builtin_inff() && !yint && ab < __builtin_inff()) return __builtin_nanf("");
+    if (ab <= 2.0f && ax > 0.0f && ax < __builtin_inff()) {
+        float m = __builtin_amdgcn_frexp_mantf(ax);
+        int e = __builtin_amdgcn_frexp_expf(ax);
+        if (m < 0.70710678f) {
+            m += m;
+            e -= 1;
+        }
+        const float fe = (float)e;
+        const float lm = __builtin_amdgcn_logf(m);
+        const float p = b * fe, pe = fmaf(b, fe, -p);
+        const float q = b * lm, qe = fmaf(b, lm, -q);
+        const float th = p + q;
+        const float bb = th - p;
+        const float tl = ((p - (th - bb)) + (q - bb)) + (pe + qe);
+        if (th >= -125.0f && th <= 127.0f) {
+            float r = __builtin_amdgcn_exp2f(th);
+            r = fmaf(r, tl * 0.693147182f, r);
+            return (a < 0.0f && ab == 1.0f) ? -r : r;
+        }
+    }
     return (a == 0.0f && b == 0.0f) ? 0.0f : pow_f32(a, b);
 }
 __device__ __forceinline__ float f_min(float a, float b) { return fminf(a, b); }
@@ -42,9 +75,27 @@ __device__ __forceinline__ float f_sign(float a) {
 }
 __device__ __forceinline__ float f_abs(float a) { return fabsf(a); }
 __device__ __forceinline__ float f_clip(float a, float b, float c) { return fmaxf(fminf(a, c), b); }
-// Floored remainder (the divisor's sign), rounded once from its exact value
-// (fp32_math.h); 0 for a zero divisor of either sign.
-__device__ __forceinline__ float f_mod(float a, float b) { return b == 0.0f ? 0.0f : floor_mod_f32(a, b); }
+// Floored remainder (the divisor's sign), rounded once from its exact value;
+// 0 for a zero divisor of either sign.  The quotient comes from the
+// hardware reciprocal (within one ulp) when |a / b| < 2^20 and 2^-125 <= |b|
+// <= 2^125: q0 = a rcp(b) is then within 2^-22.5 |a/b| of a/b, raised by
+// |q0| 2^-21 it is never below a/b and stays below a/b + 1, so its floor q
+// is floor(a/b) or one more.  Either way a - q b lies within |b| of zero and
+// the fma gives it exactly, and one more b fixes the sign when q was one
+// too many: the same correctly rounded value as floor_mod_f32
+// (fp32_math.h), which takes every other operand.
+__device__ __forceinline__ float f_mod(float a, float b) {
+    if (b == 0.0f) return 0.0f;
+    const float ab = fabsf(b);
+    const float q0 = a * __builtin_amdgcn_rcpf(b);
+    if (fabsf(q0) < 1048576.0f && ab >= 0x1p-125f && ab <= 0x1p125f) {
+        const float q = floorf(fmaf(fabsf(q0), 0x1p-21f, q0));
+        float r = fmaf(-q, b, a);
+        if (r != 0.0f && ((r < 0.0f) != (b < 0.0f))) r += b;
+        return r == 0.0f ? copysignf(0.0f, a) : r;
+    }
+    return floor_mod_f32(a, b);
+}
 __device__ __forceinline__ float f_frac(float a) { return a - floorf(a); }
 __device__ __forceinline__ float f_if(float a, float b, float c) { return a != 0.0f ? b : c; }
 __device__ __forceinline__ float f_step(float a) { return a < 0.0f ? -1.0f : 1.0f; }

@@ -991,25 +991,69 @@ struct Planner {
         return TGP_OK;
     }
 
+    // The fused-form kind and .y word of child c when c can be a fused
+    // operand (x, y, a constant or a cached row), else -1.
+    int fuse_operand(int32_t c, uint32_t &y) const {
+        if (cached[c]) {
+            y = (uint32_t)slot[c];
+            return kFuseCache;
+        }
+        const int o = op(c);
+        if (o == TGP_VAR) {
+            const int v = (d.op[c] >> 8) & 0xff;
+            return v == 0 ? kFuseX : (v == 1 ? kFuseY : -1);
+        }
+        if (o == TGP_CONST) {
+            memcpy(&y, !folded.empty() && folded[c] ? &fold_val[c] : &d.value[c], 4);
+            return kFuseConst;
+        }
+        return -1;
+    }
+
     // Postfix program of node n (n itself is expanded even when cached).
-    // Adds the cost-model slots of its instructions to *valu; sets *ext when
-    // it emits a bitwise operator or warp, *warp_used for warp.
+    // Every instruction carries the stack depth before it (.x bits 8-15).
+    // A binary operator whose last-evaluated child is a terminal takes its
+    // fused form and reads that child itself.  Adds the cost-model slots of
+    // its instructions to *valu; sets *ext when it emits a bitwise operator
+    // or warp, *warp_used for warp.
     void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads, double *valu, bool *ext,
               bool *warp_used) const {
-        std::vector<std::pair<int32_t, int32_t>> st;  // (node, children emitted)
-        st.push_back({root, 0});
+        struct Frame {
+            int32_t n, done;  // node, children emitted
+            int32_t fv;       // fused form index, or -1
+        };
+        std::vector<Frame> st;
+        uint32_t S = 0;  // stack depth before the next instruction
+        auto frame = [&](int32_t n) {
+            Frame f{n, 0, -1};
+            const int o = op(n);
+            if (n == root || !cached[n]) {
+                if (arity(n) == 2 && o != TGP_WARP) {
+                    const int last = kPerms[perm[n]][1];
+                    uint32_t y = 0;
+                    if (fuse_operand(d.kid[3 * n + last], y) >= 0) {
+                        const bool rev = last == 0 && !is_commutative(o);
+                        f.fv = fused_index(o, rev);
+                    }
+                }
+            }
+            return f;
+        };
+        st.push_back(frame(root));
         while (!st.empty()) {
-            auto &top = st.back();
-            const int32_t n = top.first;
+            Frame &top = st.back();
+            const int32_t n = top.n;
             const bool leafish = arity(n) == 0 || (n != root && cached[n]);
             const bool warp = op(n) == TGP_WARP;  // stack children t0, t1 only
-            if (!leafish && top.second < (warp ? 2 : arity(n))) {
-                const int32_t c = warp ? d.kid[3 * n + 1 + top.second] : d.kid[3 * n + kPerms[perm[n]][top.second]];
-                ++top.second;
-                st.push_back({c, 0});
+            const int stacked = leafish ? 0 : (warp ? 2 : arity(n)) - (top.fv >= 0 ? 1 : 0);
+            if (top.done < stacked) {
+                const int32_t c = warp ? d.kid[3 * n + 1 + top.done] : d.kid[3 * n + kPerms[perm[n]][top.done]];
+                ++top.done;
+                st.push_back(frame(c));
                 continue;
             }
             uint2 ins{0, 0};
+            uint32_t after = S + 1;
             if (n != root && cached[n]) {
                 ins.x = I_CACHE;
                 ins.y = (uint32_t)slot[n];
@@ -1024,26 +1068,44 @@ struct Planner {
                 } else if (o == TGP_CONST) {
                     ins.x = I_CONST;
                     memcpy(&ins.y, !folded.empty() && folded[n] ? &fold_val[n] : &d.value[n], 4);
+                } else if (top.fv >= 0) {
+                    const int32_t c = d.kid[3 * n + kPerms[perm[n]][1]];
+                    const int kind = fuse_operand(c, ins.y);
+                    ins.x = kFuseBase + 16 * (uint32_t)kind + (uint32_t)top.fv;
+                    if (kind == kFuseCache) {
+                        ++cache_reads;
+                        *valu += 1.0;
+                    } else {
+                        *valu += kOpCost[op(c)];
+                    }
+                    after = S;
                 } else if (o == TGP_OR || o == TGP_XOR || o == TGP_AND) {
-                    ins.x = (kFnBase + TGP_OR) | ((uint32_t)(o - TGP_OR) << 8);
+                    ins.x = kFnBase + TGP_OR;
+                    ins.y = (uint32_t)(o - TGP_OR);
                     *ext = true;
+                    after = S - 1;
                 } else if (o == TGP_WARP) {
                     ins.x = I_WARP;
                     *ext = *warp_used = true;
                     ins.y = (uint32_t)slot[d.kid[3 * n]];
                     ++cache_reads;
-                } else if (perm[n] == 0 || (kArity[o] == 2 && is_commutative(o))) {
-                    ins.x = kFnBase + o;
-                } else if (kArity[o] == 2) {
-                    ins.x = kRevBase + o;
+                    after = S - 1;
                 } else {
-                    ins.x = kPermBase + 6 * ternary_index(o) + perm[n];
+                    if (perm[n] == 0 || (kArity[o] == 2 && is_commutative(o)))
+                        ins.x = kFnBase + o;
+                    else if (kArity[o] == 2)
+                        ins.x = kRevBase + o;
+                    else
+                        ins.x = kPermBase + 6 * ternary_index(o) + perm[n];
+                    after = S + 1 - (uint32_t)kArity[o];
                 }
             }
+            ins.x |= S << 8;
+            S = after;
             code.push_back(ins);
             st.pop_back();
         }
-        code.push_back(uint2{I_END, 0});
+        code.push_back(uint2{(S << 8) | I_END, 0});
     }
 };
 
@@ -1367,7 +1429,7 @@ static tgp_status plan_decide_emit_fill(PlanJob &w, int D, bool reorder, double 
         fill.insert(fill.end(), by_level[l].begin(), by_level[l].end());
     }
     P.level_first[max_level + 1] = (int32_t)fill.size();
-    code.push_back(uint2{I_END, 0});  // padding: the interpreter reads one instruction ahead
+    code.push_back(uint2{I_END, 0});  // padding past the last program
     P.D = D;
     P.reorder = reorder;
     P.access_cost = access_cost;

@@ -315,7 +315,7 @@ void prepare(tgp_server s, tgp_ctx pc, const ReqP &rp) {
     // Programs with slots mapped to arena rows (in arena units).
     r.plan = P;
     for (uint2 &ins : r.plan.code_host)
-        if (ins.x == I_CACHE || ins.x == I_WARP) ins.y = (uint32_t)r.entry[ins.y]->off;
+        if (reads_cache_row(ins.x)) ins.y = (uint32_t)r.entry[ins.y]->off;
     for (ProgDesc &pd : r.plan.fill_host) pd.dest = (int32_t)r.entry[pd.dest]->off;
     // Slabs and work split, from this request alone.
     const int64_t cases = r.dom->cases;

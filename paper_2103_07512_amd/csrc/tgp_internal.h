@@ -45,23 +45,54 @@ static_assert(TGP_NUM_OPS <= 32, "two bits per opcode in 64 bits");
 // Arity of a valid opcode (op < TGP_NUM_OPS).
 __host__ __device__ constexpr int arity_of(uint32_t op) { return (int)((kArityPacked >> (2 * op)) & 3u); }
 
-// Interpreter instruction codes.  An instruction is a uint2: .x = code, .y =
-// the FP32 bits of a constant (I_CONST) or the cache row (I_CACHE: the row
-// starts cache_stride floats times .y past the job's cache base).  Function
-// opcodes are the public opcode plus kFnBase; the three bitwise operators
-// share the code of TGP_OR, with 0 / 1 / 2 (or / xor / and) in bits 8-9.
-// Operators whose children were evaluated out of left-to-right order (to
-// bound the stack, Sethi-Ullman order) use the permuted forms: kRevBase + op
-// for a reversed non-commutative binary operator, kPermBase + 6 t + p for
-// ternary operator t (clip, if, lerp) whose children were evaluated in the
-// order kPerms[p].
+// Interpreter instructions.  An instruction is a uint2.  .x = (S << 8) |
+// code, where S is the depth of the operand stack before the instruction
+// (the emitter knows it; the register-stack interpreter dispatches on the
+// whole word, the LDS-stack one on code alone).  .y = the FP32 bits of a
+// constant (I_CONST, constant-operand fused forms), a cache row (I_CACHE,
+// I_WARP, cache-operand fused forms: the row starts cache_stride floats
+// times .y past the job's cache base), or the kind of a bitwise operator
+// (0 or, 1 xor, 2 and; the three share the code of TGP_OR).  Function codes
+// are the public opcode plus kFnBase.  Operators whose children were
+// evaluated out of left-to-right order (to bound the stack, Sethi-Ullman
+// order) use the permuted forms: kRevBase + op for a reversed
+// non-commutative binary operator, kPermBase + 6 t + p for ternary operator
+// t (clip, if, lerp) whose children were evaluated in the order kPerms[p].
+// Fused forms (superinstructions): a binary operator whose last-evaluated
+// operand is x, y, a constant or a cache row reads that operand itself,
+// code kFuseBase + 16 * kind + v, with kind one of kFuseX .. kFuseCache and
+// v the index of (operator, reversed) in kFuseOps / kFuseRev; reversed
+// means the terminal is the operator's first operand.  A fused form at depth
+// S reads slot S - 1 and writes it.
 enum : uint32_t {
     I_X = 0, I_Y = 1, I_Z = 2, I_CONST = 3, I_CACHE = 4, I_END = 5,
     I_WARP = 6,  // pops t0, t1; pushes cache row .y at the point they name
     kFnBase = 8,
     kRevBase = 40,
     kPermBase = 72,
+    kFuseBase = 96,
+    kFuseX = 0, kFuseY = 1, kFuseConst = 2, kFuseCache = 3,
 };
+constexpr int kNumFused = 14;
+constexpr int kFuseOps[kNumFused] = {TGP_ADD, TGP_SUB, TGP_MULT, TGP_DIV, TGP_POW, TGP_MIN,  TGP_MAX,
+                                     TGP_MDIST, TGP_MOD, TGP_LEN, TGP_SUB, TGP_DIV, TGP_POW, TGP_MOD};
+constexpr bool kFuseRev[kNumFused] = {false, false, false, false, false, false, false,
+                                      false, false, false, true,  true,  true,  true};
+
+// Index v of (op, reversed) in kFuseOps / kFuseRev, or -1 if it has no
+// fused form.
+inline int fused_index(int op, bool rev) {
+    for (int v = 0; v < kNumFused; ++v)
+        if (kFuseOps[v] == op && kFuseRev[v] == rev) return v;
+    return -1;
+}
+// The code of an instruction word.
+__host__ __device__ constexpr uint32_t ins_code(uint32_t x) { return x & 0xffu; }
+// Whether the instruction's .y names a cache row.
+inline bool reads_cache_row(uint32_t x) {
+    const uint32_t c = ins_code(x);
+    return c == I_CACHE || c == I_WARP || (c >= kFuseBase + 16 * kFuseCache && c < kFuseBase + 16 * (kFuseCache + 1));
+}
 
 constexpr uint8_t kPerms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
@@ -89,7 +120,7 @@ struct ProgDesc {
 // case case_base (all of it, or one slab of it); every per-case array below
 // is indexed by the global case index case_base + i.
 struct JobDesc {
-    const uint2 *code;           // all instructions of the job, padded by one I_END
+    const uint2 *code;           // all instructions of the job, then one I_END
     int32_t n_stripes;           // work items per program
     int32_t tiles_per_stripe;    // tiles of 64*K cases per work item
     int32_t n_cases;             // cases of the job

@@ -156,6 +156,7 @@ bool run(const Plan &P, const ProgDesc &pd, int D, float x, float y, const std::
     for (uint32_t i = 0; i < pd.len; ++i) {
         const uint2 ins = P.code_host[pd.code_off + i];
         const uint32_t c = ins.x & 0xffu;
+        if ((int)(ins.x >> 8) != sp) return false;  // the depth the word carries
         if (c == I_END) {
             if (sp != 1) return false;
             *out = s[0];
@@ -172,6 +173,20 @@ bool run(const Plan &P, const ProgDesc &pd, int D, float x, float y, const std::
                 if (reads) reads->push_back((int32_t)ins.y);
             } else return false;  // no z axis here
             s[sp++] = v;
+            continue;
+        }
+        if (c >= kFuseBase) {  // fused form: the terminal operand is read here
+            const uint32_t kind = (c - kFuseBase) / 16, v = (c - kFuseBase) % 16;
+            if (kind > kFuseCache || v >= (uint32_t)kNumFused || sp < 1) return false;
+            float t = 0;
+            if (kind == kFuseX) t = x;
+            else if (kind == kFuseY) t = y;
+            else if (kind == kFuseConst) memcpy(&t, &ins.y, 4);
+            else {
+                t = cache[ins.y];
+                if (reads) reads->push_back((int32_t)ins.y);
+            }
+            s[sp - 1] = kFuseRev[v] ? apply(kFuseOps[v], t, s[sp - 1], 0) : apply(kFuseOps[v], s[sp - 1], t, 0);
             continue;
         }
         int op, ar;
@@ -285,6 +300,16 @@ int main() {
             CHECK(st == TGP_OK, "%s: status %d\n", what, st);
             if (st != TGP_OK) continue;
             check_plan(what, d, w, c.D, g);
+            int64_t fused[4] = {0, 0, 0, 0};  // fused forms by operand kind
+            for (const uint2 &ins : d.plan.code_host) {
+                const uint32_t code = ins.x & 0xffu;
+                if (code >= kFuseBase && code < kFuseBase + 64) ++fused[(code - kFuseBase) / 16];
+            }
+            printf("%s: fused forms x %lld y %lld const %lld cache %lld\n", what, (long long)fused[0],
+                   (long long)fused[1], (long long)fused[2], (long long)fused[3]);
+            if (c.n_ind >= 300)
+                CHECK(fused[0] > 0 && fused[1] > 0 && fused[2] > 0 && fused[3] > 0,
+                      "%s: a fused operand kind never emitted\n", what);
             const int t = threads == 1 ? 0 : 1;
             spills[t] = w.pl.spills;
             cached[t] = w.pl.cached;

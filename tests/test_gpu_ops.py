@@ -1,0 +1,181 @@
+"""Accuracy of the device operators that take the hardware's reciprocal,
+base-2 logarithm and exponential (Table 1 pow and mod), measured through the
+C ABI against FP64 on the device's own FP32 operands.
+
+pow: within 3 ulp of x^y (C99 pow, 0^0 = 0) wherever x^y is finite, +-inf
+     where it overflows FP32, NaN exactly where it is NaN.  The operands span
+     the fast path (|y| <= 2, normal results) and the general one (|y| > 2,
+     overflow, underflow into subnormals, negative bases with integer
+     exponents).
+mod: bit for bit the floored remainder (the divisor's sign) rounded once
+     from its exact value, with a zero result signed like the dividend,
+     over quotients below and above 2^20 and divisors near both ends of the
+     range the reciprocal serves.
+
+Each operand is itself a root of the same population, so the reference is
+computed from exactly the FP32 values the device fed the operator."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2103_07512_amd import popgen as pg
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (1024, 1024)
+LO, HI = (-3.0, -2.5), (3.0, 2.5)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2103_07512_amd import tgp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return tgp, tgp.Context(0), torch
+
+
+def _eval(env, texts):
+    tgp, ctx, torch = env
+    pop = pg.population_from_texts(texts)
+    d = tgp.Domain(ctx, SHAPE, LO, HI)
+    dag = tgp.build_dag(ctx, pop)
+    out = torch.empty(pop.n_roots, d.cases, dtype=torch.float32, device="cuda:0")
+    tgp.evaluate(ctx, dag, d, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _ulp32(v):
+    """FP32 ulp at |v| (v finite, FP64), 2^-149 in the subnormal range."""
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -149)))
+    return np.exp2(np.maximum(e - 23.0, -149.0))
+
+
+FLT_MAX = float(np.finfo(np.float32).max)
+
+
+def _check_pow(a32, b32, got, what):
+    a = a32.astype(np.float64)
+    b = b32.astype(np.float64)
+    with np.errstate(all="ignore"):
+        want = np.power(a, b)
+    want = np.where((a == 0) & (b == 0), 0.0, want)
+    nan_w, nan_g = np.isnan(want), np.isnan(got)
+    assert np.array_equal(nan_w, nan_g), f"{what}: NaN at {np.argmax(nan_w != nan_g)}"
+    big = ~nan_w & (np.abs(want) >= FLT_MAX * (1 + 2.0 ** -25))
+    assert np.all(np.isinf(got[big]) & (np.sign(got[big]) == np.sign(want[big]))), f"{what}: overflow"
+    edge = ~nan_w & ~big & (np.abs(want) > FLT_MAX * (1 - 2.0 ** -21))  # within 3 ulp of the overflow edge
+    fin = ~nan_w & ~big & ~edge
+    assert np.all(np.isfinite(got[fin])), f"{what}: non-finite where x^y is finite"
+    err = np.abs(got[fin].astype(np.float64) - want[fin]) / _ulp32(want[fin])
+    i = int(np.argmax(err))
+    assert err[i] <= 3.0, f"{what}: {err[i]:.2f} ulp at pow({a[fin][i]!r}, {b[fin][i]!r})"
+    fast = fin & (np.abs(b) <= 2) & (a != 0) & np.isfinite(a)
+    return float(err.max()), int(fast.sum()), int(fin.sum())
+
+
+@pytest.mark.parametrize("base,expo", [
+    ("x", "y"),                               # |y| <= 2.5, bases in [-3, 3]
+    ("exp(mult(x, 20.0))", "y"),              # bases e^-60 .. e^60: |t| up to 216
+    ("exp(mult(x, 20.0))", "mult(y, 0.8)"),   # |y| <= 2: the fast path, |t| up to 173
+    ("x", "mult(y, 8.0)"),                    # |y| up to 20
+    ("mult(x, 1e-20)", "mult(y, 3.0)"),       # tiny bases, overflow and subnormal results
+])
+def test_pow_accuracy(env, base, expo):
+    got = _eval(env, [base, expo, f"pow({base}, {expo})"])
+    worst, n_fast, n_fin = _check_pow(got[0], got[1], got[2], f"pow({base}, {expo})")
+    print(f"pow({base}, {expo}): max {worst:.3f} ulp, {n_fast} fast-path of {n_fin} finite cases")
+
+
+def test_pow_integer_exponents(env):
+    """Negative bases with integer exponents: the sign follows the parity."""
+    cs = [-3.0, -2.0, -1.0, 0.0, 1.0, 2.0, 3.0, 7.0]
+    texts = ["x"] + [f"pow(x, {c!r})" for c in cs] + [f"pow({c!r}, x)" for c in (-2.0, -1.0, -0.5, 0.0)]
+    got = _eval(env, texts)
+    x = got[0]
+    for j, c in enumerate(cs):
+        _check_pow(x, np.full_like(x, c), got[1 + j], f"pow(x, {c})")
+    for j, c in enumerate((-2.0, -1.0, -0.5, 0.0)):
+        _check_pow(np.full_like(x, c), x, got[1 + len(cs) + j], f"pow({c}, x)")
+
+
+SPECIALS = ["0.0", "-0.0", "inf", "-inf", "nan", "1.0", "-1.0", "0.5", "-0.5", "2.0", "-2.0", "3.0", "-3.0",
+            "2.5", "-2.5", "1e-40", "-1e-40", "1e30", "-1e30", "150.0", "-150.0"]
+
+
+def test_pow_special_values(env):
+    """Every pair of special operands (zeros of both signs, infinities, NaN,
+    +-1, integers of both parities, non-integers, subnormals, huge values):
+    C99 pow with 0^0 = 0, signs included.  Operands are if(x, c, y) (x is
+    never 0 on this grid, so they are c): they depend on x, so the
+    interpreter, not constant folding, evaluates pow."""
+    pairs = [(a, b) for a in SPECIALS for b in SPECIALS]
+    texts = [f"pow(if(x, {a}, y), if(x, {b}, y))" for a, b in pairs]
+    tgp, ctx, torch = env
+    pop = pg.population_from_texts(texts)
+    d = tgp.Domain(ctx, (4, 4))
+    dag = tgp.build_dag(ctx, pop)
+    out = torch.empty(pop.n_roots, d.cases, dtype=torch.float32, device="cuda:0")
+    tgp.evaluate(ctx, dag, d, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for (a, b), g in zip(pairs, got):
+        a32, b32 = np.float32(float(a)), np.float32(float(b))
+        with np.errstate(all="ignore"):
+            w = 0.0 if (a32 == 0 and b32 == 0) else float(np.power(np.float64(a32), np.float64(b32)))
+        for v in g:
+            if math.isnan(w):
+                assert math.isnan(v), (a, b, v, w)
+            elif math.isinf(w) or abs(w) >= FLT_MAX * (1 + 2.0 ** -25):
+                assert math.isinf(v) and math.copysign(1, v) == math.copysign(1, w), (a, b, v, w)
+            else:
+                assert math.copysign(1, v) == math.copysign(1, w), (a, b, v, w)
+                assert abs(v - w) <= 3.0 * float(_ulp32(np.array([w]))[0]), (a, b, v, w)
+
+
+def _floor_mod_exact(a32, b32):
+    """The floored remainder of FP32 operands rounded once to FP32 (b != 0,
+    both finite): fmod is exact in FP64; adding b is done exactly with
+    fractions where FP64 could round."""
+    a = a32.astype(np.float64)
+    b = b32.astype(np.float64)
+    r = np.fmod(a, b)
+    fix = (r != 0) & ((r < 0) != (b < 0))
+    out = r.copy()
+    s = r + b
+    # r + b is exact in FP64 when the exponents differ by at most 28
+    with np.errstate(all="ignore"):
+        safe = np.abs(b) <= np.abs(r) * 2.0 ** 28
+    out[fix & safe] = s[fix & safe]
+    res = out.astype(np.float32)
+    for i in np.nonzero(fix & ~safe)[0]:
+        res[i] = np.float32(float(Fraction(float(r[i])) + Fraction(float(b[i]))))
+    zero = res == 0
+    res[zero] = np.copysign(np.float32(0), a32[zero])
+    return res
+
+
+@pytest.mark.parametrize("num,den", [
+    ("x", "y"),                                 # quotients below 2^20
+    ("mult(x, 1000.0)", "y"),
+    ("x", "mult(y, 0.001)"),                    # quotients up to ~2^21 near y = 0
+    ("mult(x, 1e30)", "y"),                     # quotients far beyond 2^20
+    ("x", "mult(y, 1e-38)"),                    # divisors below 2^-125 (subnormal ones too)
+    ("mult(x, 1e38)", "mult(y, 1e37)"),         # divisors above 2^125
+    ("sin(mult(x, 7.0))", "mult(y, 0.25)"),
+])
+def test_mod_bit_exact(env, num, den):
+    got = _eval(env, [num, den, f"mod({num}, {den})"])
+    a, b, r = got
+    ok = np.isfinite(a) & np.isfinite(b) & (b != 0)
+    assert ok.mean() > 0.99
+    want = _floor_mod_exact(a[ok], b[ok])
+    g = r[ok]
+    bad = g.view(np.uint32) != want.view(np.uint32)
+    i = int(np.argmax(bad))
+    assert not bad.any(), f"mod({a[ok][i]!r}, {b[ok][i]!r}): got {g[i]!r}, want {want[i]!r} ({bad.sum()} cases)"
+    with np.errstate(all="ignore"):
+        q = np.abs(a[ok].astype(np.float64) / b[ok])
+    print(f"mod({num}, {den}): {ok.sum()} cases bit-exact, {int((q < 2 ** 20).sum())} with |a/b| < 2^20")
