@@ -159,6 +159,7 @@ def body_for_depth(D):
     e("    uint2 ins;")
     e("    for (;;) {")
     e("    ins = *++ip;")
+    e("    if (ins.x == ((1u << 8) | I_END)) break;")
     e("    switch (ins.x) {")
     variants = []
     for name, op, ar in FUNCS:
@@ -190,7 +191,7 @@ def body_for_depth(D):
             e("        continue;")
             e("    }")
         if S == 1:
-            e(f"    case {key('I_END')}: res = s0; return;")
+            pass
         if S >= 2:
             e(f"    case {key('I_WARP')}:")
             e("        if constexpr (EXT) {")
@@ -232,6 +233,8 @@ def body_for_depth(D):
     e("    default: goto BAD;")
     e("    }")
     e("    }")
+    e("    res = s0;")
+    e("    return;")
     e("BAD:")
     e("#pragma unroll")
     e("    for (int k = 0; k < K; ++k) res.v[k] = __builtin_nanf(\"\");")
