@@ -29,7 +29,9 @@ __global__ void k_fold_level(const FoldDesc *jobs, const int2 *list, int32_t n) 
     const int32_t *k = node_kid + 3 * (int64_t)u;
     auto child = [&](int32_t c) {
         if (c < 0) return 0.0f;
-        return ((uint32_t)node_op[c] & 0xffu) == TGP_CONST ? node_value[c] : val[c];
+        if (((uint32_t)node_op[c] & 0xffu) != TGP_CONST) return val[c];
+        const float v = node_value[c];
+        return v == v ? v : __builtin_nanf("");  // constants enter as quiet NaNs (ops_device.h, min/max)
     };
     const float a = child(k[0]);
     const float b = child(k[1]);

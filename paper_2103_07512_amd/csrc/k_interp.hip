@@ -185,19 +185,20 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
     }
 }
 
-// The plain interpreter kernel asks for at least kMinWaves waves per SIMD:
-// the compiler then keeps it within 80 VGPRs (a few values live in scratch
-// instead).  The launch waits mostly on memory (instruction fetch, cache rows,
-// targets), and a sixth resident wave hides more of that latency than the
-// spilled values cost (on the 1000 x 3 population: 84 ms for the fitness
-// launch against 90 ms at five waves; seven or eight waves spill more and the
-// cache-fill launches lose).  The batched kernels hold more descriptor state
-// and spill far more at six waves (measured slower), so they keep the
+// Waves per SIMD the plain interpreter asks for.  The fitness form runs at
+// seven (72 VGPRs): its dispatch chain waits on scalar loads and its cache
+// rows on vector loads, and a seventh resident wave hides more of that than
+// the few values that then live in scratch cost (only the z vector of 3-D
+// domains is reloaded inside the dispatch loop; 1000 x 3 population on
+// 1024^2: 66 ms against 69 ms at six).  The store form (cache fill) keeps
+// six, where it spills less.  The batched kernels hold more descriptor state
+// and spill far more at these counts (measured slower), so they keep the
 // compiler's choice.
-constexpr int kMinWaves = 6;
+template <int MODE>
+constexpr int min_waves() { return MODE == MODE_REDUCE ? 7 : 6; }
 
 template <int K, int D, int MODE, bool EXT>
-__global__ __launch_bounds__(64, kMinWaves) void k_interp(const InterpArgs a) {
+__global__ __launch_bounds__(64, min_waves<MODE>()) void k_interp(const InterpArgs a) {
     const uint32_t item = blockIdx.x;
     const uint32_t p = item / (uint32_t)a.job.n_stripes;
     const uint32_t stripe = item - p * (uint32_t)a.job.n_stripes;

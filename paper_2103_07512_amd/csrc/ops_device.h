@@ -25,8 +25,32 @@ __device__ __forceinline__ float f_div(float a, float b) { return b == 0.0f ? 0.
 __device__ __forceinline__ float f_sin(float a) { return sinpi_f32(a); }
 __device__ __forceinline__ float f_cos(float a) { return cospi_f32(a); }
 __device__ __forceinline__ float f_tan(float a) { return tanpi_f32(a); }
-__device__ __forceinline__ float f_exp(float a) { return expf(a); }
-__device__ __forceinline__ float f_log(float a) { return a < 0.0f ? -1.0f : logf(a); }
+// e^x: for |x| < 87 (a normal result) 2^t with t = x log2(e) carried as a
+// double-FP32 sum (the product split exactly by fma, plus x times the low
+// part of log2(e)), 2^t = 2^t_hi (1 + t_lo ln 2) from the hardware exp2
+// (within 0.77 ulp): within 1.3 ulp.  Other arguments take the library's
+// expf (overflow, subnormal results, NaN).
+__device__ __forceinline__ float f_exp(float a) {
+    if (fabsf(a) < 87.0f) {
+        const float th = a * 0x1.715476p+0f;
+        const float tl = fmaf(a, 0x1.715476p+0f, -th) + a * 0x1.4ae0c0p-26f;
+        const float r = __builtin_amdgcn_exp2f(th);
+        return fmaf(r, tl * 0x1.62e430p-1f, r);
+    }
+    return expf(a);
+}
+// Protected log: -1 for a negative argument.  A positive normal argument
+// takes the hardware log2 (within one ulp) times ln 2 split in two FP32
+// parts: within 1.5 ulp of the result's relative error bound 2^-21.  Zero,
+// subnormals, infinity and NaN take the library's logf.
+__device__ __forceinline__ float f_log(float a) {
+    if (a < 0.0f) return -1.0f;
+    if (a >= 0x1p-126f && a < __builtin_inff()) {
+        const float l2 = __builtin_amdgcn_logf(a);
+        return fmaf(l2, 0x1.62e430p-1f, l2 * -0x1.05c610p-29f);
+    }
+    return logf(a);
+}
 // x^y with 0^0 = 0, otherwise C99 pow.  The common case -- a finite
 // nonzero base (positive, or negative with an integer exponent), |y| <= 2,
 // and a result in the normal range -- goes through the hardware base-2
@@ -58,14 +82,29 @@ __device__ __forceinline__ float f_pow(float a, float b) {
         const float tl = ((p - (th - bb)) + (q - bb)) + (pe + qe);
         if (th >= -125.0f && th <= 127.0f) {
             float r = __builtin_amdgcn_exp2f(th);
-            r = fmaf(r, tl * 0.693147182f, r);
+            r = fmaf(r, tl * 0x1.62e430p-1f, r);
             return (a < 0.0f && ab == 1.0f) ? -r : r;
         }
     }
     return (a == 0.0f && b == 0.0f) ? 0.0f : pow_f32(a, b);
 }
-__device__ __forceinline__ float f_min(float a, float b) { return fminf(a, b); }
-__device__ __forceinline__ float f_max(float a, float b) { return fmaxf(a, b); }
+// min and max: the hardware's v_min_f32 / v_max_f32, which return the other
+// operand when one is a quiet NaN and order -0 below +0 (the reading of
+// include/tgp.h).  They differ from fminf / fmaxf only on signalling NaNs,
+// and no operand here is one: constants are made quiet where they enter
+// (the program emitter, the folding kernel) and every operator returns quiet
+// NaNs, so the compiler's quieting of both operands (two more instructions
+// per call, as it cannot prove this) is left out.
+__device__ __forceinline__ float f_min(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float f_max(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 // Halving each operand first is exact in the normal range and cannot overflow.
 __device__ __forceinline__ float f_mdist(float a, float b) { return a * 0.5f + b * 0.5f; }
 __device__ __forceinline__ float f_neg(float a) { return -a; }
@@ -74,7 +113,7 @@ __device__ __forceinline__ float f_sign(float a) {
     return a > 0.0f ? 1.0f : (a < 0.0f ? -1.0f : 0.0f);
 }
 __device__ __forceinline__ float f_abs(float a) { return fabsf(a); }
-__device__ __forceinline__ float f_clip(float a, float b, float c) { return fmaxf(fminf(a, c), b); }
+__device__ __forceinline__ float f_clip(float a, float b, float c) { return f_max(f_min(a, c), b); }
 // Floored remainder (the divisor's sign), rounded once from its exact value;
 // 0 for a zero divisor of either sign.  The quotient comes from the
 // hardware reciprocal (within one ulp) when |a / b| < 2^20 and 2^-125 <= |b|

@@ -991,6 +991,16 @@ struct Planner {
         return TGP_OK;
     }
 
+    // The FP32 bits of constant (or folded) node n; every NaN becomes the
+    // quiet NaN 0x7fc00000, so that no signalling NaN reaches the
+    // interpreter's min and max (ops_device.h).
+    uint32_t const_word(int64_t n) const {
+        const float v = !folded.empty() && folded[n] ? fold_val[n] : d.value[n];
+        uint32_t w;
+        memcpy(&w, &v, 4);
+        return v == v ? w : 0x7fc00000u;
+    }
+
     // The fused-form kind and .y word of child c when c can be a fused
     // operand (x, y, a constant or a cached row), else -1.
     int fuse_operand(int32_t c, uint32_t &y) const {
@@ -1004,7 +1014,7 @@ struct Planner {
             return v == 0 ? kFuseX : (v == 1 ? kFuseY : -1);
         }
         if (o == TGP_CONST) {
-            memcpy(&y, !folded.empty() && folded[c] ? &fold_val[c] : &d.value[c], 4);
+            y = const_word(c);
             return kFuseConst;
         }
         return -1;
@@ -1067,7 +1077,7 @@ struct Planner {
                     ins.x = v == 0 ? I_X : (v == 1 ? I_Y : I_Z);
                 } else if (o == TGP_CONST) {
                     ins.x = I_CONST;
-                    memcpy(&ins.y, !folded.empty() && folded[n] ? &fold_val[n] : &d.value[n], 4);
+                    ins.y = const_word(n);
                 } else if (top.fv >= 0) {
                     const int32_t c = d.kid[3 * n + kPerms[perm[n]][1]];
                     const int kind = fuse_operand(c, ins.y);

@@ -1,12 +1,17 @@
 """Accuracy of the device operators that take the hardware's reciprocal,
-base-2 logarithm and exponential (Table 1 pow and mod), measured through the
-C ABI against FP64 on the device's own FP32 operands.
+base-2 logarithm and exponential (Table 1 pow, mod, exp, log) or its raw
+min and max, measured through the C ABI against FP64 on the device's own
+FP32 operands.
 
 pow: within 3 ulp of x^y (C99 pow, 0^0 = 0) wherever x^y is finite, +-inf
      where it overflows FP32, NaN exactly where it is NaN.  The operands span
      the fast path (|y| <= 2, normal results) and the general one (|y| > 2,
      overflow, underflow into subnormals, negative bases with integer
      exponents).
+exp, log: within 3 ulp of e^x and ln x (log protected: -1 below 0),
+     overflow, subnormal results and non-positive arguments included.
+min, max, clip: bit for bit the oracle's reading (a NaN operand gives the
+     other one, -0 below +0), with NaN constants among the operands.
 mod: bit for bit the floored remainder (the divisor's sign) rounded once
      from its exact value, with a zero result signed like the dividend,
      over quotients below and above 2^20 and divisors near both ends of the
@@ -179,3 +184,68 @@ def test_mod_bit_exact(env, num, den):
     with np.errstate(all="ignore"):
         q = np.abs(a[ok].astype(np.float64) / b[ok])
     print(f"mod({num}, {den}): {ok.sum()} cases bit-exact, {int((q < 2 ** 20).sum())} with |a/b| < 2^20")
+
+
+def _check_unary(a32, got, ref, what):
+    a = a32.astype(np.float64)
+    with np.errstate(all="ignore"):
+        want = ref(a)
+    nan_w, nan_g = np.isnan(want), np.isnan(got)
+    assert np.array_equal(nan_w, nan_g), f"{what}: NaN at {np.argmax(nan_w != nan_g)}"
+    big = ~nan_w & (np.abs(want) >= FLT_MAX * (1 + 2.0 ** -25))
+    assert np.all(np.isinf(got[big]) & (np.sign(got[big]) == np.sign(want[big]))), f"{what}: overflow"
+    edge = ~nan_w & ~big & (np.abs(want) > FLT_MAX * (1 - 2.0 ** -21))
+    fin = ~nan_w & ~big & ~edge
+    assert np.all(np.isfinite(got[fin])), f"{what}: non-finite where the result is finite"
+    err = np.abs(got[fin].astype(np.float64) - want[fin]) / _ulp32(want[fin])
+    i = int(np.argmax(err))
+    assert err[i] <= 3.0, f"{what}: {err[i]:.2f} ulp at {a[fin][i]!r}"
+    return float(err.max()), int(fin.sum())
+
+
+@pytest.mark.parametrize("arg", ["x", "mult(x, 30.0)", "mult(y, 35.0)", "add(mult(x, 0.01), 87.0)"])
+def test_exp_accuracy(env, arg):
+    got = _eval(env, [arg, f"exp({arg})"])
+    worst, n = _check_unary(got[0], got[1], np.exp, f"exp({arg})")
+    print(f"exp({arg}): max {worst:.3f} ulp over {n} finite results")
+
+
+def _log_ref(a):
+    return np.where(a < 0, -1.0, np.log(np.where(a < 0, 1.0, a)))
+
+
+@pytest.mark.parametrize("arg", ["x", "exp(mult(x, 29.0))", "mult(y, 1e-39)", "add(mult(x, 1e-6), 1.0)",
+                                 "pow(2.0, mult(y, 50.0))"])
+def test_log_accuracy(env, arg):
+    got = _eval(env, [arg, f"log({arg})"])
+    worst, n = _check_unary(got[0], got[1], _log_ref, f"log({arg})")
+    print(f"log({arg}): max {worst:.3f} ulp over {n} finite results")
+
+
+def test_min_max_nan_and_zeros(env):
+    """NaN constants and signed zeros through min, max and clip, in every
+    operand position (fused and stacked forms), against the oracle bit for
+    bit."""
+    import oracle
+    ops = ["nan", "-0.0", "0.0", "y", "x", "1.0"]
+    texts = []
+    for a in ops:
+        for b in ops:
+            ea, eb = f"if(x, {a}, y)", f"if(x, {b}, y)"
+            texts += [f"min({ea}, {eb})", f"max({ea}, {eb})", f"min({ea}, {b})", f"max({a}, {eb})",
+                      f"clip({ea}, {eb}, y)", f"clip(y, {ea}, {eb})"]
+    shape = (8, 8)
+    tgp, ctx, torch = env
+    pop = pg.population_from_texts(texts)
+    d = tgp.Domain(ctx, shape)
+    dag = tgp.build_dag(ctx, pop)
+    out = torch.empty(pop.n_roots, d.cases, dtype=torch.float32, device="cuda:0")
+    tgp.evaluate(ctx, dag, d, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = oracle.evaluate(pop.tokens, pop.offsets, shape).astype(np.float32)
+    gn, wn = np.isnan(got), np.isnan(want)
+    assert np.array_equal(gn, wn)
+    bad = ~gn & (got.view(np.uint32) != want.view(np.uint32))
+    r = int(np.argmax(bad.any(axis=1)))
+    assert not bad.any(), f"{texts[r]}: {got[r][bad[r]][:4]} vs {want[r][bad[r]][:4]}"
