@@ -8,6 +8,8 @@ pow: within 3 ulp of x^y (C99 pow, 0^0 = 0) wherever x^y is finite, +-inf
      the fast path (|y| <= 2, normal results) and the general one (|y| > 2,
      overflow, underflow into subnormals, negative bases with integer
      exponents).
+sqrt: within one ulp of the square root (protected: 0 below 0), exact on
+     exact squares, subnormal arguments included.
 exp, log: within 3 ulp of e^x and ln x (log protected: -1 below 0),
      overflow, subnormal results and non-positive arguments included.
 min, max, clip: bit for bit the oracle's reading (a NaN operand gives the
@@ -249,3 +251,18 @@ def test_min_max_nan_and_zeros(env):
     bad = ~gn & (got.view(np.uint32) != want.view(np.uint32))
     r = int(np.argmax(bad.any(axis=1)))
     assert not bad.any(), f"{texts[r]}: {got[r][bad[r]][:4]} vs {want[r][bad[r]][:4]}"
+
+
+@pytest.mark.parametrize("arg", ["x", "mult(y, 1e30)", "mult(x, 1e-40)", "mult(x, x)", "mult(mult(x, 64.0), mult(x, 64.0))"])
+def test_sqrt_accuracy(env, arg):
+    got = _eval(env, [arg, f"sqrt({arg})"])
+    a = got[0].astype(np.float64)
+    want = np.where(a < 0, 0.0, np.sqrt(np.where(a < 0, 0.0, a)))
+    g = got[1].astype(np.float64)
+    assert np.all(np.isfinite(g))
+    err = np.abs(g - want) / _ulp32(want)
+    i = int(np.argmax(err))
+    assert err[i] <= 1.0, f"sqrt({a[i]!r}): {err[i]:.2f} ulp"
+    exact = (want.astype(np.float32).astype(np.float64) ** 2 == a) & (a > 0)
+    assert np.array_equal(g[exact], want[exact]), f"sqrt({arg}): inexact on an exact square"
+    print(f"sqrt({arg}): max {err.max():.3f} ulp, {int(exact.sum())} exact squares exact")
