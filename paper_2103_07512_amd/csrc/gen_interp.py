@@ -93,8 +93,9 @@ def fused_checks():
 
 def fused_case(e, key_expr, name, rev, kind, read, dst, ind, end):
     """One fused case: dst = name(dst, T) (or name(T, dst) when reversed),
-    T the terminal operand of the given kind; ends with `end`."""
-    e(f"{ind}case {key_expr}: {{")
+    T the terminal operand of the given kind; ends with `end`.  With key_expr
+    None only the braced body is written (the dispatch tree's leaves)."""
+    e(f"{ind}case {key_expr}: {{" if key_expr is not None else f"{ind}{{")
     if kind == "kFuseConst":
         e(f"{ind}    const float c = __uint_as_float(ins.y);")
     if kind == "kFuseCache":
@@ -146,6 +147,56 @@ def called_functions():
     return "\n".join(L)
 
 
+# Numeric values of the instruction codes (tgp_internal.h; checked by the
+# static_asserts of the generated file).
+CODES = {"I_X": 0, "I_Y": 1, "I_Z": 2, "I_CONST": 3, "I_CACHE": 4, "I_END": 5, "I_WARP": 6}
+KINDS = {"kFuseX": 0, "kFuseY": 1, "kFuseConst": 2, "kFuseCache": 3}
+
+
+def code_checks():
+    L = ["// Instruction codes as the dispatch tree below numbers them."]
+    L += [f"static_assert({n} == {v}, \"code {n}\");" for n, v in CODES.items()]
+    L += [f"static_assert({n} == {v}, \"fused kind {n}\");" for n, v in KINDS.items()]
+    L.append(f"static_assert(kFnBase == {FN_BASE} && kRevBase == {REV_BASE} && kPermBase == {PERM_BASE}, \"bases\");")
+    L.append("")
+    return "\n".join(L)
+
+
+def dispatch_weights():
+    """Measured frequency of each instruction word (dispatch_weights.txt):
+    key -> count.  Words it does not list weigh 1."""
+    path = os.path.join(HERE, "dispatch_weights.txt")
+    w = {}
+    for line in open(path):
+        line = line.split("#")[0].split()
+        if len(line) == 2:
+            w[int(line[0])] = float(line[1])
+    return w
+
+
+def tree(e, keys, bodies, weight, ind):
+    """Binary search on the instruction word over the sorted keys, split
+    where the weights on both sides balance (Mehlhorn's rule), so a frequent
+    word is found after few comparisons; a leaf holds one case.  Every word
+    the emitter writes is one of the keys, so a leaf does not test its key."""
+    if len(keys) == 1:
+        for line in bodies[keys[0]]:
+            e(ind + line if not line.startswith("#") else line)
+        return
+    ws = [weight.get(k, 1.0) for k in keys]
+    total, acc, best, m = sum(ws), 0.0, None, 1
+    for i in range(1, len(keys)):
+        acc += ws[i - 1]
+        d = abs(2 * acc - total)
+        if best is None or d < best:
+            best, m = d, i
+    e(f"{ind}if (ins.x < {keys[m]}u) {{")
+    tree(e, keys[:m], bodies, weight, ind + "    ")
+    e(f"{ind}}} else {{")
+    tree(e, keys[m:], bodies, weight, ind + "    ")
+    e(f"{ind}}}")
+
+
 def body_for_depth(D):
     L = []
     e = L.append
@@ -160,7 +211,12 @@ def body_for_depth(D):
     e("    for (;;) {")
     e("    ins = *++ip;")
     e("    if (ins.x == ((1u << 8) | I_END)) break;")
-    e("    switch (ins.x) {")
+    bodies = {}
+
+    def case(key, lines):
+        assert key not in bodies
+        bodies[key] = lines
+
     variants = []
     for name, op, ar in FUNCS:
         if name in BITWISE[1:]:
@@ -174,64 +230,53 @@ def body_for_depth(D):
                 if p:
                     variants.append((PERM_BASE + 6 * t + p, name, ar, order))
     for S in range(D + 1):
-        key = lambda c: f"({S}u << 8) | {c}"
+        key = lambda c: (S << 8) | c
         if S < D:
             for name, reg in (("I_X", "xv"), ("I_Y", "yv"), ("I_Z", "zv")):
-                e(f"    case {key(name)}: s{S} = {reg}; continue;")
-            e(f"    case {key('I_CONST')}: {{")
-            e("        const float c = __uint_as_float(ins.y);")
-            e("#pragma unroll")
-            e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = c;")
-            e("        continue;")
-            e("    }")
-            e(f"    case {key('I_CACHE')}: {{")
-            e("        const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
-            e("#pragma unroll")
-            e(f"        for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];")
-            e("        continue;")
-            e("    }")
-        if S == 1:
-            pass
+                case(key(CODES[name]), [f"s{S} = {reg};", "continue;"])
+            case(key(CODES["I_CONST"]), ["const float c = __uint_as_float(ins.y);", "#pragma unroll",
+                                         f"for (int k = 0; k < K; ++k) s{S}.v[k] = c;", "continue;"])
+            case(key(CODES["I_CACHE"]), ["const float *row = cache + (size_t)ins.y * (size_t)cache_stride;",
+                                         "#pragma unroll",
+                                         f"for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];", "continue;"])
         if S >= 2:
-            e(f"    case {key('I_WARP')}:")
-            e("        if constexpr (EXT) {")
-            e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
-            e("#pragma unroll")
-            e(f"            for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row[warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], cidx[k])];")
-            e("            continue;")
-            e("        } else {")
-            e("            goto BAD;")
-            e("        }")
+            case(key(CODES["I_WARP"]), [
+                "if constexpr (EXT) {",
+                "    const float *row = cache + (size_t)ins.y * (size_t)cache_stride;",
+                "#pragma unroll",
+                f"    for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row[warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], cidx[k])];",
+                "    continue;",
+                "} else {",
+                "    goto BAD;",
+                "}"])
         for c, name, ar, order in variants:
             if S < ar:
                 continue
             dst = S - ar
             src = [f"s{dst + order.index(i)}" for i in range(ar)]
             if name == BITWISE[0]:
-                e(f"    case {key(c)}:")
-                e("        if constexpr (EXT) {")
-                e("            const uint32_t kind = ins.y;")
-                e("#pragma unroll")
-                e(f"            for (int k = 0; k < K; ++k) s{dst}.v[k] = f_bitop({src[0]}.v[k], {src[1]}.v[k], kind);")
-                e("            continue;")
-                e("        } else {")
-                e("            goto BAD;")
-                e("        }")
+                case(key(c), [
+                    "if constexpr (EXT) {",
+                    "    const uint32_t kind = ins.y;",
+                    "#pragma unroll",
+                    f"    for (int k = 0; k < K; ++k) s{dst}.v[k] = f_bitop({src[0]}.v[k], {src[1]}.v[k], kind);",
+                    "    continue;",
+                    "} else {",
+                    "    goto BAD;",
+                    "}"])
             elif name in CALLED:
-                e(f"    case {key(c)}: s{dst} = vcall_{name}<K>({', '.join(src)}); continue;")
+                case(key(c), [f"s{dst} = vcall_{name}<K>({', '.join(src)});", "continue;"])
             else:
-                e(f"    case {key(c)}:")
-                e("#pragma unroll")
                 args = ", ".join(f"{x}.v[k]" for x in src)
-                e(f"        for (int k = 0; k < K; ++k) s{dst}.v[k] = f_{name}({args});")
-                e("        continue;")
+                case(key(c), ["#pragma unroll", f"for (int k = 0; k < K; ++k) s{dst}.v[k] = f_{name}({args});",
+                              "continue;"])
         if S >= 1:
             for kind, read in FUSE_KINDS:
                 for v, (name, rev) in enumerate(FUSED):
-                    fused_case(e, f"({S}u << 8) | {fused_key(kind, v)}", name, rev, kind, read, f"s{S - 1}",
-                               "    ", "continue;")
-    e("    default: goto BAD;")
-    e("    }")
+                    lines = []
+                    fused_case(lines.append, None, name, rev, kind, read, f"s{S - 1}", "", "continue;")
+                    case(key(FUSE_BASE + 16 * KINDS[kind] + v), lines)
+    tree(e, sorted(bodies), bodies, dispatch_weights(), "    ")
     e("    }")
     e("    res = s0;")
     e("    return;")
@@ -357,6 +402,7 @@ def generate():
            f"// Stack sizes: {', '.join(map(str, DEPTHS))}.",
            "",
            fused_checks(),
+           code_checks(),
            called_functions()]
     for D in DEPTHS:
         out.append(body_for_depth(D))
