@@ -208,9 +208,14 @@ def body_for_depth(D):
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
     e("    uint2 ins;")
+    e("    // one scalar load of the next whole word, issued a dispatch ahead")
+    e("    uint64_t nxt;")
+    e("    __builtin_memcpy(&nxt, ++ip, 8);")
     e("    for (;;) {")
-    e("    ins = *++ip;")
+    e("    ins = make_uint2((uint32_t)nxt, (uint32_t)(nxt >> 32));")
     e("    if (ins.x == ((1u << 8) | I_END)) break;")
+    e("    __builtin_amdgcn_sched_barrier(0);")
+    e("    __builtin_memcpy(&nxt, ++ip, 8);")
     bodies = {}
 
     def case(key, lines):
