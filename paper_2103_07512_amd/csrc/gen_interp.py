@@ -64,8 +64,9 @@ PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
 # Operators compiled once, out of line.
 CALLED = {"sin", "cos", "tan", "exp", "log", "pow", "mod", "sstep", "sstepp", "len", "lerp"}
 # The bitwise operators share one opcode (that of "or"); the instruction's
-# bits 8-9 say which (0 or, 1 xor, 2 and).  They and warp (I_WARP) are
-# compiled only into the interpreters instantiated with EXT = true.
+# .y says which (0 or, 1 xor, 2 and).  They, warp (I_WARP) and the third
+# axis (I_Z) are compiled only into the interpreters instantiated with
+# EXT = true, so the others carry no z vector.
 BITWISE = ("or", "xor", "and")
 DEPTHS = [8]
 ARGS = "abc"
@@ -190,7 +191,10 @@ def tree(e, keys, bodies, weight, ind):
         d = abs(2 * acc - total)
         if best is None or d < best:
             best, m = d, i
-    e(f"{ind}if (ins.x < {keys[m]}u) {{")
+    # the split's probability, so the compiler's block frequencies (register
+    # allocation, spill placement, layout) follow the measured ones
+    p = min(max(sum(ws[:m]) / total, 0.001), 0.999)
+    e(f"{ind}if (__builtin_expect_with_probability(ins.x < {keys[m]}u, 1, {p:.3f})) {{")
     tree(e, keys[:m], bodies, weight, ind + "    ")
     e(f"{ind}}} else {{")
     tree(e, keys[m:], bodies, weight, ind + "    ")
@@ -237,8 +241,11 @@ def body_for_depth(D):
     for S in range(D + 1):
         key = lambda c: (S << 8) | c
         if S < D:
-            for name, reg in (("I_X", "xv"), ("I_Y", "yv"), ("I_Z", "zv")):
+            for name, reg in (("I_X", "xv"), ("I_Y", "yv")):
                 case(key(CODES[name]), [f"s{S} = {reg};", "continue;"])
+            # the third axis only in the extended interpreter (3-D domains)
+            case(key(CODES["I_Z"]), ["if constexpr (EXT) {", f"    s{S} = zv;", "    continue;", "} else {",
+                                     "    goto BAD;", "}"])
             case(key(CODES["I_CONST"]), ["const float c = __uint_as_float(ins.y);", "#pragma unroll",
                                          f"for (int k = 0; k < K; ++k) s{S}.v[k] = c;", "continue;"])
             case(key(CODES["I_CACHE"]), ["const float *row = cache + (size_t)ins.y * (size_t)cache_stride;",

@@ -1024,8 +1024,8 @@ struct Planner {
     // Every instruction carries the stack depth before it (.x bits 8-15).
     // A binary operator whose last-evaluated child is a terminal takes its
     // fused form and reads that child itself.  Adds the cost-model slots of
-    // its instructions to *valu; sets *ext when it emits a bitwise operator
-    // or warp, *warp_used for warp.
+    // its instructions to *valu; sets *ext when it emits a bitwise operator,
+    // warp or the third axis, *warp_used for warp.
     void emit(int32_t root, std::vector<uint2> &code, int64_t &cache_reads, double *valu, bool *ext,
               bool *warp_used) const {
         struct Frame {
@@ -1075,6 +1075,7 @@ struct Planner {
                 if (o == TGP_VAR) {
                     const int v = (d.op[n] >> 8) & 0xff;
                     ins.x = v == 0 ? I_X : (v == 1 ? I_Y : I_Z);
+                    if (v > 1) *ext = true;  // the third axis: extended interpreter only
                 } else if (o == TGP_CONST) {
                     ins.x = I_CONST;
                     ins.y = const_word(n);

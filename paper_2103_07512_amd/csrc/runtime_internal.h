@@ -107,7 +107,7 @@ struct Plan {
     std::vector<int32_t> ind_rows_host;
     std::vector<int32_t> slot_node;     // DAG node held by each cache slot
     std::vector<uint8_t> slot_pre;      // slot already resident (no fill program)
-    bool ext = false;                   // uses the bitwise operators or warp
+    bool ext = false;                   // uses the bitwise operators, warp or the third axis
     bool warp = false;                  // uses warp
     int64_t instructions = 0;
     double exec_per_case = 0;           // instructions run per case, fitness form
