@@ -218,7 +218,9 @@ tgp_status tgp_debug_set_hash_bits(int32_t bits);
  * fl32(lo[k] + (hi[k] - lo[k]) * i / (shape[k] - 1)) computed in FP64 (lo[k]
  * when shape[k] == 1).  lo/hi NULL mean -1 and 1 for every axis (the paper's
  * standard range).  Cases are numbered row-major, last axis fastest; at most
- * 2^31 - 1 cases.  The coordinate tables are copied to the device. */
+ * 2^30 cases (a row of one FP32 value per case then stays within 4 GiB, which
+ * the interpreter addresses with 32-bit byte offsets).  The coordinate tables
+ * are copied to the device. */
 tgp_status tgp_domain_create(tgp_ctx ctx, int32_t ndim, const int64_t *shape, const double *lo,
                              const double *hi, tgp_domain *out);
 void tgp_domain_destroy(tgp_domain dom);

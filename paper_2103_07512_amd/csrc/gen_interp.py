@@ -77,7 +77,7 @@ FUSED = [("add", False), ("sub", False), ("mult", False), ("div", False), ("pow"
          ("min", False), ("max", False), ("mdist", False), ("mod", False), ("len", False),
          ("sub", True), ("div", True), ("pow", True), ("mod", True)]
 # terminal kinds of a fused operand: (code offset name, how to read case k)
-FUSE_KINDS = [("kFuseX", "xv.v[k]"), ("kFuseY", "yv.v[k]"), ("kFuseConst", "c"), ("kFuseCache", "row[cidx[k]]")]
+FUSE_KINDS = [("kFuseX", "xv.v[k]"), ("kFuseY", "yv.v[k]"), ("kFuseConst", "c"), ("kFuseCache", "row_load(row, coff[k])")]
 
 
 def fused_checks():
@@ -100,7 +100,7 @@ def fused_case(e, key_expr, name, rev, kind, read, dst, ind, end):
     if kind == "kFuseConst":
         e(f"{ind}    const float c = __uint_as_float(ins.y);")
     if kind == "kFuseCache":
-        e(f"{ind}    const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+        e(f"{ind}    const Row row = row_at(cache, cache_stride, ins.y);")
     if name in CALLED:
         if kind in ("kFuseX", "kFuseY"):
             tv = "xv" if kind == "kFuseX" else "yv"
@@ -208,7 +208,7 @@ def body_for_depth(D):
     e("template <int K, bool EXT>")
     e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
     e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
-    e("        const int32_t (&cidx)[K], const WarpGeom &wg, FV<K> &res)")
+    e("        const uint32_t (&coff)[K], const WarpGeom &wg, FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
     e("    uint2 ins;")
@@ -248,15 +248,16 @@ def body_for_depth(D):
                                      "    goto BAD;", "}"])
             case(key(CODES["I_CONST"]), ["const float c = __uint_as_float(ins.y);", "#pragma unroll",
                                          f"for (int k = 0; k < K; ++k) s{S}.v[k] = c;", "continue;"])
-            case(key(CODES["I_CACHE"]), ["const float *row = cache + (size_t)ins.y * (size_t)cache_stride;",
+            case(key(CODES["I_CACHE"]), ["const Row row = row_at(cache, cache_stride, ins.y);",
                                          "#pragma unroll",
-                                         f"for (int k = 0; k < K; ++k) s{S}.v[k] = row[cidx[k]];", "continue;"])
+                                         f"for (int k = 0; k < K; ++k) s{S}.v[k] = row_load(row, coff[k]);",
+                                         "continue;"])
         if S >= 2:
             case(key(CODES["I_WARP"]), [
                 "if constexpr (EXT) {",
-                "    const float *row = cache + (size_t)ins.y * (size_t)cache_stride;",
+                "    const Row row = row_at(cache, cache_stride, ins.y);",
                 "#pragma unroll",
-                f"    for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row[warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], cidx[k])];",
+                f"    for (int k = 0; k < K; ++k) s{S - 2}.v[k] = row_load(row, 4u * (uint32_t)warp_case(wg, s{S - 2}.v[k], s{S - 1}.v[k], (int32_t)(coff[k] >> 2)));",
                 "    continue;",
                 "} else {",
                 "    goto BAD;",
@@ -329,7 +330,7 @@ def body_lds():
     e("template <int K>")
     e("__device__ __forceinline__ void run_prog_lds(const uint2 *__restrict__ ip, const FV<K> &xv,")
     e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
-    e("        const int32_t (&cidx)[K], const WarpGeom &wg, float *sl, int lane, FV<K> &res)")
+    e("        const uint32_t (&coff)[K], const WarpGeom &wg, float *sl, int lane, FV<K> &res)")
     e("{")
     e("    FV<K> t;")
     e("#pragma unroll")
@@ -350,17 +351,17 @@ def body_lds():
     e("        }")
     e("        case I_CACHE: {")
     e("            lds_put<K>(sl, sp++, lane, t);")
-    e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+    e("            const Row row = row_at(cache, cache_stride, ins.y);")
     e("#pragma unroll")
-    e("            for (int k = 0; k < K; ++k) t.v[k] = row[cidx[k]];")
+    e("            for (int k = 0; k < K; ++k) t.v[k] = row_load(row, coff[k]);")
     e("            break;")
     e("        }")
     e("        case I_END: res = t; return;")
     e("        case I_WARP: {")
     e("            const FV<K> t0 = lds_get<K>(sl, --sp, lane);")
-    e("            const float *row = cache + (size_t)ins.y * (size_t)cache_stride;")
+    e("            const Row row = row_at(cache, cache_stride, ins.y);")
     e("#pragma unroll")
-    e("            for (int k = 0; k < K; ++k) t.v[k] = row[warp_case(wg, t0.v[k], t.v[k], cidx[k])];")
+    e("            for (int k = 0; k < K; ++k) t.v[k] = row_load(row, 4u * (uint32_t)warp_case(wg, t0.v[k], t.v[k], (int32_t)(coff[k] >> 2)));")
     e("            break;")
     e("        }")
     for name, op, ar in FUNCS:

@@ -43,6 +43,26 @@ struct WarpGeom {
     int32_t ndim;
 };
 
+// A row of FP32 values (one per case) read and written through a buffer
+// resource: the row's base in scalar registers and each lane's 32-bit byte
+// offset in one vector register, so no 64-bit address arithmetic is done per
+// case.  The resource spans 4 GiB from the row's start (a row of at most
+// 2^30 cases; the serving arena's rows are index * stride floats in, and
+// longer than stride).  Word 3 is the 32-bit data format of the gfx9 family.
+struct Row {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ Row row_at(const float *base, int64_t stride, uint32_t index) {
+    const float *p = base + (size_t)index * (size_t)stride;
+    return Row{__builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, -1, 0x00020000)};
+}
+__device__ __forceinline__ float row_load(const Row &row, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row.r, off, 0, 0));
+}
+__device__ __forceinline__ void row_store(const Row &row, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), row.r, off, 0, 0);
+}
+
 // The case warp reads for a case c: the points named by t0 and t1 along
 // axes 0 and 1, the case's own point along a third axis.
 __device__ __forceinline__ int32_t warp_case(const WarpGeom &g, float t0, float t1, int32_t c) {
@@ -87,13 +107,13 @@ constexpr int kLdsSlots = 16;
 template <int K, int D, bool EXT>
 __device__ __forceinline__ void run_prog(const uint2 *ip, const FV<K> &xv, const FV<K> &yv,
                                          const FV<K> &zv, const float *cache, int64_t cache_stride,
-                                         const int32_t (&cidx)[K], const WarpGeom &wg, float *sl,
+                                         const uint32_t (&coff)[K], const WarpGeom &wg, float *sl,
                                          int lane, FV<K> &res) {
     static_assert(D == 8 || D == kLdsSlots, "compiled stack forms: 8 registers, 16 LDS slots");
     if constexpr (D == kLdsSlots)
-        run_prog_lds<K>(ip, xv, yv, zv, cache, cache_stride, cidx, wg, sl, lane, res);
+        run_prog_lds<K>(ip, xv, yv, zv, cache, cache_stride, coff, wg, sl, lane, res);
     else
-        run_prog_d8<K, EXT>(ip - 1, xv, yv, zv, cache, cache_stride, cidx, wg, res);  // fetches pre-increment
+        run_prog_d8<K, EXT>(ip - 1, xv, yv, zv, cache, cache_stride, coff, wg, res);  // fetches pre-increment
 }
 
 // This wave's LDS stack rows (one wave per workgroup).
@@ -145,13 +165,17 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
                 zv.v[k] = 0.0f;
             }
         }
+        // byte offsets of the lane's cases in every row (cases < 2^30)
+        uint32_t coff[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) coff[k] = (uint32_t)cidx[k] * 4u;
         // the target values are loaded before the program runs, so that
         // their latency overlaps its execution
         FV<K> tv;
         if constexpr (MODE != MODE_STORE) {
-            const float *trow = a.target + (size_t)chan * (size_t)a.target_stride;
+            const Row trow = row_at(a.target, a.target_stride, (uint32_t)chan);
 #pragma unroll
-            for (int k = 0; k < K; ++k) tv.v[k] = trow[cidx[k]];
+            for (int k = 0; k < K; ++k) tv.v[k] = row_load(trow, coff[k]);
         }
         FV<K> res;
         WarpGeom wg{};
@@ -159,12 +183,12 @@ __device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, in
             wg = WarpGeom{a.warp_lo[0], a.warp_lo[1], a.warp_scale[0], a.warp_scale[1], a.shape[0], a.shape[1],
                           (uint32_t)a.stride[0], (uint32_t)a.stride[1], a.ndim};
         }
-        run_prog<K, D, EXT>(code, xv, yv, zv, a.cache, a.cache_stride, cidx, wg, lds_stack<K, D>(), lane, res);
+        run_prog<K, D, EXT>(code, xv, yv, zv, a.cache, a.cache_stride, coff, wg, lds_stack<K, D>(), lane, res);
         if constexpr (MODE == MODE_STORE) {
-            float *row = a.out + (size_t)dest * (size_t)a.out_stride;
+            const Row row = row_at(a.out, a.out_stride, (uint32_t)dest);
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (valid[k]) row[cidx[k]] = res.v[k];
+                if (valid[k]) row_store(row, coff[k], res.v[k]);
         } else {
 #pragma unroll
             for (int k = 0; k < K; ++k) {

@@ -295,7 +295,7 @@ tgp_status tgp_domain_create(tgp_ctx ctx, int32_t ndim, const int64_t *shape, co
     for (int k = 0; k < ndim; ++k) {
         if (shape[k] < 1) return fail(ctx, TGP_ESHAPE, "shape[%d] = %lld < 1", k, (long long)shape[k]);
         cases *= shape[k];
-        if (cases > 0x7fffffffLL) return fail(ctx, TGP_ESHAPE, "more than 2^31-1 cases");
+        if (cases > (1LL << 30)) return fail(ctx, TGP_ESHAPE, "more than 2^30 cases");
     }
     HCHK(ctx, hipSetDevice(ctx->device));
     tgp_domain d = new tgp_domain_s();
