@@ -184,8 +184,8 @@ tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles
 tgp_status tgp_ctx_set_plan(tgp_ctx ctx, int32_t reorder_children, double cache_access_cost);
 
 /* Where the interpreter keeps a program's operand stack: lds = 0 (default)
- * in 8 register slots per case, with a dispatch block per stack depth and
- * four cases per lane; lds != 0 in 16 LDS slots per case (the top of the
+ * in 8 register slots per case, with one dispatch loop over (stack depth,
+ * instruction) and four cases per lane; lds != 0 in 16 LDS slots per case (the top of the
  * stack in registers, one dispatch loop, two cases per lane), which needs
  * fewer subtrees spilled to cache rows for deep programs.  Values never
  * depend on it; the autotuner chooses between the two. */

@@ -85,7 +85,7 @@ struct tgp_batch_s {
     bool use_graph = true;
     bool persistent = true;  // persistent kernels, or one wave per work item
     bool ext = false;        // interpreter with the bitwise operators and warp
-    int D = 8;               // stack slots: 8 registers or the LDS form
+    int D = 0;               // stack slots: the register form's or the LDS form's
     int K = 4;
     int levels_cap = 4;  // fill levels the graph has launches for
     int grid_store = 0, grid_reduce = 0;

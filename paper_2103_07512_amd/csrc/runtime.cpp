@@ -245,7 +245,7 @@ tgp_status tgp_last_timing(tgp_ctx ctx, tgp_timing *out) {
 // automatic) and tiles per work item (0 = automatic).
 tgp_status tgp_ctx_set_tuning(tgp_ctx ctx, int32_t cases_per_lane, int32_t tiles_per_item) {
     if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
-    if (cases_per_lane != 0 && !interp_variant_exists(cases_per_lane, 8))
+    if (cases_per_lane != 0 && !interp_variant_exists(cases_per_lane, interp_max_stack()))
         return fail(ctx, TGP_EINVAL, "no interpreter with %d cases per lane", cases_per_lane);
     if (tiles_per_item < 0) return fail(ctx, TGP_EINVAL, "tiles_per_item < 0");
     ctx->force_K = cases_per_lane;
@@ -611,6 +611,28 @@ struct Planner {
     int op(int64_t n) const { return opv[n]; }
     int arity(int64_t n) const { return arv[n]; }
 
+    // Whether child j of binary node n, evaluated last, is read by the
+    // node's fused form (x, y, a constant or a cached row under an operator
+    // with a fused form): it then never occupies a stack slot.  The emitter
+    // fuses exactly these (cached only grows, so a later decision can only
+    // fuse more).
+    bool fuses_last(int64_t n, int j) const {
+        const int o = opv[n];
+        if (fused_index(o, j == 0 && !is_commutative(o)) < 0) return false;
+        const int32_t c = d.kid[3 * n + j];
+        if (cached[c]) return true;
+        if (opv[c] == TGP_CONST) return true;
+        return opv[c] == TGP_VAR && ((d.op[c] >> 8) & 0xff) <= 1;
+    }
+    // Stack slots a node needs with its children in order o: the i-th
+    // child evaluated sits on i values; a fused last child takes none.
+    int order_need(int64_t n, int a, const uint8_t *o, const int *r) const {
+        if (a == 2 && fuses_last(n, o[1])) return r[o[0]];
+        int v = 0;
+        for (int q = 0; q < a; ++q) v = std::max(v, q + r[o[q]]);
+        return v;
+    }
+
     // The same decisions made level by level (DAG node heights) on T host
     // threads.  Within a level the nodes are independent: each reads only
     // what lower levels decided (bottom-up passes) or higher levels
@@ -729,8 +751,7 @@ struct Planner {
                         const int n_orders = reorder ? (a == 3 ? 6 : 2) : 1;
                         for (int p = 0; p < n_orders; ++p) {
                             const uint8_t *o = a == 2 ? (p ? kPerms[2] : kPerms[0]) : kPerms[p];
-                            int vv = 0;
-                            for (int q = 0; q < a; ++q) vv = std::max(vv, q + r[o[q]]);
+                            const int vv = order_need(n, a, o, r);
                             if (vv < best) {
                                 best = vv;
                                 best_p = a == 2 ? (p ? 2 : 0) : p;
@@ -885,9 +906,10 @@ struct Planner {
                 ++used;
             }
         // Bottom-up: bound the register stack of every program.  Children are
-        // evaluated in decreasing order of the stack they need (Sethi-Ullman);
-        // a node whose children still cannot be evaluated within D slots gets
-        // its most demanding child's subtree spilled to a cache row.
+        // evaluated in decreasing order of the stack they need (Sethi-Ullman,
+        // a fused last operand taking no slot); a node whose children still
+        // cannot be evaluated within D slots gets its most demanding child's
+        // subtree spilled to a cache row.
         std::vector<uint8_t> need(U, 1);
         perm.assign(U, 0);
         auto ref_need = [&](int32_t c) { return cached[c] ? 1 : (int)need[c]; };
@@ -921,8 +943,7 @@ struct Planner {
                 const int n_orders = reorder ? (a == 3 ? 6 : 2) : 1;
                 for (int p = 0; p < n_orders; ++p) {
                     const uint8_t *o = a == 2 ? (p ? kPerms[2] : kPerms[0]) : kPerms[p];
-                    int v = 0;
-                    for (int i = 0; i < a; ++i) v = std::max(v, i + r[o[i]]);
+                    const int v = order_need(n, a, o, r);
                     if (v < best) {
                         best = v;
                         best_p = a == 2 ? (p ? 2 : 0) : p;
