@@ -695,10 +695,9 @@ def main():
         line["roofline"]["traffic_source"] = traffic["source"]
     issue = recorded("k_interp_c3_valu.md", "VALU")
     if issue is not None:
-        # issued VALU instructions of the fitness launch over what the SIMDs
-        # can issue in its time (counters), beside the algorithmic fraction
-        line["roofline"]["issued_valu_frac_fitness_launch"] = issue["issue_frac"]
-        line["roofline"]["issued_valu_source"] = issue["source"]
+        # the fitness launch's issue counters, beside the algorithmic fraction
+        line["roofline"]["counters_fitness_launch"] = {
+            k: issue[k] for k in ("valu_insts", "salu_insts", "branch_insts", "launch_ms", "valubusy_pct", "source")}
     if not args.no_latency:
         loads = [float(x) for x in args.loads.split(",") if x.strip()]
         res = serve_c5(args.latency_generations, loads, False)

@@ -93,12 +93,15 @@ constexpr bool packed_arities_match() {
 static_assert(packed_arities_match(), "every arity fits two bits and unpacks to the table's value");
 
 // --------------------------------------------------------------- cost model
-// The planner's estimate of each operator's cost: VALU instructions per case
-// as this library compiles it for gfx950, measured once with a one-operator
-// kernel over random inputs in [-1, 1] (SQ_INSTS_VALU less its loads, stores
-// and indexing); terminals cost the register move that places them on the
-// stack, warp is estimated (two axis points and a gathered read).  It steers
-// caching and program order only; reported throughput does not use it.
+// The planner's estimate of each operator's cost in VALU instructions per
+// case, first measured with one-operator kernels over random inputs in
+// [-1, 1] (SQ_INSTS_VALU less loads, stores and indexing) on earlier
+// implementations of the operators; pow, mod, exp, log and sqrt have fast
+// paths since and cost less, which only makes the planner cache a little
+// more of them than it would.  Terminals cost the register move that places
+// them on the stack; warp is estimated (two axis points and a gathered
+// read).  It steers caching and program order only; reported throughput
+// does not use it.
 const double kOpCost[TGP_NUM_OPS] = {
     1,  1,              // var const
     1,  1,  1, 13,      // add sub mult div
