@@ -206,6 +206,21 @@ tgp_status tgp_ctx_set_folding(tgp_ctx ctx, int32_t on);
  * either way; the DAG (and the credited node count) can only shrink. */
 tgp_status tgp_ctx_set_hashing(tgp_ctx ctx, int32_t commutative);
 
+/* Identity rewrites while hash-consing later tgp_build_dag calls (on != 0;
+ * default off): the algebraic-equivalence caching of Wong and Zhang (Sec. 2)
+ * and the expression simplification the paper proposes (Sec. 5), kept to
+ * rules that hold bit for bit under this library's readings (NaN payloads
+ * aside) and map a node to one that already exists:
+ *   neg(neg(x)) -> x, abs(abs(x)) -> abs(x), sign(sign(x)) -> sign(x),
+ *   step(step(x)) -> step(x), min(x, x) -> x, max(x, x) -> x,
+ *   if(c, y, y) -> y, sub(x, +0) -> x, add(x, -0) -> x, add(-0, x) -> x,
+ *   mult(x, 1) -> x, mult(1, x) -> x, div(x, 1) -> x
+ * (x, y, c any subtrees; the constants are literal tokens with exactly
+ * these bits).  A rewritten token gets no node of its own: it stands for
+ * the node it maps to, which counts it in its multiplicity.  Per-case values
+ * are the same as without rewrites; the DAG can only shrink. */
+tgp_status tgp_ctx_set_rewrite(tgp_ctx ctx, int32_t on);
+
 /* Test hook: keep only the low `bits` bits of the DAG builder's 64-bit key
  * hash (0 = all bits), forcing collisions so that the full-key comparison is
  * exercised.  Process-wide; the DAG produced must not change. */

@@ -32,12 +32,65 @@ def tree_stack_depth(ops) -> int:
 COMMUTATIVE = (2, 4, 14, 26, 28, 29, 30)
 
 
-def build_dag(tokens, offsets, commutative=False):
+# Opcodes (Table 1 order) the rewrites name.
+_ADD, _SUB, _MULT, _DIV, _MIN, _MAX, _NEG, _SIGN, _ABS, _IF, _STEP = 2, 3, 4, 5, 12, 13, 15, 17, 18, 22, 23
+_POS_ZERO, _NEG_ZERO, _ONE = 0x00000000, 0x80000000, 0x3F800000
+
+
+def rewrite_target(op, kids, node_key):
+    """The node a token of operator op over canonical children kids stands
+    for under the identity rewrites, or None.  Every rule maps to an
+    existing node (a child or a grandchild) and holds bit for bit under the
+    library's readings, NaN payloads aside (a NaN stays a NaN):
+
+      neg(neg(x)) -> x          sign flipped twice
+      abs(abs(x)) -> abs(x)     |x| is already non-negative
+      sign(sign(x)) -> sign(x)  sign of -1, 0 (never -0) and 1
+      step(step(x)) -> step(x)  step of -1 and 1
+      min(x, x) -> x, max(x, x) -> x
+      if(c, y, y) -> y          either branch is y
+      sub(x, +0) -> x           x - (+0) = x, also for x = -0
+      add(x, -0) -> x, add(-0, x) -> x
+      mult(x, 1) -> x, mult(1, x) -> x, div(x, 1) -> x
+
+    sub(x, -0) and add(x, +0) are not rewrites: -0 + (+0) is +0."""
+    def const_bits(k):
+        o, payload, _ = node_key[k]
+        return payload if o == 1 else None
+
+    if op in (_NEG,) and node_key[kids[0]][0] == _NEG:
+        return node_key[kids[0]][2][0]
+    if op in (_ABS, _SIGN, _STEP) and node_key[kids[0]][0] == op:
+        return kids[0]
+    if op in (_MIN, _MAX) and kids[0] == kids[1]:
+        return kids[0]
+    if op == _IF and kids[1] == kids[2]:
+        return kids[1]
+    if op == _SUB and const_bits(kids[1]) == _POS_ZERO:
+        return kids[0]
+    if op == _ADD:
+        if const_bits(kids[1]) == _NEG_ZERO:
+            return kids[0]
+        if const_bits(kids[0]) == _NEG_ZERO:
+            return kids[1]
+    if op == _MULT:
+        if const_bits(kids[1]) == _ONE:
+            return kids[0]
+        if const_bits(kids[0]) == _ONE:
+            return kids[1]
+    if op == _DIV and const_bits(kids[1]) == _ONE:
+        return kids[0]
+    return None
+
+
+def build_dag(tokens, offsets, commutative=False, rewrite=False):
     """Canonicalise a population.
 
     With commutative=True, a node of a COMMUTATIVE operator is identified by
     the unordered pair of its children (its children stay in the order of
-    its first occurrence).
+    its first occurrence).  With rewrite=True, a token that rewrite_target
+    maps to an existing node stands for that node (no node of its own; it
+    counts in that node's multiplicity).
 
     Returns a dict with
       node_op, node_var (uint8), node_value (float32), children (int32 [U][3], -1 = none),
@@ -70,6 +123,12 @@ def build_dag(tokens, offsets, commutative=False):
                 del hstack[len(hstack) - a:]
                 key = (op, 0, tuple(sorted(kids)) if commutative and op in COMMUTATIVE else kids)
                 first_kids = kids
+                target = rewrite_target(op, kids, node_key) if rewrite else None
+                if target is not None:
+                    mult[target] += 1
+                    stack.append(target)
+                    hstack.append(h)
+                    continue
             else:
                 payload = int(var[t]) if op == 0 else int(bits[t])
                 key = (op, payload, ())

@@ -8,12 +8,16 @@
 //      validates arities and opcodes, and records each token's children and
 //      height (a terminal has height 0);
 //   2. hash-consing, level by level in increasing height: a token's key is
-//      (opcode, payload, canonical ids of its children), whose children all
-//      lie on lower, already finished levels.  Keys go into an open-addressing
-//      table (linear probing, capacity >= 2 x tokens); equal keys are
-//      detected by comparing the full key, never the hash alone, and the
-//      representative of a key is its smallest token index (atomicMin), so
-//      the result does not depend on thread timing;
+//      (opcode, payload, classes of its children), whose children all lie on
+//      lower, already finished levels.  Keys go into an open-addressing table
+//      (linear probing, capacity >= 2 x tokens); equal keys are detected by
+//      comparing the full key, never the hash alone.  While the levels run, a
+//      token's class is the table slot of its key (a slot never moves, so the
+//      keys built from classes stay put); the representative of a key is its
+//      smallest token index (atomicMin over every level: with rewrites, one
+//      key can occur at several tree heights), and a last pass replaces each
+//      class by its representative, so the result does not depend on thread
+//      timing;
 //   3. compaction: representatives are numbered by an exclusive scan in token
 //      order, which is the order of first occurrence in a postfix walk of the
 //      trees in population order, so children get smaller ids than parents.
@@ -257,22 +261,63 @@ __device__ __forceinline__ uint64_t key_hash(const Key &k, uint32_t hash_mask_bi
     return h;
 }
 
+// Identity rewrites (tgp_ctx_set_rewrite; the algebraic equivalences of Wong
+// and Zhang's subtree caching, Sec. 2, and the simplification the paper
+// proposes as future work, Sec. 5), restricted to those that hold bit for bit
+// under this library's readings (NaN payloads aside) and whose result is a
+// node that already exists: the representative token that token t stands for,
+// or -1 (as a class, like canon while the levels run).  The rules:
+//   neg(neg(x)) -> x; abs(abs(x)) -> abs(x); sign(sign(x)) -> sign(x);
+//   step(step(x)) -> step(x); min(x, x) -> x; max(x, x) -> x;
+//   if(c, y, y) -> y; sub(x, +0) -> x; add(x, -0), add(-0, x) -> x;
+//   mult(x, 1), mult(1, x) -> x; div(x, 1) -> x.
+// The children are already canonical (lower levels), so a rule sees through
+// earlier rewrites.
+__device__ __forceinline__ int32_t rewrite_target(int32_t t, const uint2 *tok, const int32_t *kid,
+                                                  const int32_t *canon, const int32_t *table) {
+    const uint32_t op = tok[t].x & 0xffu;
+    const int a = arity_of(op);
+    if (a == 0) return -1;
+    // classes (table slots) of the children; any token of a class (its
+    // slot's current value) has the class's opcode, payload and children
+    const int32_t c0 = canon[kid[3 * t]];
+    const int32_t c1 = a > 1 ? canon[kid[3 * t + 1]] : -1;
+    const int32_t c2 = a > 2 ? canon[kid[3 * t + 2]] : -1;
+    auto op_of = [&](int32_t c) { return tok[table[c]].x & 0xffu; };
+    auto is_const = [&](int32_t c, uint32_t bits) { return op_of(c) == TGP_CONST && tok[table[c]].y == bits; };
+    switch (op) {
+    case TGP_NEG: return op_of(c0) == TGP_NEG ? canon[kid[3 * table[c0]]] : -1;
+    case TGP_ABS:
+    case TGP_SIGN:
+    case TGP_STEP: return op_of(c0) == op ? c0 : -1;
+    case TGP_MIN:
+    case TGP_MAX: return c0 == c1 ? c0 : -1;
+    case TGP_IF: return c1 == c2 ? c1 : -1;
+    case TGP_SUB: return is_const(c1, 0x00000000u) ? c0 : -1;
+    case TGP_ADD: return is_const(c1, 0x80000000u) ? c0 : (is_const(c0, 0x80000000u) ? c1 : -1);
+    case TGP_MULT: return is_const(c1, 0x3f800000u) ? c0 : (is_const(c0, 0x3f800000u) ? c1 : -1);
+    case TGP_DIV: return is_const(c1, 0x3f800000u) ? c0 : -1;
+    default: return -1;
+    }
+}
+
 // 2a. Insert the tokens of one level; the slot of a key ends up holding the
-// smallest token index with that key.
+// smallest token index with that key.  A rewritten token is not inserted.
 __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
                               const int32_t *canon, int32_t *table, uint64_t mask,
-                              uint32_t hash_bits, bool commute) {
+                              uint32_t hash_bits, bool commute, bool rewrite) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < n;
     int32_t t = live ? list[i] : -1;
     const Key k = live ? key_of(t, tok, kid, canon, commute) : Key{0xffffffffu, 0, 0, 0};
+    const bool rewritten = live && rewrite && rewrite_target(t, tok, kid, canon, table) >= 0;
     // Leaves (x, y, z and the constants) repeat many times within one wave:
     // lanes holding the same leaf key (its first two words) insert once,
     // through the group's lowest lane, with the group's smallest token index.
     // Every lane of the wave takes part in the ballots and shuffles.
     const uint32_t op = k.k0 & 0xffu;
     const bool leaf = live && (op == TGP_VAR || op == TGP_CONST);
-    bool insert = live && !leaf;
+    bool insert = live && !leaf && !rewritten;
     const int lane = (int)(threadIdx.x & 63u);
     uint64_t todo = __ballot(leaf);
     while (todo) {
@@ -312,10 +357,17 @@ __global__ void k_hash_insert(const int32_t *list, int32_t n, const uint2 *tok, 
 // representative.
 __global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok, const int32_t *kid,
                                int32_t *canon, const int32_t *table, uint64_t mask,
-                               uint32_t hash_bits, bool commute, BuildStatus *st) {
+                               uint32_t hash_bits, bool commute, bool rewrite, BuildStatus *st) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t t = list[i];
+    if (rewrite) {
+        const int32_t target = rewrite_target(t, tok, kid, canon, table);
+        if (target >= 0) {
+            canon[t] = target;
+            return;
+        }
+    }
     const Key k = key_of(t, tok, kid, canon, commute);
     uint64_t s = key_hash(k, hash_bits) & mask;
     for (;;) {
@@ -325,15 +377,22 @@ __global__ void k_hash_resolve(const int32_t *list, int32_t n, const uint2 *tok,
             // sequence, so reaching one means the table is corrupt: the build
             // fails with an error instead of yielding a wrong DAG
             atomicOr(&st->lost_key, 1);
-            canon[t] = t;
+            canon[t] = (int32_t)s;  // an empty slot; the build fails with an error
             return;
         }
         if (key_eq(key_of(e, tok, kid, canon, commute), k)) {
-            canon[t] = e;
+            canon[t] = (int32_t)s;  // the class: the key's slot
             return;
         }
         s = (s + 1) & mask;
     }
+}
+
+// 2c. After the last level: every class becomes its representative, the
+// smallest token index with that key.
+__global__ void k_class_to_token(int32_t *canon, int64_t T, const int32_t *table) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) canon[t] = table[canon[t]];
 }
 
 __global__ void k_flags(const int32_t *canon, int64_t T, int32_t *flag) {
@@ -522,7 +581,7 @@ uint32_t g_debug_hash_bits = 0;  // set by tests to force hash collisions
 
 DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
                                 int64_t T, DagDevice *dev, DevicePool &pool, hipStream_t s,
-                                char *err, size_t errlen, bool commute) {
+                                char *err, size_t errlen, bool commute, bool rewrite) {
     DagBuildResult res{};
     res.status = TGP_OK;
     res.bad_tree = -1;
@@ -604,10 +663,12 @@ DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev
             if (!n) continue;
             const int32_t *lst = list + start[h];
             hipLaunchKernelGGL(k_hash_insert, grid_for(n), dim3(256), 0, s, lst, n, tok, kid, canon,
-                               table, (uint64_t)(cap - 1), g_debug_hash_bits, commute);
+                               table, (uint64_t)(cap - 1), g_debug_hash_bits, commute, rewrite);
             hipLaunchKernelGGL(k_hash_resolve, grid_for(n), dim3(256), 0, s, lst, n, tok, kid,
-                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits, commute, st);
+                               canon, table, (uint64_t)(cap - 1), g_debug_hash_bits, commute, rewrite, st);
         }
+        DCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_class_to_token, grid_for(T), dim3(256), 0, s, canon, T, table);
         DCHK(hipGetLastError());
         DCHK(pool.alloc((void **)&flag, sizeof(int32_t) * T));
         DCHK(pool.alloc((void **)&pos, sizeof(int32_t) * T));

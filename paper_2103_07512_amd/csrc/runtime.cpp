@@ -263,6 +263,12 @@ tgp_status tgp_ctx_set_hashing(tgp_ctx ctx, int32_t commutative) {
     return TGP_OK;
 }
 
+tgp_status tgp_ctx_set_rewrite(tgp_ctx ctx, int32_t on) {
+    if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
+    ctx->rewrite = on != 0;
+    return TGP_OK;
+}
+
 tgp_status tgp_ctx_set_folding(tgp_ctx ctx, int32_t on) {
     if (!ctx) return fail(nullptr, TGP_EINVAL, "ctx is NULL");
     ctx->fold = on != 0;
@@ -401,7 +407,7 @@ tgp_status tgp_build_dag(tgp_ctx ctx, const tgp_population *pop, tgp_dag *out) {
         char msg[256] = "";
         DagBuildResult br =
             build_dag_device(tok_dev, off_dev, R, T, &d->dev, ctx->pool, ctx->stream, msg, sizeof msg,
-                             ctx->commute != 0);
+                             ctx->commute != 0, ctx->rewrite != 0);
         ctx->pool.release(off_own);  // build_dag_device has synchronised the stream
         if (br.status != TGP_OK) {
             delete d;

@@ -35,6 +35,7 @@ struct tgp_ctx_s {
     int stack_lds = 0;                   // operand stack in LDS (1) or registers (0)
     int fold = 1;                        // constant folding
     int commute = 0;                     // hash-consing up to operand order of commuting operators
+    int rewrite = 0;                     // identity rewrites while hash-consing
     double cache_access_cost = 20.0;     // < 0: no benefit-driven caching
     DevBuf partial, cache;
     DevBuf fit_out;  // device copy of fitness values bound for host memory

@@ -359,10 +359,11 @@ struct DagBuildResult {
 // arrays from the pool (returned with dag_device_free once the stream has
 // passed every use).
 // commute: identify nodes of operators whose operands commute by the
-// unordered pair of their children.
+// unordered pair of their children; rewrite: apply the identity rewrites
+// (tgp_ctx_set_rewrite).
 DagBuildResult build_dag_device(const tgp_token *tok_dev, const int64_t *off_dev, int64_t R,
                                 int64_t T, DagDevice *dev, DevicePool &pool, hipStream_t s,
-                                char *err, size_t errlen, bool commute);
+                                char *err, size_t errlen, bool commute, bool rewrite);
 void dag_device_free(DagDevice *dev, DevicePool &pool);
 
 }  // namespace tgp

@@ -161,6 +161,7 @@ SIGNATURES = [
     ("tgp_ctx_set_stack", I32, [P, I32]),
     ("tgp_ctx_set_folding", I32, [P, I32]),
     ("tgp_ctx_set_hashing", I32, [P, I32]),
+    ("tgp_ctx_set_rewrite", I32, [P, I32]),
     ("tgp_debug_set_hash_bits", I32, [I32]),
     ("tgp_domain_create", I32, [P, I32, P, P, P, PP]),
     ("tgp_domain_destroy", None, [P]),
@@ -265,6 +266,10 @@ class Context:
     def set_hashing(self, commutative: bool = False):
         """Hash-cons up to the operand order of commuting operators."""
         _check(lib().tgp_ctx_set_hashing(self.h, 1 if commutative else 0), self.h)
+
+    def set_rewrite(self, on: bool = True):
+        """Apply the identity rewrites while hash-consing (tgp_ctx_set_rewrite)."""
+        _check(lib().tgp_ctx_set_rewrite(self.h, 1 if on else 0), self.h)
 
     def set_folding(self, on: bool = True):
         """Evaluate constant subtrees once and use their values as constants."""

@@ -3,8 +3,10 @@ mistake (a swapped operand, a dropped term, a wrong sign or protection, a
 wrong accuracy constant or margin in the stability classifier) in a copy of
 oracle.c, builds it on the CPU, and runs the pin suites (tests/test_oracle.py
 and tests/test_oracle_stability.py) against it in a fresh process; they must
-fail."""
+fail.  The identity rewrites of the oracle's DAG builder (dag.py) get the same
+treatment against tests/test_oracle_rewrite.py."""
 import os
+import shutil
 import subprocess
 import sys
 
@@ -26,8 +28,8 @@ MUTANTS = [
     ("pow(0, 0) = 1", "return (a == 0.0 && b == 0.0) ? 0.0 : pow(a, b);",
      "return (a == 0.0 && b == 0.0) ? 1.0 : pow(a, b);"),
     ("mod truncated", "if (r != 0.0 && ((r < 0.0) != (y < 0.0)))", "if (0)"),
-    ("clip bounds swapped", "case OV_CLIP: return fmax(fmin(a, c), b);",
-     "case OV_CLIP: return fmax(fmin(a, b), c);"),
+    ("clip bounds swapped", "case OV_CLIP: return max_num(min_num(a, c), b);",
+     "case OV_CLIP: return max_num(min_num(a, b), c);"),
     ("mdist not halved", "case OV_MDIST: return (a + b) / 2.0;", "case OV_MDIST: return (a + b);"),
     ("sstepp term dropped", "return a * a * a * (a * (6.0 * a - 15.0) + 10.0);",
      "return a * a * a * (a * (6.0 * a - 15.0));"),
@@ -84,4 +86,45 @@ def test_pins_catch_planted_mistake(tmp_path, name, old, new):
         text = f.read()
     assert text.count(old) == 1, f"mutation site not unique or missing: {old!r}"
     r = _run_pins(tmp_path, text.replace(old, new))
+    assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"
+
+
+DAG = os.path.join(os.path.dirname(HERE), "oracle", "dag.py")
+DAG_MUTANTS = [
+    ("sub(x, -0) rewritten", "if op == _SUB and const_bits(kids[1]) == _POS_ZERO:",
+     "if op == _SUB and const_bits(kids[1]) in (_POS_ZERO, _NEG_ZERO):"),
+    ("add(x, +0) rewritten", "        if const_bits(kids[1]) == _NEG_ZERO:\n            return kids[0]",
+     "        if const_bits(kids[1]) in (_NEG_ZERO, _POS_ZERO):\n            return kids[0]"),
+    ("neg(neg(x)) to the inner neg", "return node_key[kids[0]][2][0]", "return kids[0]"),
+    ("min/max of different operands", "if op in (_MIN, _MAX) and kids[0] == kids[1]:", "if op in (_MIN, _MAX):"),
+    ("if(c, y, y) to the condition", "if op == _IF and kids[1] == kids[2]:\n        return kids[1]",
+     "if op == _IF and kids[1] == kids[2]:\n        return kids[0]"),
+    ("rewritten token not counted", "                    mult[target] += 1\n", ""),
+    ("mult by -1 rewritten", "        if const_bits(kids[1]) == _ONE:\n            return kids[0]\n        if const_bits(kids[0]) == _ONE:",
+     "        if const_bits(kids[1]) in (_ONE, 0xBF800000):\n            return kids[0]\n        if const_bits(kids[0]) == _ONE:"),
+]
+
+
+def _run_rewrite_pins(tmp_path, text):
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.dirname(DAG), pkg, ignore=shutil.ignore_patterns("__pycache__"))
+    (pkg / "dag.py").write_text(text)
+    env = dict(os.environ, PYTHONPATH=os.pathsep.join([str(tmp_path), HERE, os.path.dirname(HERE)]))
+    return subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                           os.path.join(HERE, "test_oracle_rewrite.py")],
+                          env=env, capture_output=True, text=True, timeout=600, cwd=str(tmp_path))
+
+
+def test_rewrite_control_passes(tmp_path):
+    with open(DAG) as f:
+        r = _run_rewrite_pins(tmp_path, f.read())
+    assert r.returncode == 0, r.stdout[-3000:]
+
+
+@pytest.mark.parametrize("name,old,new", DAG_MUTANTS, ids=[m[0] for m in DAG_MUTANTS])
+def test_rewrite_pins_catch_planted_mistake(tmp_path, name, old, new):
+    with open(DAG) as f:
+        text = f.read()
+    assert text.count(old) == 1, f"mutation site not unique or missing: {old!r}"
+    r = _run_rewrite_pins(tmp_path, text.replace(old, new))
     assert r.returncode != 0, f"planted mistake '{name}' passed every pin:\n{r.stdout[-2000:]}"
