@@ -124,8 +124,8 @@ __device__ __forceinline__ float *lds_stack() {
 }
 
 // One work item: program `code` over tiles_per_stripe tiles of one stripe.
-template <int K, int D, int MODE, bool EXT>
-__device__ __forceinline__ void run_item(const JobDesc &a, const uint2 *code, int32_t dest, int32_t chan,
+template <int K, int D, int MODE, bool EXT, typename Job>
+__device__ __forceinline__ void run_item(const Job &a, const uint2 *code, int32_t dest, int32_t chan,
                                          uint32_t stripe, int lane) {
     const int32_t n = a.n_cases;
     const int64_t tile_cases = 64 * K;
@@ -251,6 +251,11 @@ __device__ __forceinline__ T load_const(const T *p) {
     return r;
 }
 
+// A job descriptor read in place through the constant address space: each
+// field is a scalar load the compiler may repeat where it is used, so the
+// descriptor does not occupy scalar registers for a whole work item.
+typedef const __attribute__((address_space(4))) JobDesc CJobDesc;
+
 __device__ __forceinline__ uint32_t load_const_u32(const uint32_t *p) {
     typedef const __attribute__((address_space(4))) uint32_t cword;
     return *(cword *)(p);
@@ -271,7 +276,7 @@ __device__ __forceinline__ uint32_t find_pair(const uint32_t *__restrict__ item_
 }
 
 template <int K, int D, int MODE, bool EXT>
-__global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(64, min_waves<MODE>()) void k_batch(const JobDesc *__restrict__ jobs,
                                               const PairDesc *__restrict__ pairs,
                                               const uint32_t *__restrict__ item_first,
                                               const GroupDesc *__restrict__ groups, int32_t g,
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
                 const uint32_t item = gd.item_begin + part + kParts * k;
                 lo = find_pair(item_first, lo, gd.pair_end, item);
                 const PairDesc pd = load_const(pairs + lo);
-                const JobDesc jd = load_const(jobs + pd.job);
+                const CJobDesc &jd = *(CJobDesc *)(jobs + pd.job);
                 const uint32_t stripe = item - load_const_u32(item_first + lo);
                 run_item<K, D, MODE, EXT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, stripe, threadIdx.x);
             }
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(64) void k_batch(const JobDesc *__restrict__ jobs,
 // Direct form: one wave per item (grid = the group's item count, or more);
 // the hardware dispatcher hands out the waves in item order.
 template <int K, int D, int MODE, bool EXT>
-__global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(64, min_waves<MODE>()) void k_batch_direct(const JobDesc *__restrict__ jobs,
                                                      const PairDesc *__restrict__ pairs,
                                                      const uint32_t *__restrict__ item_first,
                                                      const GroupDesc *__restrict__ groups, int32_t g) {
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(64) void k_batch_direct(const JobDesc *__restrict__
     if (item >= gd.item_end) return;
     const uint32_t lo = find_pair(item_first, gd.pair_begin, gd.pair_end, item);
     const PairDesc pd = load_const(pairs + lo);
-    const JobDesc jd = load_const(jobs + pd.job);
+    const CJobDesc &jd = *(CJobDesc *)(jobs + pd.job);
     run_item<K, D, MODE, EXT>(jd, jd.code + pd.code_off, pd.dest, pd.chan, item - load_const_u32(item_first + lo),
                          threadIdx.x);
 }
