@@ -206,17 +206,27 @@ def body_for_depth(D):
     e = L.append
     e(f"// Stack of {D} register slots, one dispatch loop over (depth, opcode).")
     e("template <int K, bool EXT>")
-    e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv,")
-    e("        const FV<K> &yv, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
+    e(f"__device__ __forceinline__ void run_prog_d{D}(const uint2 *__restrict__ ip, const FV<K> &xv0,")
+    e("        const FV<K> &yv0, const FV<K> &zv, const float *__restrict__ cache, int64_t cache_stride,")
     e("        const uint32_t (&coff)[K], const WarpGeom &wg, FV<K> &res)")
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
+    e("    FV<K> xv = xv0, yv = yv0;")
     e("    uint2 ins;")
     e("    // one scalar load of the next whole word, issued a dispatch ahead")
     e("    uint64_t nxt;")
     e("    __builtin_memcpy(&nxt, ++ip, 8);")
     e("    for (;;) {")
     e("    ins = make_uint2((uint32_t)nxt, (uint32_t)(nxt >> 32));")
+    # The coordinates pass through an empty asm at every dispatch, so the
+    # compiler sees them redefined in the loop and does not hoist the cases'
+    # expressions of them (x / 2 for mdist, x == 0 for div, ...) out of it
+    # into registers that then spill: fewer VGPRs, no per-tile spill stores.
+    e("#pragma unroll")
+    e("    for (int k = 0; k < K; ++k) {")
+    e("        asm volatile(\"\" : \"+v\"(xv.v[k]));")
+    e("        asm volatile(\"\" : \"+v\"(yv.v[k]));")
+    e("    }")
     e("    if (ins.x == ((1u << 8) | I_END)) break;")
     e("    __builtin_amdgcn_sched_barrier(0);")
     e("    __builtin_memcpy(&nxt, ++ip, 8);")
