@@ -200,9 +200,10 @@ tgp_status tgp_ctx_set_folding(tgp_ctx ctx, int32_t on);
 /* Hash-consing identity of later tgp_build_dag calls: structural (0, the
  * default: op, payload and children in order, Handley's DAG of Sec. 2), or
  * also up to the operand order of the operators whose operands commute
- * bitwise in this library (1: add, mult, mdist, len, or, xor, and; not min
- * and max, whose result for +0 / -0 may follow the operand order).  A node
- * keeps the child order of its first occurrence.  Values are the same
+ * bitwise in this library, NaN payloads aside (1: add, mult, min, max,
+ * mdist, len, or, xor, and; min and max order -0 below +0 and give the
+ * other operand for a NaN).  A node keeps the child order of its first
+ * occurrence.  Values are the same
  * either way; the DAG (and the credited node count) can only shrink. */
 tgp_status tgp_ctx_set_hashing(tgp_ctx ctx, int32_t commutative);
 

@@ -217,8 +217,8 @@ struct Key {
 // Operators whose operands commute bitwise in this library (see
 // tgp_ctx_set_hashing).
 __device__ __forceinline__ bool commutes(uint32_t op) {
-    return op == TGP_ADD || op == TGP_MULT || op == TGP_MDIST || op == TGP_LEN || op == TGP_OR ||
-           op == TGP_XOR || op == TGP_AND;
+    return op == TGP_ADD || op == TGP_MULT || op == TGP_MIN || op == TGP_MAX || op == TGP_MDIST ||
+           op == TGP_LEN || op == TGP_OR || op == TGP_XOR || op == TGP_AND;
 }
 
 __device__ __forceinline__ Key key_of(int32_t t, const uint2 *tok, const int32_t *kid,

@@ -512,17 +512,17 @@ def test_dag_invariants():
 
 
 def test_dag_commutative_identity():
-    """Hash-consing up to the operand order of commuting operators: add and
-    mult pairs merge, sub and min pairs do not; a merged node keeps the child
-    order of its first occurrence."""
+    """Hash-consing up to the operand order of commuting operators: add, mult
+    and min pairs merge, sub and pow pairs do not; a merged node keeps the
+    child order of its first occurrence."""
     texts = ["add(x, y)", "add(y, x)", "sub(x, y)", "sub(y, x)", "min(x, y)", "min(y, x)",
-             "mult(add(x, y), 2.0)", "mult(2.0, add(y, x))"]
+             "mult(add(x, y), 2.0)", "mult(2.0, add(y, x))", "pow(x, y)", "pow(y, x)"]
     pop = pg.population_from_texts(texts)
     s = oracle.build_dag(pop.tokens, pop.offsets)
     c = oracle.build_dag(pop.tokens, pop.offsets, commutative=True)
-    assert s["dag_nodes"] == 3 + 8 and c["dag_nodes"] == 3 + 1 + 2 + 2 + 1
+    assert s["dag_nodes"] == 3 + 10 and c["dag_nodes"] == 3 + 1 + 2 + 1 + 1 + 2
     r = c["roots"].tolist()
-    assert r[0] == r[1] and r[2] != r[3] and r[4] != r[5] and r[6] == r[7]
+    assert r[0] == r[1] and r[2] != r[3] and r[4] == r[5] and r[6] == r[7] and r[8] != r[9]
     assert c["children"][r[0]][:2].tolist() == [0, 1]          # add(x, y) as first met
     assert c["children"][r[6]][:2].tolist() == [r[0], c["children"][r[6]][1]]
     assert c["node_value"][c["children"][r[6]][1]] == 2.0
@@ -532,6 +532,28 @@ def test_dag_commutative_identity():
     b = oracle.build_dag(pop2.tokens, pop2.offsets, commutative=True)
     assert b["dag_nodes"] <= a["dag_nodes"] and b["tree_nodes"] == a["tree_nodes"]
     assert b["multiplicity"].sum() == len(pop2.tokens)
+
+
+def test_commutative_set_is_exactly_the_bitwise_commuting_operators():
+    """Every operator in the hashing identity's set gives the same bits (NaN
+    positions aside) for both operand orders over operands that take signed
+    zeros, infinities, NaN, subnormals and large values; every other binary
+    operator differs in some case, so it cannot be in the set."""
+    from oracle.dag import COMMUTATIVE
+    subs = ["x", "y", "mult(x, 0.0)", "mult(y, 0.0)", "pow(x, 0.5)", "exp(mult(y, 1000.0))",
+            "neg(exp(mult(x, 1000.0)))", "mult(x, 1e-40)", "mult(y, 3e38)", "add(x, 0.25)"]
+    binary = [o for o in range(len(pg.OP_NAME)) if pg.ARITY[o] == 2 and pg.OP_NAME[o] != "warp"]
+    for o in binary:
+        name = pg.OP_NAME[o]
+        texts = [f"{name}({a}, {b})" for a in subs for b in subs] + [f"{name}({b}, {a})" for a in subs
+                                                                     for b in subs]
+        pop = pg.population_from_texts(texts)
+        v = oracle.evaluate(pop.tokens, pop.offsets, (9, 7))
+        n = len(texts) // 2
+        a, b = v[:n], v[n:]
+        same = np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(
+            a[~np.isnan(a)].view(np.uint64), b[~np.isnan(b)].view(np.uint64))
+        assert same == (o in COMMUTATIVE), name
 
 
 def test_c2_sharing_in_range():
