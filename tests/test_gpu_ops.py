@@ -142,6 +142,39 @@ def test_pow_special_values(env):
                 assert abs(v - w) <= 3.0 * float(_ulp32(np.array([w]))[0]), (a, b, v, w)
 
 
+def test_mod_special_values(env):
+    """Every pair of special operands through mod: the floored remainder
+    rounded once (the divisor's sign, a zero result signed like the
+    dividend), 0 for a zero divisor of either sign, NaN for a NaN operand or
+    an infinite dividend, and over an infinite divisor the dividend, or the
+    divisor when the signs differ and the dividend is not zero."""
+    pairs = [(a, b) for a in SPECIALS for b in SPECIALS]
+    texts = [f"mod(if(x, {a}, y), if(x, {b}, y))" for a, b in pairs]
+    tgp, ctx, torch = env
+    pop = pg.population_from_texts(texts)
+    d = tgp.Domain(ctx, (4, 4))
+    dag = tgp.build_dag(ctx, pop)
+    out = torch.empty(pop.n_roots, d.cases, dtype=torch.float32, device="cuda:0")
+    tgp.evaluate(ctx, dag, d, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for (a, b), g in zip(pairs, got):
+        a32, b32 = np.float32(float(a)), np.float32(float(b))
+        if b32 == 0:
+            w = np.float32(0.0)
+        elif np.isnan(a32) or np.isnan(b32) or np.isinf(a32):
+            w = np.float32(np.nan)
+        elif np.isinf(b32):
+            w = b32 if (a32 != 0 and (a32 < 0) != (b32 < 0)) else a32
+        else:
+            w = _floor_mod_exact(np.array([a32]), np.array([b32]))[0]
+        for v in g:
+            if np.isnan(w):
+                assert np.isnan(v), (a, b, v, w)
+            else:
+                assert np.float32(v).view(np.uint32) == np.float32(w).view(np.uint32), (a, b, v, w)
+
+
 def _floor_mod_exact(a32, b32):
     """The floored remainder of FP32 operands rounded once to FP32 (b != 0,
     both finite): fmod is exact in FP64; adding b is done exactly with
