@@ -212,10 +212,23 @@ def body_for_depth(D):
     e("{")
     e("    " + " ".join(f"FV<K> s{j};" for j in range(D)))
     e("    FV<K> xv = xv0, yv = yv0;")
+    # One opaque pass before the loop as well: it waits for the coordinate
+    # loads there, so the passes inside the loop find no load pending on
+    # those registers and the loop head carries no wait for them.
+    e("#pragma unroll")
+    e("    for (int k = 0; k < K; ++k) {")
+    e("        asm volatile(\"\" : \"+v\"(xv.v[k]));")
+    e("        asm volatile(\"\" : \"+v\"(yv.v[k]));")
+    e("    }")
     e("    uint2 ins;")
-    e("    // one scalar load of the next whole word, issued a dispatch ahead")
-    e("    uint64_t nxt;")
-    e("    __builtin_memcpy(&nxt, ++ip, 8);")
+    e("    // one scalar load of the next whole word, issued a dispatch ahead,")
+    e("    // through the constant address space at a 32-bit byte offset (one")
+    e("    // scalar add per instruction)")
+    e("    typedef const __attribute__((address_space(4))) char cchar;")
+    e("    typedef const __attribute__((address_space(4))) uint64_t cword;")
+    e("    cchar *const cb = (cchar *)ip;")
+    e("    uint32_t off = 8;")
+    e("    uint64_t nxt = *(cword *)(cb + off);")
     e("    for (;;) {")
     e("    ins = make_uint2((uint32_t)nxt, (uint32_t)(nxt >> 32));")
     # The coordinates pass through an empty asm at every dispatch, so the
@@ -229,7 +242,8 @@ def body_for_depth(D):
     e("    }")
     e("    if (ins.x == ((1u << 8) | I_END)) break;")
     e("    __builtin_amdgcn_sched_barrier(0);")
-    e("    __builtin_memcpy(&nxt, ++ip, 8);")
+    e("    off += 8;")
+    e("    nxt = *(cword *)(cb + off);")
     bodies = {}
 
     def case(key, lines):
