@@ -79,7 +79,8 @@ WORKLOADS = {
     "c1": "50 ramped half-and-half trees depth 2-6, 6 operators, 64x64 grid, RMSE vs a seeded "
           "depth-4 tree",
     "c4": "64 populations (sizes log-uniform 20-2000, depths 4-14, 18 operators), domains 2-D "
-          "32^2-1024^2 or 3-D 64^3, RMSE; one batched persistent step vs 64 plain launches",
+          "32^2-1024^2 or 3-D 64^3, RMSE; one batched step (stack form, cases per lane and launch "
+          "form autotuned) vs 64 plain launches",
     "evolve": "a GP run on the headline workload kept on the GPU: each generation hash-conses and "
               "evaluates the population (1000 x 3 trees, 1024x1024, MSE) and breeds the next one "
               "on the device (tournament 3, crossover 0.8, mutation 0.1, depth <= 12, 18 operators)",
