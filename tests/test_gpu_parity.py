@@ -571,6 +571,50 @@ def _c3_check_rows(out, pop, shape, rows, say_every=4):
     return tot
 
 
+def test_c3_every_individual_64x1024(env):
+    """Every one of C3's 1000 individuals (3 channel trees each, MSE) on a
+    64 x 1024 grid of its own: per-case values of all 3000 trees and each
+    individual's MSE against the oracle's, by the parity contract (strict,
+    envelope, +inf or hybrid; none skipped).  The plan still has several
+    cache levels and every program spans several stripes."""
+    tgp, ctx, torch = env
+    pop, _, tgt = pg.workload_c3()
+    shape = (64, 1024)
+    d = tgp.Domain(ctx, shape)
+    dag = tgp.build_dag(ctx, pop)
+    target = finite_target(tgt, shape)
+    t_dev = torch.from_numpy(target).to("cuda:0")
+    f_dev = torch.empty(pop.n_individuals, dtype=torch.float64, device="cuda:0")
+    tgp.fitness(ctx, dag, d, t_dev, tgp.MSE, f_dev)
+    torch.cuda.synchronize()
+    w = ctx.last_work()
+    say("C3 64x1024: cache levels", w["cache_levels"], "cached", w["cached_nodes"], "programs", w["programs"])
+    assert w["cache_levels"] >= 2
+    out = torch.empty(pop.n_roots, d.cases, dtype=torch.float32, device="cuda:0")
+    tgp.evaluate(ctx, dag, d, out)
+    torch.cuda.synchronize()
+    f = f_dev.cpu().numpy()
+    cases = fits = None
+    for i0 in range(0, pop.n_individuals, 100):
+        sel = np.arange(i0, min(i0 + 100, pop.n_individuals))
+        roots = np.array([3 * i + c for i in sel for c in range(3)])
+        sub = pg.Population.from_trees([pop.tree(int(r)) for r in roots], n_channels=3)
+        v64, v32, st, eb = oracle.evaluate(sub.tokens, sub.offsets, shape, bound=True)
+        g = out[torch.from_numpy(roots).to("cuda:0")].cpu().numpy()
+        rc = _parity.check_cases(g, v64, v32, st, eb, f"C3 64x1024 individuals {i0}..")
+        rf = _parity.check_fitness(f[sel], g, v64, st, eb, target, len(sel), 3, "mse",
+                                   f"C3 64x1024 individuals {i0}..")
+        cases = rc if cases is None else {k: max(cases[k], rc[k]) if k.startswith("max_") else cases[k] + rc[k]
+                                          for k in cases}
+        fits = rf if fits is None else {k: fits[k] + rf[k] for k in fits}
+    say("C3 64x1024 cases", cases, "individuals", fits)
+    assert sum(fits.values()) == pop.n_individuals
+    assert (cases["stable"] + cases["envelope"] + cases["nonfinite"]) >= 0.9 * cases["cases"]
+    assert fits["partial"] <= pop.n_individuals // 2
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_c3_full_size(env):
     """The headline workload (1000 individuals x 3 channel trees, 1024x1024,
     MSE) at full size, in the launch configuration the benchmark times:
