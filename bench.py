@@ -84,6 +84,9 @@ WORKLOADS = {
     "evolve": "a GP run on the headline workload kept on the GPU: each generation hash-conses and "
               "evaluates the population (1000 x 3 trees, 1024x1024, MSE) and breeds the next one "
               "on the device (tournament 3, crossover 0.8, mutation 0.1, depth <= 12, 18 operators)",
+    "p": "the paper's tree-evaluation experiment shape: 5 populations of 50 individuals, ramped "
+         "half-and-half depths 2-12, 18 operators, RMSE against the Pagie polynomial on 2-D grids "
+         "of 64^2 to 2048^2 cases in [-1, 1]^2",
     "c5": "16 concurrent GP runs (grids 512^2-4096^2, populations log-uniform 200-2000, bred "
           "closed-loop from returned fitness, depth <= 12, 18 operators), RMSE; served with "
           "continuous batching and a resident subtree cache",
@@ -221,6 +224,90 @@ def run_c4(args):
                    "autotune": tune, "batch": st, "max_rel_diff_batched_vs_plain": agree},
     }
     return line
+
+
+# Pagie polynomial (Eq. 1), 1/(1 + x^-4) + 1/(1 + y^-4) = x^4/(1 + x^4) + y^4/(1 + y^4),
+# as an expression the library itself renders on the device
+PAGIE = ("add(div(mult(mult(x, x), mult(x, x)), add(1.0, mult(mult(x, x), mult(x, x)))), "
+         "div(mult(mult(y, y), mult(y, y)), add(1.0, mult(mult(y, y), mult(y, y)))))")
+
+
+def bench_p(args):
+    """The paper's tree-evaluation experiment shape (Table 2): the same 5
+    populations of 50 individuals on each grid from 64^2 to 2048^2, RMSE
+    against the Pagie polynomial.  A step evaluates the 5 populations on one
+    grid (DAG build from device-resident tokens, plan, fill, fused fitness);
+    per grid it reports the mean and spread of one population's evaluation
+    and the credited node-evals/s.  The paper's seconds (other hardware,
+    other systems) are context only."""
+    import numpy as np
+    import torch
+
+    from paper_2103_07512_amd import popgen as pg
+    from paper_2103_07512_amd import tgp
+
+    dev = torch.device("cuda:0")
+    ctx = tgp.Context(0)
+    pops = [pg.ramped_half_and_half(50, 2, 12, 20 + r, pg.F18, 2) for r in range(5)]
+    dev_tok = [(torch.from_numpy(p.tokens.view(np.uint8).copy()).to(dev), torch.from_numpy(p.offsets.copy()).to(dev))
+               for p in pops]
+    target_pop = pg.population_from_texts([PAGIE])
+    out = torch.empty(50, dtype=torch.float64, device=dev)
+    rows, tot_credited, tot_s = [], 0, 0.0
+    for side in (64, 128, 256, 512, 1024, 2048):
+        dom = tgp.Domain(ctx, (side, side))
+        tdag = tgp.build_dag(ctx, target_pop)
+        target = torch.empty(1, dom.cases, dtype=torch.float32, device=dev)
+        tgp.evaluate(ctx, tdag, dom, target)
+        tdag.close()
+
+        def one(r):
+            dag = tgp.Dag(ctx, dev_tok[r][0], dev_tok[r][1], 50, 1)
+            tgp.fitness(ctx, dag, dom, target, tgp.RMSE, out)
+            return dag
+
+        for _ in range(args.warmup):
+            for r in range(5):
+                one(r).close()
+        torch.cuda.synchronize()
+        times, credited = [], 0
+        for _ in range(args.steps):
+            for r in range(5):
+                t0 = time.perf_counter()
+                dag = one(r)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                credited += dag.stats()["dag_nodes"] * dom.cases
+                dag.close()
+        s_sum = float(np.sum(times))
+        rows.append({"side": side, "cases": dom.cases, "ms_per_population_mean": 1e3 * float(np.mean(times)),
+                     "ms_per_population_std": 1e3 * float(np.std(times)),
+                     "ms_per_5_populations": 5e3 * float(np.mean(times)),
+                     "node_evals_per_s": credited / s_sum})
+        tot_credited += credited
+        tot_s += s_sum
+        print(f"[p] {side}^2: {rows[-1]['ms_per_population_mean']:.3f} ms per population", file=sys.stderr,
+              flush=True)
+    line = {
+        "metric": "node-evals/s (DAG nodes x fitness cases / s) over the six grids",
+        "value": tot_credited / tot_s,
+        "unit": "node-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * tot_s / (args.steps * 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["p"], "populations": 5, "individuals": 50,
+                   "tree_nodes": [int(len(p.tokens)) for p in pops]},
+        "roofline": None,
+        "cpu_baseline": None,
+        "detail": {"by_grid": rows},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_evolve(args):
@@ -564,6 +651,8 @@ def main():
         return bench_c5(args)
     if args.workload == "evolve":
         return bench_evolve(args)
+    if args.workload == "p":
+        return bench_p(args)
 
     import numpy as np
     import torch
