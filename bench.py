@@ -506,12 +506,24 @@ def serve_c5(generations, loads, with_plain, warm_generations=2, log=None, confi
                 pop = pg.breed(pop, rng, pg.F18, 2, max_depth=spec.max_depth, fitness=f)
 
     def run_threads(target_fn):
-        th = [threading.Thread(target=target_fn, args=(spec,)) for spec in runs]
+        # a request that fails ends its run's thread: report it instead of
+        # timing the runs that are left
+        errors = []
+
+        def guarded(spec):
+            try:
+                target_fn(spec)
+            except Exception as e:  # noqa: BLE001
+                errors.append(f"run {spec.run}: {e}")
+
+        th = [threading.Thread(target=guarded, args=(spec,)) for spec in runs]
         t0 = time.perf_counter()
         for x in th:
             x.start()
         for x in th:
             x.join()
+        if errors:
+            raise RuntimeError(f"{len(errors)} serving run(s) failed; first: {errors[0]}")
         return time.perf_counter() - t0
 
     say("c5: closed loop with breeding")
