@@ -594,9 +594,13 @@ tgp_status tgp_server_create(tgp_ctx ctx, size_t cache_budget_bytes, int32_t max
         c->tile_cap = ctx->tile_cap;
         c->batch_persistent = ctx->batch_persistent;
     }
+    // A request may plan new cache rows for at most half the arena, so that
+    // it can be admitted beside the resident rows it reads (pinned while it
+    // runs) even when the arena is fragmented; beyond that its plan
+    // recomputes subtrees instead of caching them.
     for (tgp_ctx c : s->prep) {
         c->plan_upload = false;
-        c->cache_budget = budget;
+        c->cache_budget = budget / 2;
     }
     // One case split for every step, whatever the requests in it: four cases
     // per lane (the split, and so the summation order, of a request must not
