@@ -795,6 +795,19 @@ def main():
     if traffic is not None:
         line["roofline"]["traffic"] = traffic["bytes_per_launch"]
         line["roofline"]["traffic_source"] = traffic["source"]
+    # the cache path: the fill launches' algorithmic bytes (the rows they
+    # write) over their HIP-event time, against the 8 TB/s HBM peak; the
+    # counters' byte count (reads of lower rows included) beside it
+    cp = {"kernel": "k_interp cache-fill launches of a step (one per cache level)",
+          "algorithmic_write_bytes": work["cache_bytes_written"], "ms": fill_ms,
+          "achieved_GB_per_s": work["cache_bytes_written"] / (fill_ms / 1e3) / 1e9 if fill_ms > 0 else None,
+          "peak_GB_per_s": 8000.0}
+    cp["frac"] = cp["achieved_GB_per_s"] / cp["peak_GB_per_s"] if cp["achieved_GB_per_s"] else None
+    if traffic is not None and fill_ms > 0:
+        cp["measured_bytes"] = traffic["fill_fetch_bytes"] + traffic["fill_write_bytes"]
+        cp["measured_GB_per_s"] = cp["measured_bytes"] / (fill_ms / 1e3) / 1e9
+        cp["source"] = traffic["source"]
+    line["cache_path"] = cp
     issue = recorded("k_interp_c3_valu.md", "VALU")
     if issue is not None:
         # the fitness launch's issue counters, beside the algorithmic fraction
